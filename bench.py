@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the fused fluctuating two-species D2Q9 step.
+
+One "step" advances every replica of the workload by one lattice-Boltzmann
+time step (collision with forcing and noise, streaming, walls) with the
+structure-factor and pressure sampling fused in at its configured cadence.
+
+Default workload (N = 1): the batched ensemble of 96 replicas with L in
+{32, 64, 128, 256}, Lx = 2L, FP32-deviation storage, sampled every 10 steps.
+Printed as one JSON line:
+  value        MLUPS over the whole batch (one update = both species at one node)
+  roofline     the step kernel alone (sampling off), HBM-bound: algorithmic
+               bytes (18 reads + 18 writes per node) / measured launch time
+  compare      plain FP64 storage on the single 512 x 256 lattice, same timing
+  cpu_baseline the FP64 CPU oracle on a bounded sample of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published peak
+
+
+def _events_time(lat, nsteps):
+    """Elapsed ms of nsteps steps between two HIP events on the library's stream."""
+    import torch
+    s = lat.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    lat.step(nsteps)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def _traffic_from_profiles():
+    """HBM bytes per step launch from the committed counter summary, if it was
+    taken on the current kernel build (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_step_batched96_fp32dev.json")
+    lib = os.path.join(ROOT, "paper_1808_05168_amd", "libfnlb.so")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        import hashlib
+        src = b"".join(open(os.path.join(ROOT, "paper_1808_05168_amd", "csrc", n), "rb").read()
+                       for n in ("k_step.hip", "fnlb_device.hpp", "fnlb_internal.hpp"))
+        if d.get("source_sha256") != hashlib.sha256(src).hexdigest():
+            return None
+        return d["bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(reps, budget_s: float):
+    """The oracle as it stands, on one replica of each lattice size, for as many
+    steps as fit the budget (at least 20)."""
+    from oracle import oracle as O
+    threads = min(os.cpu_count() or 1, 16)
+    O.set_threads(threads)
+    seen, sample = set(), []
+    for r in reps:
+        if (r.Lx, r.Lz) not in seen:
+            seen.add((r.Lx, r.Lz))
+            sample.append(r)
+    # calibrate with a few steps, then run the budget
+    f = [O.init_state(r) for r in sample]
+    t = time.perf_counter()
+    for r, fr in zip(sample, f):
+        O.run(r, fr, 0, 5)
+    cal = (time.perf_counter() - t) / 5
+    steps = max(20, int(budget_s / max(cal, 1e-9)))
+    t = time.perf_counter()
+    for r, fr in zip(sample, f):
+        O.run(r, fr, 5, steps)
+    dt = time.perf_counter() - t
+    nodes = sum(r.Lx * r.Lz for r in sample)
+    return {"value": round(nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{len(sample)} replicas (one per size: "
+                      + ", ".join(f"{r.Lx}x{r.Lz}" for r in sample)
+                      + f"), {steps} steps each, FP64, no sampling, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="batched96",
+                    choices=["batched96", "large4096x1024", "single512x256"])
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run a plain device copy of this size (3 times), the "
+                         "reference for scaling HBM byte counters")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(replicas and z-slabs would shard across GPUs, see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1808_05168_amd as F
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    if args.copy_calibration_mb > 0:
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    every = 10
+    if args.workload == "batched96":
+        reps, prec = W.batched_ensemble(96), F.FP32_DEV
+        desc = "96 replicas, L = 32*2^(i%4), Lx = 2L, G in {0, 0.5}, grad_c0 in [0, 1e-3]"
+    elif args.workload == "large4096x1024":
+        reps, prec, every = [W.large_4096x1024()], F.FP32_DEV, 50
+        desc = "single 4096 x 1024 lattice, G = 0.5, grad_c0 = 5e-4"
+    else:
+        reps, prec = [W.single_512x256()], F.FP64
+        desc = "single 512 x 256 lattice, G = 0.5, grad_c0 = 1e-3"
+    nodes = sum(r.Lx * r.Lz for r in reps)
+    store_bytes = 4 if prec == F.FP32_DEV else 8
+    bytes_per_node = 36 * store_bytes
+
+    lat = F.Lattice(reps, precision=prec, sample_every=every)
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = _events_time(lat, args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sec = ms / 1e3
+    mlups = nodes * args.steps / sec / 1e6
+
+    # roofline leg: the step kernel alone (no sampling), same batch
+    lat_r = F.Lattice(reps, precision=prec, sample_every=0)
+    lat_r.step(min(args.warmup, 100))
+    nr = max(50, min(args.steps, 1000))
+    ms_r = _events_time(lat_r, nr)
+    t_launch = ms_r / 1e3 / nr
+    achieved = bytes_per_node * nodes / t_launch / 1e9
+    del lat_r
+    traffic = _traffic_from_profiles()
+
+    out = {
+        "metric": "MLUPS (both species)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == F.FP32_DEV else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "nodes": nodes,
+                   "storage": "fp32-deviation" if prec == F.FP32_DEV else "fp64",
+                   "sample_every": every, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_step (fused collide-stream)",
+                     "launch_ms": round(t_launch * 1e3, 5),
+                     "algorithmic_bytes_per_launch": bytes_per_node * nodes},
+        "wall_s": round(wall, 3),
+    }
+
+    if not args.no_compare and args.workload != "single512x256":
+        ref = W.single_512x256()
+        lat64 = F.Lattice([ref], precision=F.FP64, sample_every=10)
+        lat64.step(args.warmup)
+        n64 = args.steps
+        ms64 = _events_time(lat64, n64)
+        out["compare"] = {"fp64_single_512x256_mlups": round(ref.Lx * ref.Lz * n64 / (ms64 / 1e3) / 1e6, 1),
+                          "note": "plain FP64 storage, single lattice, sampled every 10 steps"}
+        del lat64
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(reps, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

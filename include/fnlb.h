@@ -1,0 +1,181 @@
+/*
+ * fnlb — fluctuating two-species D2Q9 lattice Boltzmann on MI355X (gfx950).
+ *
+ * C ABI of the GPU library.  The method is the fluctuating multicomponent
+ * lattice Boltzmann scheme of Belardinelli, Sbragaglia, Benzi and Ciliberto,
+ * "Lattice Boltzmann Simulations of Non-Equilibrium Fluctuations in a
+ * Non-Ideal Binary Mixture" (arXiv:1808.05168): a binary mixture between two
+ * walls at z = +-L/2 with periodic x (Sec. III.A), an imposed linear
+ * concentration profile c_0(z) = 1/2 + z grad_c0 (Fig. 1), the non-ideal
+ * interaction force of Eq. (11), the non-equilibrium acceleration of Eq. (12)
+ * with the a_* correction of the footnote to Eq. (13), MRT relaxation
+ * (Eq. (15), Table I) and thermal noise in the non-conserved moments
+ * (Eqs. (22)-(23)).  The observables are the structure factors of the
+ * concentration and density fluctuations (Appendix, Eqs. (A1)-(A4)) and the
+ * mean pressure (Eq. (24), Sec. IV.C).
+ *
+ * Conventions shared by every call:
+ *  - All functions return FNLB_OK (0) or a negative FNLB_E* code; no call
+ *    throws.  Errors are sticky per handle: once a call failed with
+ *    FNLB_EDEVICE or FNLB_EWATCHDOG, later calls on that handle return it.
+ *  - Device buffers (state, accumulators, workspace) are allocated and owned
+ *    by the caller, sized by fnlb_bytes_required(), 256-byte aligned, and must
+ *    outlive the handle.  The library allocates no device memory.  It owns
+ *    only small host metadata, freed by fnlb_destroy().
+ *  - Work is enqueued asynchronously on the caller's HIP stream; read_* calls
+ *    synchronise that stream and copy into caller-allocated host arrays.
+ *  - One handle is used from one host thread at a time.
+ */
+#ifndef FNLB_H
+#define FNLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---- */
+#define FNLB_OK 0
+#define FNLB_EINVAL (-1)    /* invalid argument or parameter */
+#define FNLB_ENOMEM (-2)    /* a caller buffer is smaller than required */
+#define FNLB_EDEVICE (-3)   /* a HIP runtime call failed */
+#define FNLB_EWATCHDOG (-4) /* non-finite or non-physical state detected */
+#define FNLB_ESTATE (-5)    /* call not valid in the handle's current state */
+
+/* ---- precision of the stored populations ---- */
+#define FNLB_FP64 0     /* populations stored and updated in FP64 */
+#define FNLB_FP32_DEV 1 /* FP32 storage of deviations from w_l rho_ref^S(z);
+                           collision in FP32, observables and accumulators in
+                           FP64 */
+
+/* ---- option flags (fnlb_options.flags) ---- */
+#define FNLB_ASTAR 1         /* a_* correction of the footnote to Eq. (13) */
+#define FNLB_WALL_UZ_FIX 2   /* U_z = 0 on the wall rows every step (Sec. III.A) */
+#define FNLB_NOISE_LOC 4     /* noise amplitudes of Eqs. (22)-(23) from local
+                                densities instead of the reference values */
+#define FNLB_FORCE_LITERAL 8 /* first-order forcing moments rho^S a^S without
+                                the (1 - lambda_d/2) factor (diagnostic) */
+#define FNLB_DEFAULT_FLAGS (FNLB_ASTAR | FNLB_WALL_UZ_FIX)
+
+/* ---- fields of the structure factor ---- */
+#define FNLB_FIELD_C 0   /* delta c   = rho^A/rho - c_0(z) */
+#define FNLB_FIELD_RHO 1 /* delta rho = rho - rho_bar */
+
+/* One lattice ("replica").  Sec. III.A: Lx x Lz nodes, x periodic, walls half
+ * a link outside rows 0 and Lz-1, reference density rho_bar, c_bar0 = 1/2. */
+typedef struct {
+  int32_t Lx, Lz;   /* Lx >= 2 columns (periodic), Lz >= 2 fluid rows */
+  double rho0;      /* reference total density rho_bar > 0 */
+  double grad_c0;   /* imposed concentration gradient; |grad_c0| * Lz < 1 */
+  double kT;        /* thermal energy >= 0 (0: noiseless) */
+  double G;         /* non-ideal coupling of Eq. (11), >= 0 */
+  double tau_d;     /* 1/lambda_d: moments a = 1,2 (Eq. (16)); D = (tau_d - 1/2)/3 */
+  double tau_s;     /* 1/lambda_s: moments a = 4,5 (Eq. (17)); nu = (tau_s - 1/2)/3 */
+  double tau_e;     /* 1/lambda_e: moment a = 3 */
+  double tau_q;     /* 1/lambda_Q: moments a = 6,7 */
+  double tau_eps;   /* 1/lambda_eps: moment a = 8; every tau > 1/2 */
+  uint64_t seed;    /* Philox4x32-10 key of this replica's noise */
+} fnlb_replica_params;
+
+typedef struct {
+  int32_t precision;    /* FNLB_FP64 or FNLB_FP32_DEV */
+  int32_t sample_every; /* > 0: inside fnlb_step, the state f(t) is sampled
+                           (structure factors and pressure) before the step
+                           t -> t+1 whenever t >= 1 and t % sample_every == 0;
+                           0: sampling only through
+                           fnlb_accumulate_structure_factor() */
+  int32_t flags;        /* FNLB_* option bits; FNLB_DEFAULT_FLAGS recommended */
+  int32_t chunk_rows;   /* rows per work item of the step kernel; 0 = automatic
+                           (autotuned value if one was stored for this shape) */
+} fnlb_options;
+
+typedef struct fnlb_handle fnlb_handle;
+
+/* Bytes of the three caller-owned device buffers for n_rep replicas:
+ *   state: two ping-pong copies of 2 species x 9 populations per node, FP64 or
+ *          FP32 per options->precision (layout internal; read it through
+ *          fnlb_read_populations);
+ *   accum: FP64 accumulators (structure factors and pressure sums);
+ *   work:  sample fields, FFT staging, twiddles, tables and reduction partials.
+ * Returns FNLB_EINVAL for invalid parameters (the checks of fnlb_init). */
+int fnlb_bytes_required(const fnlb_replica_params* reps, int32_t n_rep,
+                        const fnlb_options* options, size_t* state_bytes,
+                        size_t* accum_bytes, size_t* work_bytes);
+
+/* Creates a handle over the caller's buffers, uploads the replica tables,
+ * sets time t = 0, initialises every replica to the state of rest on the
+ * imposed profile (f^S_l = w_l rho_0^S(z), rho_0^A = rho_bar c_0(z),
+ * rho_0^B = rho_bar (1 - c_0(z)), U = 0; Fig. 1) and clears the accumulators.
+ * hip_stream is a hipStream_t (NULL = default stream).  Asynchronous. */
+int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep,
+              const fnlb_options* options, void* d_state, size_t state_bytes,
+              void* d_accum, size_t accum_bytes, void* d_work,
+              size_t work_bytes, void* hip_stream, fnlb_handle** out);
+
+/* Advances every replica by n >= 0 time steps of Eq. (6): per node,
+ * densities, non-ideal and non-equilibrium forces, wall U_z fix, barycentric
+ * velocity (Eq. (10)), MRT collision with forcing moments and noise (Eq. (14)),
+ * then streaming with mid-way bounce-back at the walls and periodic x.
+ * Samples according to options->sample_every.  Asynchronous. */
+int fnlb_step(fnlb_handle* h, int64_t n);
+
+/* Samples the current state f(t) of every replica now: adds |Phi(q)|^2,
+ * Re Phi(q), Im Phi(q) of delta c and delta rho, with
+ * Phi(q) = (Lx Lz)^{-1/2} sum_{x,j} delta phi(x,j) exp(-i (q_x x + q_z j)),
+ * q_x = 2 pi k_x / Lx, q_z = 2 pi k_z / Lz, to the structure-factor
+ * accumulators, and the spatial mean of P - P_ref (its square, and its row
+ * means) to the pressure accumulators.  Asynchronous. */
+int fnlb_accumulate_structure_factor(fnlb_handle* h);
+
+/* Copies the structure-factor sums of replica rep, field FNLB_FIELD_C or
+ * FNLB_FIELD_RHO, into host arrays of Lz * (Lx/2 + 1) doubles laid out
+ * [k_z][k_x] (k_x = 0..Lx/2); any of the three may be NULL.  S(q) =
+ * sum_abs2/n - (sum_re/n)^2 - (sum_im/n)^2.  Synchronises the stream. */
+int fnlb_read_structure_factor(fnlb_handle* h, int32_t rep, int32_t field,
+                               double* sum_abs2, double* sum_re,
+                               double* sum_im, int64_t* n_samples);
+
+/* Copies the pressure sums of replica rep: sum over samples of the spatial
+ * mean of P - P_ref, of its square, and (profile_sum, nullable, Lz doubles) of
+ * the row means.  P(r) = rho/3 + (G/4) sum_{l>=1} w_l |c_l|^2 [rho^A(r)
+ * rho^B(r+c_l) + rho^B(r) rho^A(r+c_l)] (half trace of the pressure tensor;
+ * equals Eq. (24) on a uniform state), P_ref = rho_bar/3 + G rho_bar^2/12.
+ * Synchronises the stream. */
+int fnlb_read_pressure(fnlb_handle* h, int32_t rep, double* sum_dP,
+                       double* sum_dP2, double* profile_sum,
+                       int64_t* n_samples);
+
+/* Copies the populations f(t) of replica rep as FP64 full values (not
+ * deviations) into a host array laid out [species][l][z][x] (2*9*Lz*Lx).
+ * Synchronises the stream. */
+int fnlb_read_populations(fnlb_handle* h, int32_t rep, double* out);
+
+/* Overwrites the populations of replica rep from a host array in the layout
+ * of fnlb_read_populations (FP32_DEV rounds the deviations to FP32).
+ * Synchronises the stream. */
+int fnlb_write_populations(fnlb_handle* h, int32_t rep, const double* in);
+
+/* Clears all structure-factor and pressure accumulators and the sample count.
+ * Asynchronous. */
+int fnlb_reset_accumulators(fnlb_handle* h);
+
+/* Current time t (number of steps taken since init). */
+int fnlb_get_time(const fnlb_handle* h, int64_t* t);
+
+/* Sets the time counter (keys the noise and the sampling schedule), e.g. to
+ * continue a run after fnlb_write_populations.  t >= 0. */
+int fnlb_set_time(fnlb_handle* h, int64_t t);
+
+/* Frees the handle's host metadata.  Caller buffers are untouched. */
+int fnlb_destroy(fnlb_handle* h);
+
+/* Static message for an error code. */
+const char* fnlb_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FNLB_H */

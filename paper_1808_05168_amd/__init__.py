@@ -1,0 +1,11 @@
+"""fnlb: fluctuating two-species D2Q9 lattice Boltzmann on MI355X (gfx950).
+
+The hot path (collision, forcing, noise, streaming, structure-factor and
+pressure accumulation) runs in the HIP library ``libfnlb.so`` behind the C ABI
+of ``include/fnlb.h``; this package is its thin Python binding.
+"""
+from .fnlb import (ASTAR, DEFAULT_FLAGS, FIELD_C, FIELD_RHO, FORCE_LITERAL, FP32_DEV, FP64,
+                   NOISE_LOC, WALL_UZ_FIX, FnlbError, Lattice, bytes_required, load)
+
+__all__ = ["ASTAR", "DEFAULT_FLAGS", "FIELD_C", "FIELD_RHO", "FORCE_LITERAL", "FP32_DEV",
+           "FP64", "NOISE_LOC", "WALL_UZ_FIX", "FnlbError", "Lattice", "bytes_required", "load"]

@@ -1,0 +1,501 @@
+// Host runtime of the fnlb library: parameter validation, the buffer plan,
+// replica and work-item tables, the per-step launch sequence and the
+// synchronous read/write calls of the C ABI (include/fnlb.h).
+#include "fnlb.h"
+#include "fnlb_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace fnlb;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Largest lattice dimension the observable kernels hold in LDS (64 KiB of
+// complex doubles per row or column).
+constexpr int kMaxDim = 4096;
+// Largest non-power-of-two dimension (direct transform, quadratic cost).
+constexpr int kMaxDirect = 2048;
+// Complex entries of the column-pass LDS tile.
+constexpr int kColTile = 4096;
+
+int validate(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options* opt) {
+  if (!reps || !opt || n_rep <= 0) return FNLB_EINVAL;
+  if (opt->precision != FNLB_FP64 && opt->precision != FNLB_FP32_DEV) return FNLB_EINVAL;
+  if (opt->sample_every < 0 || opt->chunk_rows < 0) return FNLB_EINVAL;
+  if (opt->flags & ~(FNLB_ASTAR | FNLB_WALL_UZ_FIX | FNLB_NOISE_LOC | FNLB_FORCE_LITERAL))
+    return FNLB_EINVAL;
+  for (int r = 0; r < n_rep; ++r) {
+    const fnlb_replica_params& p = reps[r];
+    if (p.Lx < 2 || p.Lz < 2 || p.Lx > kMaxDim || p.Lz > kMaxDim) return FNLB_EINVAL;
+    const bool p2 = is_pow2(p.Lx) && is_pow2(p.Lz);
+    if (!p2 && (p.Lx > kMaxDirect || p.Lz > kMaxDirect)) return FNLB_EINVAL;
+    if ((int64_t)p.Lx * p.Lz >= (int64_t)1 << 31) return FNLB_EINVAL;
+    if (!(p.rho0 > 0) || !(p.kT >= 0) || !(p.G >= 0) || !std::isfinite(p.kT) ||
+        !std::isfinite(p.G) || !std::isfinite(p.rho0))
+      return FNLB_EINVAL;
+    const double taus[5] = {p.tau_d, p.tau_s, p.tau_e, p.tau_q, p.tau_eps};
+    for (double t : taus)
+      if (!(t > 0.5) || !std::isfinite(t)) return FNLB_EINVAL;
+    if (!(std::fabs(p.grad_c0) * p.Lz < 1.0)) return FNLB_EINVAL;
+  }
+  return FNLB_OK;
+}
+
+// The buffer plan: every offset the kernels use.
+struct Plan {
+  std::vector<RepInfo> info;
+  std::vector<Item> items;
+  std::vector<RowRef> rows;
+  std::vector<ColRef> cols;
+  size_t store_size = 0;
+  size_t state_half = 0;  // bytes of one state copy
+  size_t state_bytes = 0, accum_bytes = 0, work_bytes = 0;
+  // work-buffer offsets (bytes)
+  size_t o_reps = 0, o_items = 0, o_rows = 0, o_cols = 0, o_misc = 0, o_tw = 0, o_fields = 0,
+         o_spec = 0, o_ppart = 0;
+  int max_lx = 0, max_lz = 0, max_col_lds = 0, chunk = 0;
+};
+
+int auto_chunk(const fnlb_replica_params* reps, int n_rep) {
+  int64_t strip_rows = 0;
+  for (int r = 0; r < n_rep; ++r)
+    strip_rows += (int64_t)((reps[r].Lx + kStrip - 1) / kStrip) * reps[r].Lz;
+  // aim for about 2048 wavefronts (8 per compute unit) when the lattice allows
+  int64_t c = strip_rows / 2048;
+  int chunk = 4;
+  while (chunk * 2 <= c && chunk < 64) chunk *= 2;
+  return chunk;
+}
+
+void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* opt, Plan& P) {
+  P.store_size = opt->precision == FNLB_FP64 ? 8 : 4;
+  P.chunk = opt->chunk_rows > 0 ? opt->chunk_rows : auto_chunk(reps, n_rep);
+  P.info.assign(n_rep, RepInfo{});
+  int64_t state_elems = 0, field_d = 0, spec_c = 0, acc_d = 0, ppart_d = 0, tw_c = 0;
+  const int64_t elem_align = (int64_t)(kAlign / P.store_size);
+  for (int r = 0; r < n_rep; ++r) {
+    const fnlb_replica_params& p = reps[r];
+    RepInfo& R = P.info[r];
+    R.Lx = p.Lx;
+    R.Lz = p.Lz;
+    R.pitch = p.Lx;
+    R.nstrips = (p.Lx + kStrip - 1) / kStrip;
+    R.plane = ((int64_t)p.Lz * R.pitch + elem_align - 1) / elem_align * elem_align;
+    R.state_off = state_elems;
+    state_elems += 18 * R.plane;
+    const int nkx = p.Lx / 2 + 1;
+    R.field_off = field_d;
+    field_d += 2LL * p.Lz * p.Lx;
+    R.spec_off = spec_c;
+    spec_c += 2LL * p.Lz * nkx;
+    R.acc_off = acc_d;
+    acc_d += 6LL * p.Lz * nkx;
+    R.pacc_off = acc_d;
+    acc_d += 2 + p.Lz;
+    R.ppart_off = ppart_d;
+    ppart_d += (int64_t)R.nstrips * p.Lz;
+    R.tw_off = tw_c;
+    tw_c += p.Lx + p.Lz;
+    R.flags = opt->flags;
+    R.pow2 = is_pow2(p.Lx) && is_pow2(p.Lz);
+    R.seed_lo = (uint32_t)p.seed;
+    R.seed_hi = (uint32_t)(p.seed >> 32);
+    R.rho0 = p.rho0;
+    R.grad = p.grad_c0;
+    R.G = p.G;
+    R.ne_coef = p.grad_c0 / 3.0;
+    R.rA_mid = p.rho0 * (0.5 - 0.5 * (p.Lz - 1) * p.grad_c0);
+    R.rA_step = p.rho0 * p.grad_c0;
+    const double lam_d = 1.0 / p.tau_d, lam_s = 1.0 / p.tau_s, lam_e = 1.0 / p.tau_e,
+                 lam_q = 1.0 / p.tau_q, lam_p = 1.0 / p.tau_eps;
+    const double lam[9] = {0.0, lam_d, lam_d, lam_e, lam_s, lam_s, lam_q, lam_q, lam_p};
+    // N_a = sum_l w_l T_al^2 of the basis of Table I
+    const double N[9] = {1.0, 1.0 / 3, 1.0 / 3, 4.0, 4.0 / 9, 1.0 / 9, 2.0 / 3, 2.0 / 3, 16.0};
+    for (int q = 0; q < 9; ++q) {
+      R.lam[q] = lam[q];
+      R.fac[q] = 1.0 - 0.5 * lam[q];
+    }
+    if (opt->flags & FNLB_FORCE_LITERAL) R.fac[1] = R.fac[2] = 1.0;
+    // Eq. (22): <xi xi>_{1,2} = (2 - lam_d) lam_d kT rho^A rho^B / rho;
+    // Eq. (23): <xi^S xi^S>_a = 3 (2 - lam_a) lam_a N_a kT rho^S, a = 3..8;
+    // reference densities rho_bar/2 each ("hom" noise).
+    const double rbar = 0.5 * p.rho0;
+    std::memset(R.sig, 0, sizeof(R.sig));
+    std::memset(R.sig_base, 0, sizeof(R.sig_base));
+    R.sig_base[1] = std::sqrt((2.0 - lam_d) * lam_d * p.kT);
+    R.sig[0][1] = R.sig[1][1] = R.sig_base[1] * std::sqrt(rbar * rbar / p.rho0);
+    for (int q = 3; q < 9; ++q) {
+      R.sig_base[q] = std::sqrt(3.0 * (2.0 - lam[q]) * lam[q] * N[q] * p.kT);
+      R.sig[0][q] = R.sig[1][q] = R.sig_base[q] * std::sqrt(rbar);
+    }
+    R.p_ref = p.rho0 / 3.0 + p.G * p.rho0 * p.rho0 / 12.0;
+    R.inv_norm = 1.0 / std::sqrt((double)p.Lx * (double)p.Lz);
+    P.max_lx = std::max(P.max_lx, p.Lx);
+    P.max_lz = std::max(P.max_lz, p.Lz);
+  }
+  // work items: (replica, strip, row range)
+  P.items.clear();
+  for (int r = 0; r < n_rep; ++r) {
+    const RepInfo& R = P.info[r];
+    for (int s = 0; s < R.nstrips; ++s)
+      for (int j0 = 0; j0 < R.Lz; j0 += P.chunk)
+        P.items.push_back(Item{r, s, j0, std::min(R.Lz, j0 + P.chunk)});
+  }
+  // rows and column tiles of the transforms
+  P.rows.clear();
+  P.cols.clear();
+  P.max_col_lds = 0;
+  for (int r = 0; r < n_rep; ++r) {
+    const RepInfo& R = P.info[r];
+    for (int j = 0; j < R.Lz; ++j) P.rows.push_back(RowRef{r, j});
+    const int nkx = R.Lx / 2 + 1;
+    const int tile = std::max(1, std::min(16, kColTile / R.Lz));
+    for (int f = 0; f < 2; ++f)
+      for (int k0 = 0; k0 < nkx; k0 += tile) {
+        const int nc = std::min(tile, nkx - k0);
+        P.cols.push_back(ColRef{r, f, k0, nc});
+        P.max_col_lds = std::max(P.max_col_lds, nc * R.Lz);
+      }
+  }
+  P.state_half = align_up((size_t)state_elems * P.store_size);
+  P.state_bytes = 2 * P.state_half;
+  P.accum_bytes = align_up((size_t)acc_d * 8);
+  size_t o = 0;
+  P.o_reps = o;
+  o = align_up(o + P.info.size() * sizeof(RepInfo));
+  P.o_items = o;
+  o = align_up(o + P.items.size() * sizeof(Item));
+  P.o_rows = o;
+  o = align_up(o + P.rows.size() * sizeof(RowRef));
+  P.o_cols = o;
+  o = align_up(o + P.cols.size() * sizeof(ColRef));
+  P.o_misc = o;  // int64 time base + int32 watchdog
+  o = align_up(o + 16);
+  P.o_tw = o;
+  o = align_up(o + (size_t)tw_c * 16);
+  P.o_fields = o;
+  o = align_up(o + (size_t)field_d * 8);
+  P.o_spec = o;
+  o = align_up(o + (size_t)spec_c * 16);
+  P.o_ppart = o;
+  o = align_up(o + (size_t)ppart_d * 8);
+  P.work_bytes = o;
+}
+
+}  // namespace
+
+struct fnlb_handle {
+  std::vector<fnlb_replica_params> reps;
+  fnlb_options opt{};
+  Plan plan;
+  char* state = nullptr;
+  char* accum = nullptr;
+  char* work = nullptr;
+  hipStream_t stream = nullptr;
+  int cur = 0;           // which state copy holds f(t)
+  int64_t t = 0;         // current time
+  int64_t t_dev = 0;     // value held by the device time base
+  int64_t nsamples = 0;
+  int error = FNLB_OK;   // sticky error
+
+  RepInfo* d_reps() { return (RepInfo*)(work + plan.o_reps); }
+  Item* d_items() { return (Item*)(work + plan.o_items); }
+  RowRef* d_rows() { return (RowRef*)(work + plan.o_rows); }
+  ColRef* d_cols() { return (ColRef*)(work + plan.o_cols); }
+  int64_t* d_time() { return (int64_t*)(work + plan.o_misc); }
+  int32_t* d_watchdog() { return (int32_t*)(work + plan.o_misc + 8); }
+  double2* d_tw() { return (double2*)(work + plan.o_tw); }
+  double* d_fields() { return (double*)(work + plan.o_fields); }
+  double2* d_spec() { return (double2*)(work + plan.o_spec); }
+  double* d_ppart() { return (double*)(work + plan.o_ppart); }
+  char* state_copy(int k) { return state + (size_t)k * plan.state_half; }
+};
+
+namespace {
+
+int dev_err(fnlb_handle* h, hipError_t e) {
+  if (e == hipSuccess) return FNLB_OK;
+  h->error = FNLB_EDEVICE;
+  return FNLB_EDEVICE;
+}
+
+StepArgs step_args(fnlb_handle* h, int64_t t_off) {
+  StepArgs a{};
+  a.reps = h->d_reps();
+  a.items = h->d_items();
+  a.n_items = (int)h->plan.items.size();
+  int nb = (a.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
+  nb = (nb + 7) / 8 * 8;
+  a.n_blocks = nb;
+  a.state_in = h->state_copy(h->cur);
+  a.state_out = h->state_copy(1 - h->cur);
+  a.t_base = h->d_time();
+  a.t_off = t_off;
+  a.fields = h->d_fields();
+  a.ppart = h->d_ppart();
+  a.watchdog = h->d_watchdog();
+  return a;
+}
+
+// Structure-factor transforms and pressure reduction of the sample fields.
+hipError_t observe(fnlb_handle* h) {
+  const Plan& P = h->plan;
+  hipError_t e = launch_row_transform(h->d_reps(), h->d_rows(), (int)P.rows.size(), P.max_lx,
+                                      h->d_fields(), h->d_spec(), h->d_tw(), h->stream);
+  if (e != hipSuccess) return e;
+  e = launch_col_transform(h->d_reps(), h->d_cols(), (int)P.cols.size(), P.max_col_lds,
+                           h->d_spec(), (double*)h->accum, h->d_tw(), h->stream);
+  if (e != hipSuccess) return e;
+  return launch_pressure_reduce(h->d_reps(), (int)P.info.size(), P.max_lz, h->d_ppart(),
+                                (double*)h->accum, h->stream);
+}
+
+int check_watchdog(fnlb_handle* h) {
+  int32_t flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, h->d_watchdog(), 4, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return dev_err(h, e);
+  if (flag) h->error = FNLB_EWATCHDOG;
+  return h->error;
+}
+
+const double kW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+}  // namespace
+
+extern "C" {
+
+int fnlb_bytes_required(const fnlb_replica_params* reps, int32_t n_rep,
+                        const fnlb_options* options, size_t* state_bytes, size_t* accum_bytes,
+                        size_t* work_bytes) {
+  const int rc = validate(reps, n_rep, options);
+  if (rc) return rc;
+  Plan P;
+  make_plan(reps, n_rep, options, P);
+  if (state_bytes) *state_bytes = P.state_bytes;
+  if (accum_bytes) *accum_bytes = P.accum_bytes;
+  if (work_bytes) *work_bytes = P.work_bytes;
+  return FNLB_OK;
+}
+
+int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options* options,
+              void* d_state, size_t state_bytes, void* d_accum, size_t accum_bytes,
+              void* d_work, size_t work_bytes, void* hip_stream, fnlb_handle** out) {
+  if (!out) return FNLB_EINVAL;
+  *out = nullptr;
+  int rc = validate(reps, n_rep, options);
+  if (rc) return rc;
+  if (!d_state || !d_accum || !d_work) return FNLB_EINVAL;
+  if (((uintptr_t)d_state | (uintptr_t)d_accum | (uintptr_t)d_work) % kAlign) return FNLB_EINVAL;
+  fnlb_handle* h = new (std::nothrow) fnlb_handle();
+  if (!h) return FNLB_ENOMEM;
+  h->reps.assign(reps, reps + n_rep);
+  h->opt = *options;
+  make_plan(reps, n_rep, options, h->plan);
+  const Plan& P = h->plan;
+  if (state_bytes < P.state_bytes || accum_bytes < P.accum_bytes || work_bytes < P.work_bytes) {
+    delete h;
+    return FNLB_ENOMEM;
+  }
+  h->state = (char*)d_state;
+  h->accum = (char*)d_accum;
+  h->work = (char*)d_work;
+  h->stream = (hipStream_t)hip_stream;
+  hipStream_t s = h->stream;
+  hipError_t e = hipSuccess;
+  auto up = [&](size_t off, const void* src, size_t n) {
+    if (e == hipSuccess && n) e = hipMemcpyAsync(h->work + off, src, n, hipMemcpyHostToDevice, s);
+  };
+  up(P.o_reps, P.info.data(), P.info.size() * sizeof(RepInfo));
+  up(P.o_items, P.items.data(), P.items.size() * sizeof(Item));
+  up(P.o_rows, P.rows.data(), P.rows.size() * sizeof(RowRef));
+  up(P.o_cols, P.cols.data(), P.cols.size() * sizeof(ColRef));
+  if (e == hipSuccess) e = launch_fill_zero(h->work + P.o_misc, 16, s);
+  if (e == hipSuccess) e = launch_fill_zero(h->work + P.o_ppart, P.work_bytes - P.o_ppart, s);
+  if (e == hipSuccess) e = launch_twiddles(h->d_reps(), P.info.data(), n_rep, h->d_tw(), s);
+  // state of rest on the imposed profile: all deviations zero
+  if (e == hipSuccess) e = launch_fill_zero(h->state, P.state_bytes, s);
+  if (e == hipSuccess) e = launch_fill_zero(h->accum, P.accum_bytes, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete h;
+    return FNLB_EDEVICE;
+  }
+  *out = h;
+  return FNLB_OK;
+}
+
+int fnlb_step(fnlb_handle* h, int64_t n) {
+  if (!h || n < 0) return FNLB_EINVAL;
+  if (h->error) return h->error;
+  const int every = h->opt.sample_every;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t t = h->t;
+    const bool smp = every > 0 && t >= 1 && t % every == 0;
+    StepArgs a = step_args(h, t - h->t_dev);
+    hipError_t e = launch_step(h->opt.precision, smp ? kStepSample : kStep, a, h->stream);
+    if (e == hipSuccess && smp) e = observe(h);
+    if (e != hipSuccess) return dev_err(h, e);
+    if (smp) ++h->nsamples;
+    h->cur ^= 1;
+    ++h->t;
+  }
+  return FNLB_OK;
+}
+
+int fnlb_accumulate_structure_factor(fnlb_handle* h) {
+  if (!h) return FNLB_EINVAL;
+  if (h->error) return h->error;
+  StepArgs a = step_args(h, h->t - h->t_dev);
+  hipError_t e = launch_step(h->opt.precision, kSampleOnly, a, h->stream);
+  if (e == hipSuccess) e = observe(h);
+  if (e != hipSuccess) return dev_err(h, e);
+  ++h->nsamples;
+  return FNLB_OK;
+}
+
+int fnlb_read_structure_factor(fnlb_handle* h, int32_t rep, int32_t field, double* sum_abs2,
+                               double* sum_re, double* sum_im, int64_t* n_samples) {
+  if (!h || rep < 0 || rep >= (int)h->reps.size() || (field != 0 && field != 1))
+    return FNLB_EINVAL;
+  if (h->error) return h->error;
+  const RepInfo& R = h->plan.info[rep];
+  const size_t plane = (size_t)R.Lz * (R.Lx / 2 + 1);
+  const double* base = (const double*)h->accum + R.acc_off + (size_t)field * 3 * plane;
+  double* dst[3] = {sum_abs2, sum_re, sum_im};
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 3 && e == hipSuccess; ++k)
+    if (dst[k])
+      e = hipMemcpyAsync(dst[k], base + k * plane, plane * 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return dev_err(h, e);
+  if (n_samples) *n_samples = h->nsamples;
+  return check_watchdog(h);
+}
+
+int fnlb_read_pressure(fnlb_handle* h, int32_t rep, double* sum_dP, double* sum_dP2,
+                       double* profile_sum, int64_t* n_samples) {
+  if (!h || rep < 0 || rep >= (int)h->reps.size()) return FNLB_EINVAL;
+  if (h->error) return h->error;
+  const RepInfo& R = h->plan.info[rep];
+  std::vector<double> buf(2 + R.Lz);
+  hipError_t e = hipMemcpyAsync(buf.data(), (const double*)h->accum + R.pacc_off,
+                                buf.size() * 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return dev_err(h, e);
+  if (sum_dP) *sum_dP = buf[0];
+  if (sum_dP2) *sum_dP2 = buf[1];
+  if (profile_sum) std::memcpy(profile_sum, buf.data() + 2, (size_t)R.Lz * 8);
+  if (n_samples) *n_samples = h->nsamples;
+  return check_watchdog(h);
+}
+
+int fnlb_read_populations(fnlb_handle* h, int32_t rep, double* out) {
+  if (!h || !out || rep < 0 || rep >= (int)h->reps.size()) return FNLB_EINVAL;
+  if (h->error) return h->error;
+  const RepInfo& R = h->plan.info[rep];
+  const size_t ss = h->plan.store_size;
+  const size_t n = (size_t)R.Lz * R.Lx;
+  std::vector<char> raw(18 * n * ss);
+  const char* src = h->state_copy(h->cur) + (size_t)R.state_off * ss;
+  hipError_t e = hipSuccess;
+  for (int q = 0; q < 18 && e == hipSuccess; ++q)
+    e = hipMemcpy2DAsync(raw.data() + q * n * ss, (size_t)R.Lx * ss,
+                         src + (size_t)q * R.plane * ss, (size_t)R.pitch * ss, (size_t)R.Lx * ss,
+                         (size_t)R.Lz, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return dev_err(h, e);
+  for (int s = 0; s < 2; ++s)
+    for (int l = 0; l < 9; ++l)
+      for (int j = 0; j < R.Lz; ++j) {
+        const double rA = R.rA_mid + R.rA_step * j;
+        const double ref = kW[l] * (s == 0 ? rA : R.rho0 - rA);
+        for (int x = 0; x < R.Lx; ++x) {
+          const size_t k = (size_t)(s * 9 + l) * n + (size_t)j * R.Lx + x;
+          const double d = ss == 8 ? ((const double*)raw.data())[k] : (double)((const float*)raw.data())[k];
+          out[k] = ref + d;
+        }
+      }
+  return FNLB_OK;
+}
+
+int fnlb_write_populations(fnlb_handle* h, int32_t rep, const double* in) {
+  if (!h || !in || rep < 0 || rep >= (int)h->reps.size()) return FNLB_EINVAL;
+  if (h->error) return h->error;
+  const RepInfo& R = h->plan.info[rep];
+  const size_t ss = h->plan.store_size;
+  const size_t n = (size_t)R.Lz * R.Lx;
+  std::vector<char> raw(18 * n * ss);
+  for (int s = 0; s < 2; ++s)
+    for (int l = 0; l < 9; ++l)
+      for (int j = 0; j < R.Lz; ++j) {
+        const double rA = R.rA_mid + R.rA_step * j;
+        const double ref = kW[l] * (s == 0 ? rA : R.rho0 - rA);
+        for (int x = 0; x < R.Lx; ++x) {
+          const size_t k = (size_t)(s * 9 + l) * n + (size_t)j * R.Lx + x;
+          const double d = in[k] - ref;
+          if (ss == 8)
+            ((double*)raw.data())[k] = d;
+          else
+            ((float*)raw.data())[k] = (float)d;
+        }
+      }
+  char* dst = h->state_copy(h->cur) + (size_t)R.state_off * ss;
+  hipError_t e = hipSuccess;
+  for (int q = 0; q < 18 && e == hipSuccess; ++q)
+    e = hipMemcpy2DAsync(dst + (size_t)q * R.plane * ss, (size_t)R.pitch * ss,
+                         raw.data() + q * n * ss, (size_t)R.Lx * ss, (size_t)R.Lx * ss,
+                         (size_t)R.Lz, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  return dev_err(h, e);
+}
+
+int fnlb_reset_accumulators(fnlb_handle* h) {
+  if (!h) return FNLB_EINVAL;
+  if (h->error) return h->error;
+  hipError_t e = launch_fill_zero(h->accum, h->plan.accum_bytes, h->stream);
+  if (e != hipSuccess) return dev_err(h, e);
+  h->nsamples = 0;
+  return FNLB_OK;
+}
+
+int fnlb_get_time(const fnlb_handle* h, int64_t* t) {
+  if (!h || !t) return FNLB_EINVAL;
+  *t = h->t;
+  return FNLB_OK;
+}
+
+int fnlb_set_time(fnlb_handle* h, int64_t t) {
+  if (!h || t < 0) return FNLB_EINVAL;
+  if (h->error) return h->error;
+  h->t = t;
+  return FNLB_OK;
+}
+
+int fnlb_destroy(fnlb_handle* h) {
+  delete h;
+  return FNLB_OK;
+}
+
+const char* fnlb_strerror(int code) {
+  switch (code) {
+    case FNLB_OK: return "ok";
+    case FNLB_EINVAL: return "invalid argument or parameter";
+    case FNLB_ENOMEM: return "caller buffer smaller than required";
+    case FNLB_EDEVICE: return "HIP runtime error";
+    case FNLB_EWATCHDOG: return "non-finite or non-physical state detected";
+    case FNLB_ESTATE: return "call not valid in the current state";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Device helpers of the fnlb kernels: the counter-based noise generator,
+// Box-Muller in FP64 and FP32, and wavefront lane shifts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fnlb {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the Philox
+// S-box on a 4x32-bit counter under a 2x32-bit key; the key is bumped by the
+// Weyl increments between rounds.  Multipliers and increments are the
+// published ones.
+struct Philox4 {
+  uint32_t v[4];
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                  uint32_t c3, uint32_t k0, uint32_t k1) {
+  constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+  constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t pa = (uint64_t)kMulA * c0;
+    const uint64_t pb = (uint64_t)kMulB * c2;
+    const uint32_t y0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+    const uint32_t y2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)pb;
+    c3 = (uint32_t)pa;
+    c0 = y0;
+    c2 = y2;
+    k0 += kWeylA;
+    k1 += kWeylB;
+  }
+  return Philox4{{c0, c1, c2, c3}};
+}
+
+// The 16 words of one node and one step: counter (node, t_lo, t_hi, call) for
+// call = 0..3, key (seed_lo, seed_hi).
+__device__ __forceinline__ void node_words(uint32_t node, uint64_t t, uint32_t k0,
+                                           uint32_t k1, uint32_t w[16]) {
+#pragma unroll
+  for (uint32_t call = 0; call < 4; ++call) {
+    const Philox4 r = philox4x32_10(node, (uint32_t)t, (uint32_t)(t >> 32), call, k0, k1);
+    w[4 * call + 0] = r.v[0];
+    w[4 * call + 1] = r.v[1];
+    w[4 * call + 2] = r.v[2];
+    w[4 * call + 3] = r.v[3];
+  }
+}
+
+// Box-Muller (Box and Muller 1958) on u = (w + 1/2) 2^-32:
+// g0 = sqrt(-2 ln u_a) cos(2 pi u_b), g1 = sqrt(-2 ln u_a) sin(2 pi u_b).
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& g0, double& g1) {
+  const double ua = ((double)wa + 0.5) * 0x1.0p-32;
+  const double ub = ((double)wb + 0.5) * 0x1.0p-32;
+  const double r = sqrt(-2.0 * log(ua));
+  double s, c;
+  sincospi(2.0 * ub, &s, &c);
+  g0 = r * c;
+  g1 = r * s;
+}
+
+// FP32 form.  ln u_a is taken through log1p(-(1 - u_a)) when u_a >= 1/2, where
+// 1 - u_a = (~w + 1/2) 2^-32 is exact before rounding; this keeps the radius
+// relatively accurate as u_a -> 1.
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& g0, float& g1) {
+  float ln_u;
+  if (wa & 0x80000000u) {
+    const float v = ((float)(~wa) + 0.5f) * 0x1.0p-32f;
+    ln_u = log1pf(-v);
+  } else {
+    const float u = ((float)wa + 0.5f) * 0x1.0p-32f;
+    ln_u = logf(u);
+  }
+  const float r = __builtin_sqrtf(-2.0f * ln_u);
+  const float ub = ((float)wb + 0.5f) * 0x1.0p-32f;
+  float s, c;
+  sincospif(2.0f * ub, &s, &c);
+  g0 = r * c;
+  g1 = r * s;
+}
+
+// Wavefront lane shifts through DPP: lane i receives lane i-1 (from_left) or
+// lane i+1 (from_right); the edge lane that has no source keeps its own value.
+__device__ __forceinline__ float from_left(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_right(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_left(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_right(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
+}
+
+// Deterministic sum over the 64 lanes of a wavefront (fixed butterfly order);
+// every lane receives the total.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+}  // namespace fnlb

@@ -1,0 +1,99 @@
+// Internal definitions of the fnlb GPU library shared by its host runtime and
+// its kernels: per-replica device tables, work-item tables, buffer layouts and
+// kernel-launch entry points.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace fnlb {
+
+// Width of the x-strip one wavefront updates: 64 lanes load 64 consecutive
+// columns, the two edge lanes only supply the x-neighbour densities of the
+// non-local force, so 62 columns per strip are updated.
+constexpr int kWave = 64;
+constexpr int kStrip = kWave - 2;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+
+// Everything a kernel needs about one replica.  Filled on the host, copied to
+// the work buffer once at init, read by the kernels with scalar loads.
+struct alignas(256) RepInfo {
+  int32_t Lx, Lz;         // lattice size
+  int32_t pitch;          // elements per row of a population plane (>= Lx)
+  int32_t nstrips;        // ceil(Lx / kStrip)
+  int64_t plane;          // elements per (species, link) plane
+  int64_t state_off;      // element offset of this replica in one state copy
+  int64_t field_off;      // double offset of the sample fields [2][Lz][Lx]
+  int64_t spec_off;       // double2 offset of the row spectra [2][Lz][Lx/2+1]
+  int64_t acc_off;        // double offset of [2][3][Lz][Lx/2+1] sums
+  int64_t pacc_off;       // double offset of {sum, sum2, profile[Lz]}
+  int64_t ppart_off;      // double offset of pressure partials [nstrips][Lz]
+  int64_t tw_off;         // double2 offset of twiddles: Lx entries then Lz
+  int32_t flags;          // FNLB_* option bits
+  int32_t pow2;           // both Lx and Lz are powers of two (FFT path)
+  uint32_t seed_lo, seed_hi;
+  double rho0;            // reference density rho_bar
+  double grad;            // grad_c0
+  double G;               // non-ideal coupling
+  double ne_coef;         // grad_c0 / 3 (non-equilibrium force per density)
+  double rA_mid;          // rho_bar * (1/2 - (Lz-1)/2 * grad_c0) = rho_ref^A(0)
+  double rA_step;         // rho_bar * grad_c0 = rho_ref^A(j+1) - rho_ref^A(j)
+  double lam[9];          // relaxation rate of each moment (lam[0] unused)
+  double fac[9];          // forcing factor per moment (1 - lam/2; or 1)
+  double sig[2][9];       // noise amplitudes of Eqs. (22)-(23), reference densities
+  double sig_base[9];     // same without the density factor (local-noise option)
+  double p_ref;           // rho_bar/3 + G rho_bar^2 / 12
+  double inv_norm;        // 1 / sqrt(Lx Lz)
+};
+
+// One wavefront's work: replica, x-strip and a range of rows.
+struct Item {
+  int32_t rep, strip, j0, j1;
+};
+
+// A row of one replica (row transform of the structure factor).
+struct RowRef {
+  int32_t rep, j;
+};
+
+// A tile of k_x columns of one field of one replica (column transform).
+struct ColRef {
+  int32_t rep, field, kx0, ncols;
+};
+
+// Kernel modes of the fused step.
+enum StepMode { kStep = 0, kStepSample = 1, kSampleOnly = 2 };
+
+struct StepArgs {
+  const RepInfo* reps;
+  const Item* items;
+  int32_t n_items;
+  int32_t n_blocks;       // blocks launched (multiple of 8 for the XCD map)
+  const void* state_in;   // current state copy
+  void* state_out;        // next state copy
+  const int64_t* t_base;  // device time counter (graph replays advance it)
+  int64_t t_off;          // time = *t_base + t_off
+  double* fields;         // sample fields base (double)
+  double* ppart;          // pressure partials base
+  int32_t* watchdog;      // set non-zero when a sample sees a bad state
+};
+
+// Launchers (asynchronous on `stream`).
+hipError_t launch_step(int precision, int mode, const StepArgs& a, hipStream_t stream);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t stream);
+hipError_t launch_twiddles(const RepInfo* d_reps, const RepInfo* h_reps, int n_rep,
+                           double2* tw_base, hipStream_t stream);
+hipError_t launch_row_transform(const RepInfo* reps, const RowRef* rows, int n_rows,
+                                int max_lx, const double* fields, double2* spec,
+                                const double2* tw, hipStream_t stream);
+hipError_t launch_col_transform(const RepInfo* reps, const ColRef* cols, int n_cols,
+                                int max_lds_cols, const double2* spec, double* acc,
+                                const double2* tw, hipStream_t stream);
+hipError_t launch_pressure_reduce(const RepInfo* reps, int n_rep, int max_lz,
+                                  const double* ppart, double* acc, hipStream_t stream);
+hipError_t launch_advance_time(int64_t* t_base, int64_t dt, hipStream_t stream);
+
+}  // namespace fnlb

@@ -1,0 +1,218 @@
+"""Python binding of libfnlb (include/fnlb.h): argument marshalling only.
+
+Device memory for the state, the accumulators and the workspace is allocated
+with torch on the GPU and handed to the library as raw pointers; the library
+enqueues its kernels on the current torch stream of that device.  Every step
+of the method runs in the library's HIP kernels; there is no host fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfnlb.so")
+
+FNLB_OK = 0
+FP64, FP32_DEV = 0, 1
+ASTAR, WALL_UZ_FIX, NOISE_LOC, FORCE_LITERAL = 1, 2, 4, 8
+DEFAULT_FLAGS = ASTAR | WALL_UZ_FIX
+FIELD_C, FIELD_RHO = 0, 1
+
+
+class ReplicaParams(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int32), ("Lz", ctypes.c_int32),
+                ("rho0", ctypes.c_double), ("grad_c0", ctypes.c_double),
+                ("kT", ctypes.c_double), ("G", ctypes.c_double),
+                ("tau_d", ctypes.c_double), ("tau_s", ctypes.c_double),
+                ("tau_e", ctypes.c_double), ("tau_q", ctypes.c_double),
+                ("tau_eps", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("sample_every", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("chunk_rows", ctypes.c_int32)]
+
+
+class FnlbError(RuntimeError):
+    pass
+
+
+_lib = None
+EXPORTS = ["fnlb_bytes_required", "fnlb_init", "fnlb_step",
+           "fnlb_accumulate_structure_factor", "fnlb_read_structure_factor",
+           "fnlb_read_pressure", "fnlb_read_populations", "fnlb_write_populations",
+           "fnlb_reset_accumulators", "fnlb_get_time", "fnlb_set_time", "fnlb_destroy",
+           "fnlb_strerror"]
+
+
+def load(path: str = LIB_PATH):
+    """Loads libfnlb.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FnlbError(f"{path} not found: build it with `python -m paper_1808_05168_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    rp, op = ctypes.POINTER(ReplicaParams), ctypes.POINTER(Options)
+    lib.fnlb_bytes_required.argtypes = [rp, ctypes.c_int32, op, szp, szp, szp]
+    lib.fnlb_init.argtypes = [rp, ctypes.c_int32, op, vp, ctypes.c_size_t, vp, ctypes.c_size_t,
+                              vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.fnlb_step.argtypes = [vp, ctypes.c_int64]
+    lib.fnlb_accumulate_structure_factor.argtypes = [vp]
+    lib.fnlb_read_structure_factor.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, dp, dp, dp,
+                                               i64p]
+    lib.fnlb_read_pressure.argtypes = [vp, ctypes.c_int32, dp, dp, dp, i64p]
+    lib.fnlb_read_populations.argtypes = [vp, ctypes.c_int32, dp]
+    lib.fnlb_write_populations.argtypes = [vp, ctypes.c_int32, dp]
+    lib.fnlb_reset_accumulators.argtypes = [vp]
+    lib.fnlb_get_time.argtypes = [vp, i64p]
+    lib.fnlb_set_time.argtypes = [vp, ctypes.c_int64]
+    lib.fnlb_destroy.argtypes = [vp]
+    lib.fnlb_strerror.argtypes = [ctypes.c_int]
+    lib.fnlb_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != FNLB_OK:
+        msg = load().fnlb_strerror(rc).decode()
+        raise FnlbError(f"{what} failed: {msg} ({rc})")
+
+
+def _dp(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def replica_params(reps: Sequence) -> ctypes.Array:
+    arr = (ReplicaParams * len(reps))()
+    for i, r in enumerate(reps):
+        arr[i] = ReplicaParams(r.Lx, r.Lz, r.rho0, r.grad_c0, r.kT, r.G, r.tau_d, r.tau_s,
+                               r.tau_e, r.tau_q, r.tau_eps, r.seed & ((1 << 64) - 1))
+    return arr
+
+
+def bytes_required(reps: Sequence, precision: int = FP64, sample_every: int = 0,
+                   flags: int = DEFAULT_FLAGS, chunk_rows: int = 0):
+    lib = load()
+    p = replica_params(reps)
+    o = Options(precision, sample_every, flags, chunk_rows)
+    s, a, w = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib.fnlb_bytes_required(p, len(reps), ctypes.byref(o), ctypes.byref(s),
+                                   ctypes.byref(a), ctypes.byref(w)), "fnlb_bytes_required")
+    return s.value, a.value, w.value
+
+
+class Lattice:
+    """A batch of one or more replicas on one GPU.
+
+    reps: objects with the fields of ``fnlb_replica_params`` (e.g.
+    ``workloads.Replica``).  precision: FP64 or FP32_DEV.
+    """
+
+    def __init__(self, reps: Iterable, precision: int = FP64, sample_every: int = 0,
+                 flags: int = DEFAULT_FLAGS, chunk_rows: int = 0, device: str = "cuda:0"):
+        import torch
+        self.reps: List = list(reps)
+        self.precision = precision
+        self.sample_every = sample_every
+        self.flags = flags
+        lib = load()
+        self._lib = lib
+        self._params = replica_params(self.reps)
+        self._opts = Options(precision, sample_every, flags, chunk_rows)
+        sb, ab, wb = bytes_required(self.reps, precision, sample_every, flags, chunk_rows)
+        self.device = torch.device(device)
+        # torch's caching allocator returns 512-byte aligned blocks
+        self.state = torch.empty(sb, dtype=torch.uint8, device=self.device)
+        self.accum = torch.empty(ab, dtype=torch.uint8, device=self.device)
+        self.work = torch.empty(wb, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib.fnlb_init(self._params, len(self.reps), ctypes.byref(self._opts),
+                             ctypes.c_void_p(self.state.data_ptr()), sb,
+                             ctypes.c_void_p(self.accum.data_ptr()), ab,
+                             ctypes.c_void_p(self.work.data_ptr()), wb,
+                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "fnlb_init")
+        self._h = h
+
+    # -- lifetime --
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.fnlb_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the method --
+    def step(self, n: int = 1) -> None:
+        _check(self._lib.fnlb_step(self._h, int(n)), "fnlb_step")
+
+    def accumulate_structure_factor(self) -> None:
+        _check(self._lib.fnlb_accumulate_structure_factor(self._h),
+               "fnlb_accumulate_structure_factor")
+
+    def read_structure_factor(self, rep: int = 0, field: int = FIELD_C):
+        r = self.reps[rep]
+        shape = (r.Lz, r.Lx // 2 + 1)
+        a2, re, im = np.empty(shape), np.empty(shape), np.empty(shape)
+        n = ctypes.c_int64()
+        _check(self._lib.fnlb_read_structure_factor(self._h, rep, field, _dp(a2), _dp(re),
+                                                    _dp(im), ctypes.byref(n)),
+               "fnlb_read_structure_factor")
+        return a2, re, im, int(n.value)
+
+    def structure_factor(self, rep: int = 0, field: int = FIELD_C) -> np.ndarray:
+        """S(q) = mean |Phi|^2 - |mean Phi|^2, shape [Lz][Lx//2+1]."""
+        a2, re, im, n = self.read_structure_factor(rep, field)
+        n = max(n, 1)
+        return a2 / n - ((re / n) ** 2 + (im / n) ** 2)
+
+    def read_pressure(self, rep: int = 0):
+        r = self.reps[rep]
+        s, s2 = ctypes.c_double(), ctypes.c_double()
+        prof = np.empty(r.Lz)
+        n = ctypes.c_int64()
+        _check(self._lib.fnlb_read_pressure(self._h, rep, ctypes.byref(s), ctypes.byref(s2),
+                                            _dp(prof), ctypes.byref(n)), "fnlb_read_pressure")
+        return s.value, s2.value, prof, int(n.value)
+
+    def read_populations(self, rep: int = 0) -> np.ndarray:
+        r = self.reps[rep]
+        out = np.empty((2, 9, r.Lz, r.Lx))
+        _check(self._lib.fnlb_read_populations(self._h, rep, _dp(out)), "fnlb_read_populations")
+        return out
+
+    def write_populations(self, rep: int, f: np.ndarray) -> None:
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        r = self.reps[rep]
+        assert f.shape == (2, 9, r.Lz, r.Lx)
+        _check(self._lib.fnlb_write_populations(self._h, rep, _dp(f)), "fnlb_write_populations")
+
+    def reset_accumulators(self) -> None:
+        _check(self._lib.fnlb_reset_accumulators(self._h), "fnlb_reset_accumulators")
+
+    @property
+    def time(self) -> int:
+        t = ctypes.c_int64()
+        _check(self._lib.fnlb_get_time(self._h, ctypes.byref(t)), "fnlb_get_time")
+        return int(t.value)
+
+    @time.setter
+    def time(self, t: int) -> None:
+        _check(self._lib.fnlb_set_time(self._h, int(t)), "fnlb_set_time")

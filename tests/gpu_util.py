@@ -1,0 +1,74 @@
+"""Helpers of the GPU parity tests: run the same seeded replicas through the
+HIP library and through the CPU oracle, and compare them with the norms of
+the parity contract (relative to the size of the fluctuating part)."""
+import sys
+
+import numpy as np
+
+from oracle import oracle as O
+
+
+def say(msg: str) -> None:
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_flags(flags: int) -> int:
+    return flags  # the bit values coincide (each side defines its own copy)
+
+
+def run_oracle(rep, nsteps, every=0, flags=None, f0=None, t0=0, sample_at_end=False):
+    flags = O.DEFAULT_FLAGS if flags is None else flags
+    f = O.init_state(rep) if f0 is None else f0.copy()
+    acc = O.Accum(rep.Lx, rep.Lz)
+    O.run(rep, f, t0, nsteps, acc, flags=flags, sample_every=every)
+    if sample_at_end:
+        O.sample(rep, f, acc, flags=flags)
+    return f, acc
+
+
+def dev_norm(f_gpu, f_ora, rep):
+    """max |d_gpu - d_ora| / max |d_ora| with d = f - f(rest on the imposed profile)."""
+    ref = O.init_state(rep)
+    d_o = f_ora - ref
+    d_g = f_gpu - ref
+    scale = np.abs(d_o).max()
+    return np.abs(d_g - d_o).max() / scale if scale > 0 else np.abs(d_g - d_o).max()
+
+
+def sq_norm(S_gpu, S_ora):
+    """max_q |S_gpu - S_ora| / mean_q S_ora."""
+    return np.abs(S_gpu - S_ora).max() / np.abs(S_ora).mean()
+
+
+def sq_from_sums(a2, re, im, n):
+    n = max(n, 1)
+    return a2 / n - ((re / n) ** 2 + (im / n) ** 2)
+
+
+def compare_observables(lat, acc, rep_index, rep, tol):
+    """Structure factors (both fields) and pressure sums against the oracle."""
+    out = {}
+    for fld in range(2):
+        a2, re, im, n = lat.read_structure_factor(rep_index, fld)
+        assert n == acc.n_samples, (n, acc.n_samples)
+        if n == 0:
+            continue
+        S_g = sq_from_sums(a2, re, im, n)
+        S_o = sq_from_sums(acc.sq[fld, 0], acc.sq[fld, 1], acc.sq[fld, 2], n)
+        # S(q) norm of the parity contract (needs fluctuations and >= 2 samples)
+        if rep.kT > 0 and n >= 2:
+            out[f"S{fld}"] = sq_norm(S_g, S_o)
+        # raw sums: max-norm relative to the largest entry
+        out[f"abs2_{fld}"] = np.abs(a2 - acc.sq[fld, 0]).max() / np.abs(acc.sq[fld, 0]).max()
+        scale_c = max(np.abs(acc.sq[fld, 1]).max(), np.abs(acc.sq[fld, 2]).max())
+        out[f"re_{fld}"] = np.abs(re - acc.sq[fld, 1]).max() / scale_c
+        out[f"im_{fld}"] = np.abs(im - acc.sq[fld, 2]).max() / scale_c
+    s, s2, prof, n = lat.read_pressure(rep_index)
+    if n:
+        scale = np.abs(acc.prof).max()
+        out["P_prof"] = np.abs(prof - acc.prof).max() / scale
+        out["P_sum"] = abs(s - acc.pr[0]) / scale
+    for k, v in out.items():
+        assert v <= tol, f"{k}: {v:.3e} > {tol:.1e}"
+    return out
