@@ -16,6 +16,10 @@ struct Philox4 {
   uint32_t v[4];
 };
 
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);  // truth table of a ^ b ^ c
+}
+
 __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
                                                   uint32_t c3, uint32_t k0, uint32_t k1) {
   constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
@@ -24,8 +28,8 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
   for (int round = 0; round < 10; ++round) {
     const uint64_t pa = (uint64_t)kMulA * c0;
     const uint64_t pb = (uint64_t)kMulB * c2;
-    const uint32_t y0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-    const uint32_t y2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+    const uint32_t y0 = xor3((uint32_t)(pb >> 32), c1, k0);
+    const uint32_t y2 = xor3((uint32_t)(pa >> 32), c3, k1);
     c1 = (uint32_t)pb;
     c3 = (uint32_t)pa;
     c0 = y0;
@@ -62,24 +66,29 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& g0,
   g1 = r * s;
 }
 
-// FP32 form.  ln u_a is taken through log1p(-(1 - u_a)) when u_a >= 1/2, where
-// 1 - u_a = (~w + 1/2) 2^-32 is exact before rounding; this keeps the radius
-// relatively accurate as u_a -> 1.
+// FP32 form on the hardware transcendentals (v_log_f32 = log2, v_sqrt_f32,
+// v_sin_f32 / v_cos_f32 taking the angle in turns).  -2 ln u_a uses the
+// hardware log2 of the rounded u_a for u_a < 15/16; above, where rounding u_a
+// to FP32 would lose the small distance to 1, it uses the series
+// -ln(1 - v) = v + v^2/2 + ... + v^6/6 (truncation below 1e-8 relative for
+// v <= 1/16) in v = 1 - u_a = (~w + 1/2) 2^-32, which FP32 holds to full
+// relative precision.  The angle 2 pi u_b is written as pi + 2 pi x with
+// x = u_b - 1/2 in (-1/2, 1/2).
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& g0, float& g1) {
-  float ln_u;
-  if (wa & 0x80000000u) {
-    const float v = ((float)(~wa) + 0.5f) * 0x1.0p-32f;
-    ln_u = log1pf(-v);
-  } else {
-    const float u = ((float)wa + 0.5f) * 0x1.0p-32f;
-    ln_u = logf(u);
-  }
-  const float r = __builtin_sqrtf(-2.0f * ln_u);
-  const float ub = ((float)wb + 0.5f) * 0x1.0p-32f;
-  float s, c;
-  sincospif(2.0f * ub, &s, &c);
-  g0 = r * c;
-  g1 = r * s;
+  constexpr float kMinus2Ln2 = -1.3862943611198906f;
+  const float u = fmaf((float)wa, 0x1.0p-32f, 0x1.0p-33f);
+  const float nl_log = kMinus2Ln2 * __builtin_amdgcn_logf(u);
+  const float v = fmaf((float)(~wa), 0x1.0p-32f, 0x1.0p-33f);
+  float p = fmaf(v, 1.0f / 6.0f, 0.2f);
+  p = fmaf(v, p, 0.25f);
+  p = fmaf(v, p, 1.0f / 3.0f);
+  p = fmaf(v, p, 0.5f);
+  p = fmaf(v, p, 1.0f);
+  const float nl_ser = 2.0f * v * p;
+  const float r = __builtin_amdgcn_sqrtf(wa >= 0xF0000000u ? nl_ser : nl_log);
+  const float x = fmaf((float)(int)(wb ^ 0x80000000u), 0x1.0p-32f, 0x1.0p-33f);
+  g0 = -r * __builtin_amdgcn_cosf(x);
+  g1 = -r * __builtin_amdgcn_sinf(x);
 }
 
 // Wavefront lane shifts through DPP: lane i receives lane i-1 (from_left) or

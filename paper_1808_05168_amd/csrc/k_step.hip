@@ -32,22 +32,46 @@
 namespace fnlb {
 namespace {
 
-template <typename Store, typename Real>
-__device__ __forceinline__ Real ld(const Store* p) {
-  return (Real)__builtin_nontemporal_load(p);
+// Addressing: populations are read and written with buffer instructions on
+// one descriptor per replica state block; the plane offset is a scalar and
+// the lane offset a 32-bit byte offset, so no per-lane 64-bit address math is
+// needed.  Dword 3 of the descriptor is the gfx9-family raw-buffer format.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           kRsrcWord3);
 }
 
 template <typename Store>
-__device__ __forceinline__ void st(Store* p, Store v) {
-  __builtin_nontemporal_store(v, p);
+__device__ __forceinline__ Store bload(Rsrc r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float bload<float>(Rsrc r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(Rsrc r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+template <typename Store>
+__device__ __forceinline__ void bstore(Rsrc r, uint32_t voff, uint32_t soff, Store v);
+template <>
+__device__ __forceinline__ void bstore<float>(Rsrc r, uint32_t voff, uint32_t soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+}
+template <>
+__device__ __forceinline__ void bstore<double>(Rsrc r, uint32_t voff, uint32_t soff, double v) {
+  using u2 = __attribute__((ext_vector_type(2))) uint32_t;
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
 }
 
 // Rows are loaded as 18 raw values: species A links 0..8 then species B.
 template <typename Store>
-__device__ __forceinline__ void load_row(const Store* base, int64_t plane, int64_t row_off,
-                                         Store (&o)[18]) {
+__device__ __forceinline__ void load_row(Rsrc r, uint32_t plane_b, uint32_t off, Store (&o)[18]) {
 #pragma unroll
-  for (int q = 0; q < 18; ++q) o[q] = __builtin_nontemporal_load(base + q * plane + row_off);
+  for (int q = 0; q < 18; ++q) o[q] = bload<Store>(r, off, (uint32_t)q * plane_b);
 }
 
 template <typename DT, typename Store>
@@ -82,8 +106,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   const int Lx = R.Lx, Lz = R.Lz;
   const int64_t plane = R.plane;
   const int pitch = R.pitch;
-  const Store* __restrict__ in = (const Store*)a.state_in + R.state_off;
-  Store* __restrict__ out = (Store*)a.state_out + R.state_off;
+  constexpr uint32_t SB = sizeof(Store);
+  const uint32_t plane_b = (uint32_t)(plane * SB);
+  const Rsrc in = make_rsrc((const char*)a.state_in + R.state_off * SB, 18u * plane_b);
+  const Rsrc out = make_rsrc((char*)a.state_out + R.state_off * SB, 18u * plane_b);
+  const uint32_t row_b = (uint32_t)pitch * SB;
   const int flags = R.flags;
 
   // columns: lane 0 = strip*62 - 1, ..., wrapped periodically
@@ -95,6 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   if (xe == Lx) xe = 0;
   int xw = xs - 1;
   if (xw < 0) xw = Lx - 1;
+  const uint32_t xs_b = (uint32_t)xs * SB, xe_b = (uint32_t)xe * SB, xw_b = (uint32_t)xw * SB;
 
   const int64_t t = *a.t_base + a.t_off;
   const uint32_t k0 = R.seed_lo, k1 = R.seed_hi;
@@ -116,11 +144,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   // rolling densities (deviations) of rows j-1 (m), j (c), j+1 (p)
   DT dAm, dBm, dAc, dBc, dAp, dBp;
   Store cur[18], nxt[18];
-  load_row(in, plane, (int64_t)j0 * pitch + xs, cur);
+  load_row(in, plane_b, (uint32_t)j0 * row_b + xs_b, cur);
   row_density<DT>(cur, dAc, dBc);
   if (j0 > 0) {
     Store tmp[18];
-    load_row(in, plane, (int64_t)(j0 - 1) * pitch + xs, tmp);
+    load_row(in, plane_b, (uint32_t)(j0 - 1) * row_b + xs_b, tmp);
     row_density<DT>(tmp, dAm, dBm);
   } else {
     dAm = dAc;
@@ -129,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
 
   for (int j = j0; j < j1; ++j) {
     const bool top = (j == Lz - 1), bot = (j == 0);
-    if (!top) load_row(in, plane, (int64_t)(j + 1) * pitch + xs, nxt);
+    if (!top) load_row(in, plane_b, (uint32_t)(j + 1) * row_b + xs_b, nxt);
 
     // thermal noise of this node: 14 standard normals (independent of loads)
     Real g[14];
@@ -328,30 +356,30 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
 
       // streaming (push) with mid-way bounce-back
       if (upd) {
-        const int64_t rj = (int64_t)j * pitch;
-        const int64_t ru = rj + pitch, rd = rj - pitch;
+        const uint32_t rj = (uint32_t)j * row_b;
+        const uint32_t ru = rj + row_b, rd = rj - row_b;
         auto emit = [&](int s, const Real (&d)[9], Real sh1, Real sh5) {
-          Store* o = out + (int64_t)(9 * s) * plane;
-          st(o + 0 * plane + rj + xs, (Store)d[0]);
-          st(o + 1 * plane + rj + xe, (Store)d[1]);
-          st(o + 3 * plane + rj + xw, (Store)d[3]);
+          const uint32_t o = (uint32_t)(9 * s) * plane_b;
+          bstore<Store>(out, rj + xs_b, o + 0 * plane_b, (Store)d[0]);
+          bstore<Store>(out, rj + xe_b, o + 1 * plane_b, (Store)d[1]);
+          bstore<Store>(out, rj + xw_b, o + 3 * plane_b, (Store)d[3]);
           if (!top) {
-            st(o + 2 * plane + ru + xs, (Store)(d[2] + sh1));
-            st(o + 5 * plane + ru + xe, (Store)(d[5] + sh5));
-            st(o + 6 * plane + ru + xw, (Store)(d[6] + sh5));
+            bstore<Store>(out, ru + xs_b, o + 2 * plane_b, (Store)(d[2] + sh1));
+            bstore<Store>(out, ru + xe_b, o + 5 * plane_b, (Store)(d[5] + sh5));
+            bstore<Store>(out, ru + xw_b, o + 6 * plane_b, (Store)(d[6] + sh5));
           } else {
-            st(o + 4 * plane + rj + xs, (Store)d[2]);
-            st(o + 7 * plane + rj + xs, (Store)d[5]);
-            st(o + 8 * plane + rj + xs, (Store)d[6]);
+            bstore<Store>(out, rj + xs_b, o + 4 * plane_b, (Store)d[2]);
+            bstore<Store>(out, rj + xs_b, o + 7 * plane_b, (Store)d[5]);
+            bstore<Store>(out, rj + xs_b, o + 8 * plane_b, (Store)d[6]);
           }
           if (!bot) {
-            st(o + 4 * plane + rd + xs, (Store)(d[4] - sh1));
-            st(o + 7 * plane + rd + xw, (Store)(d[7] - sh5));
-            st(o + 8 * plane + rd + xe, (Store)(d[8] - sh5));
+            bstore<Store>(out, rd + xs_b, o + 4 * plane_b, (Store)(d[4] - sh1));
+            bstore<Store>(out, rd + xw_b, o + 7 * plane_b, (Store)(d[7] - sh5));
+            bstore<Store>(out, rd + xe_b, o + 8 * plane_b, (Store)(d[8] - sh5));
           } else {
-            st(o + 2 * plane + rj + xs, (Store)d[4]);
-            st(o + 5 * plane + rj + xs, (Store)d[7]);
-            st(o + 6 * plane + rj + xs, (Store)d[8]);
+            bstore<Store>(out, rj + xs_b, o + 2 * plane_b, (Store)d[4]);
+            bstore<Store>(out, rj + xs_b, o + 5 * plane_b, (Store)d[7]);
+            bstore<Store>(out, rj + xs_b, o + 6 * plane_b, (Store)d[8]);
           }
         };
         emit(0, dA, shA1, shA5);
