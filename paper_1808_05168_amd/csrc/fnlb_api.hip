@@ -65,11 +65,11 @@ struct Plan {
 };
 
 int auto_chunk(const fnlb_replica_params* reps, int n_rep) {
-  int64_t strip_rows = 0;
+  int64_t seg_rows = 0;
   for (int r = 0; r < n_rep; ++r)
-    strip_rows += (int64_t)((reps[r].Lx + kStrip - 1) / kStrip) * reps[r].Lz;
-  // aim for about 2048 wavefronts (8 per compute unit) when the lattice allows
-  int64_t c = strip_rows / 2048;
+    seg_rows += (int64_t)((reps[r].Lx + kSeg - 1) / kSeg) * reps[r].Lz;
+  // aim for about 1024 blocks (four per compute unit) when the lattice allows
+  const int64_t c = seg_rows / 1024;
   int chunk = 4;
   while (chunk * 2 <= c && chunk < 64) chunk *= 2;
   return chunk;
@@ -86,8 +86,8 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
     RepInfo& R = P.info[r];
     R.Lx = p.Lx;
     R.Lz = p.Lz;
-    R.pitch = p.Lx;
-    R.nstrips = (p.Lx + kStrip - 1) / kStrip;
+    R.pitch = (p.Lx + kRowAlign - 1) / kRowAlign * kRowAlign;
+    R.nstrips = (p.Lx + kWave - 1) / kWave;
     R.plane = ((int64_t)p.Lz * R.pitch + elem_align - 1) / elem_align * elem_align;
     R.state_off = state_elems;
     state_elems += 18 * R.plane;
@@ -141,12 +141,13 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
     P.max_lx = std::max(P.max_lx, p.Lx);
     P.max_lz = std::max(P.max_lz, p.Lz);
   }
-  // work items: (replica, strip, row range)
+  // work items: (replica, row range, segment), neighbouring segments adjacent
   P.items.clear();
   for (int r = 0; r < n_rep; ++r) {
     const RepInfo& R = P.info[r];
-    for (int s = 0; s < R.nstrips; ++s)
-      for (int j0 = 0; j0 < R.Lz; j0 += P.chunk)
+    const int nseg = (R.Lx + kSeg - 1) / kSeg;
+    for (int j0 = 0; j0 < R.Lz; j0 += P.chunk)
+      for (int s = 0; s < nseg; ++s)
         P.items.push_back(Item{r, s, j0, std::min(R.Lz, j0 + P.chunk)});
   }
   // rows and column tiles of the transforms
@@ -232,8 +233,7 @@ StepArgs step_args(fnlb_handle* h, int64_t t_off) {
   a.reps = h->d_reps();
   a.items = h->d_items();
   a.n_items = (int)h->plan.items.size();
-  int nb = (a.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
-  nb = (nb + 7) / 8 * 8;
+  const int nb = (a.n_items + 7) / 8 * 8;
   a.n_blocks = nb;
   a.state_in = h->state_copy(h->cur);
   a.state_out = h->state_copy(1 - h->cur);
@@ -269,6 +269,22 @@ int check_watchdog(fnlb_handle* h) {
 
 const double kW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                       1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+const int kCX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+const int kCZ[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+const int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+// Where f_l(x, j) of the current state is stored: link l of node
+// (x - c_lx, j - c_lz), or link opp(l) of (x, j) itself when that source lies
+// beyond a wall (mid-way bounce-back).  Returns the element index inside one
+// species block of the stored planes (plane stride `plane`, row pitch).
+size_t pull_source(const RepInfo& R, int l, int j, int x) {
+  const int js = j - kCZ[l];
+  if (js < 0 || js >= R.Lz) return (size_t)kOpp[l] * R.plane + (size_t)j * R.pitch + x;
+  int xs = x - kCX[l];
+  if (xs < 0) xs += R.Lx;
+  if (xs >= R.Lx) xs -= R.Lx;
+  return (size_t)l * R.plane + (size_t)js * R.pitch + xs;
+}
 
 }  // namespace
 
@@ -404,25 +420,23 @@ int fnlb_read_populations(fnlb_handle* h, int32_t rep, double* out) {
   if (h->error) return h->error;
   const RepInfo& R = h->plan.info[rep];
   const size_t ss = h->plan.store_size;
-  const size_t n = (size_t)R.Lz * R.Lx;
-  std::vector<char> raw(18 * n * ss);
+  const size_t block = 18 * (size_t)R.plane;
+  std::vector<char> raw(block * ss);
   const char* src = h->state_copy(h->cur) + (size_t)R.state_off * ss;
-  hipError_t e = hipSuccess;
-  for (int q = 0; q < 18 && e == hipSuccess; ++q)
-    e = hipMemcpy2DAsync(raw.data() + q * n * ss, (size_t)R.Lx * ss,
-                         src + (size_t)q * R.plane * ss, (size_t)R.pitch * ss, (size_t)R.Lx * ss,
-                         (size_t)R.Lz, hipMemcpyDeviceToHost, h->stream);
+  hipError_t e = hipMemcpyAsync(raw.data(), src, raw.size(), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return dev_err(h, e);
+  const size_t n = (size_t)R.Lz * R.Lx;
   for (int s = 0; s < 2; ++s)
     for (int l = 0; l < 9; ++l)
       for (int j = 0; j < R.Lz; ++j) {
         const double rA = R.rA_mid + R.rA_step * j;
         const double ref = kW[l] * (s == 0 ? rA : R.rho0 - rA);
         for (int x = 0; x < R.Lx; ++x) {
-          const size_t k = (size_t)(s * 9 + l) * n + (size_t)j * R.Lx + x;
-          const double d = ss == 8 ? ((const double*)raw.data())[k] : (double)((const float*)raw.data())[k];
-          out[k] = ref + d;
+          const size_t k = (size_t)s * 9 * R.plane + pull_source(R, l, j, x);
+          const double d = ss == 8 ? ((const double*)raw.data())[k]
+                                   : (double)((const float*)raw.data())[k];
+          out[(size_t)(s * 9 + l) * n + (size_t)j * R.Lx + x] = ref + d;
         }
       }
   return FNLB_OK;
@@ -433,16 +447,17 @@ int fnlb_write_populations(fnlb_handle* h, int32_t rep, const double* in) {
   if (h->error) return h->error;
   const RepInfo& R = h->plan.info[rep];
   const size_t ss = h->plan.store_size;
+  const size_t block = 18 * (size_t)R.plane;
+  std::vector<char> raw(block * ss, 0);
   const size_t n = (size_t)R.Lz * R.Lx;
-  std::vector<char> raw(18 * n * ss);
   for (int s = 0; s < 2; ++s)
     for (int l = 0; l < 9; ++l)
       for (int j = 0; j < R.Lz; ++j) {
         const double rA = R.rA_mid + R.rA_step * j;
         const double ref = kW[l] * (s == 0 ? rA : R.rho0 - rA);
         for (int x = 0; x < R.Lx; ++x) {
-          const size_t k = (size_t)(s * 9 + l) * n + (size_t)j * R.Lx + x;
-          const double d = in[k] - ref;
+          const size_t k = (size_t)s * 9 * R.plane + pull_source(R, l, j, x);
+          const double d = in[(size_t)(s * 9 + l) * n + (size_t)j * R.Lx + x] - ref;
           if (ss == 8)
             ((double*)raw.data())[k] = d;
           else
@@ -450,11 +465,7 @@ int fnlb_write_populations(fnlb_handle* h, int32_t rep, const double* in) {
         }
       }
   char* dst = h->state_copy(h->cur) + (size_t)R.state_off * ss;
-  hipError_t e = hipSuccess;
-  for (int q = 0; q < 18 && e == hipSuccess; ++q)
-    e = hipMemcpy2DAsync(dst + (size_t)q * R.plane * ss, (size_t)R.pitch * ss,
-                         raw.data() + q * n * ss, (size_t)R.Lx * ss, (size_t)R.Lx * ss,
-                         (size_t)R.Lz, hipMemcpyHostToDevice, h->stream);
+  hipError_t e = hipMemcpyAsync(dst, raw.data(), raw.size(), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   return dev_err(h, e);
 }

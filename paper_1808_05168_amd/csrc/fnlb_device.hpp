@@ -40,20 +40,6 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
   return Philox4{{c0, c1, c2, c3}};
 }
 
-// The 16 words of one node and one step: counter (node, t_lo, t_hi, call) for
-// call = 0..3, key (seed_lo, seed_hi).
-__device__ __forceinline__ void node_words(uint32_t node, uint64_t t, uint32_t k0,
-                                           uint32_t k1, uint32_t w[16]) {
-#pragma unroll
-  for (uint32_t call = 0; call < 4; ++call) {
-    const Philox4 r = philox4x32_10(node, (uint32_t)t, (uint32_t)(t >> 32), call, k0, k1);
-    w[4 * call + 0] = r.v[0];
-    w[4 * call + 1] = r.v[1];
-    w[4 * call + 2] = r.v[2];
-    w[4 * call + 3] = r.v[3];
-  }
-}
-
 // Box-Muller (Box and Muller 1958) on u = (w + 1/2) 2^-32:
 // g0 = sqrt(-2 ln u_a) cos(2 pi u_b), g1 = sqrt(-2 ln u_a) sin(2 pi u_b).
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& g0, double& g1) {
@@ -89,6 +75,23 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& g0, 
   const float x = fmaf((float)(int)(wb ^ 0x80000000u), 0x1.0p-32f, 0x1.0p-33f);
   g0 = -r * __builtin_amdgcn_cosf(x);
   g1 = -r * __builtin_amdgcn_sinf(x);
+}
+
+// Words 4 call .. 4 call + 3 of one node and one step: counter
+// (node, t_lo, t_hi, call), key (seed_lo, seed_hi).  A node uses calls 0..3.
+__device__ __forceinline__ Philox4 node_call(uint32_t node, uint64_t t, uint32_t call,
+                                             uint32_t k0, uint32_t k1) {
+  return philox4x32_10(node, (uint32_t)t, (uint32_t)(t >> 32), call, k0, k1);
+}
+
+// The standard normals g_{4c}, ..., g_{4c+3} (Box-Muller on the word pairs of
+// call c); g_14 and g_15 of call 3 are not used by the step.
+template <typename Real>
+__device__ __forceinline__ void node_normals(uint32_t node, uint64_t t, uint32_t call,
+                                             uint32_t k0, uint32_t k1, Real (&g)[4]) {
+  const Philox4 r = node_call(node, t, call, k0, k1);
+  box_muller(r.v[0], r.v[1], g[0], g[1]);
+  box_muller(r.v[2], r.v[3], g[2], g[3]);
 }
 
 // Wavefront lane shifts through DPP: lane i receives lane i-1 (from_left) or

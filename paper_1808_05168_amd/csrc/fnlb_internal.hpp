@@ -10,20 +10,22 @@
 
 namespace fnlb {
 
-// Width of the x-strip one wavefront updates: 64 lanes load 64 consecutive
-// columns, the two edge lanes only supply the x-neighbour densities of the
-// non-local force, so 62 columns per strip are updated.
+// A block of four wavefronts updates a segment of 256 consecutive columns of
+// one row range; pressure partials are kept per 64-column strip (one per
+// wavefront).  Rows are padded to 64 elements so every segment starts on a
+// cache-line boundary.
 constexpr int kWave = 64;
-constexpr int kStrip = kWave - 2;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kSeg = kBlock;
+constexpr int kRowAlign = 64;
 
 // Everything a kernel needs about one replica.  Filled on the host, copied to
 // the work buffer once at init, read by the kernels with scalar loads.
 struct alignas(256) RepInfo {
   int32_t Lx, Lz;         // lattice size
   int32_t pitch;          // elements per row of a population plane (>= Lx)
-  int32_t nstrips;        // ceil(Lx / kStrip)
+  int32_t nstrips;        // ceil(Lx / 64): pressure partials per row
   int64_t plane;          // elements per (species, link) plane
   int64_t state_off;      // element offset of this replica in one state copy
   int64_t field_off;      // double offset of the sample fields [2][Lz][Lx]
@@ -49,9 +51,9 @@ struct alignas(256) RepInfo {
   double inv_norm;        // 1 / sqrt(Lx Lz)
 };
 
-// One wavefront's work: replica, x-strip and a range of rows.
+// One block's work: replica, 256-column segment and a range of rows.
 struct Item {
-  int32_t rep, strip, j0, j1;
+  int32_t rep, strip, j0, j1;  // strip = segment index
 };
 
 // A row of one replica (row transform of the structure factor).

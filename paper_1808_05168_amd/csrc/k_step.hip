@@ -11,18 +11,25 @@
 // (1 - lambda_d/2) and the higher ones are Guo's (each with 1 - lambda_a/2),
 // the reading that makes the imposed linear profile an exact fixed point.
 //
-// Layout and mapping.  Populations are stored structure-of-arrays, one plane
-// per (species, link), x fastest, as deviations d_l = f_l - w_l rho_ref^S(z)
-// from the imposed profile rho_ref^A = rho_bar c_0(z), rho_ref^B = rho_bar
-// (1 - c_0(z)).  A wavefront owns a strip of 64 consecutive columns and
-// marches up a range of rows: lanes 1..62 are updated, lanes 0 and 63 only
-// supply the x-neighbour densities of the force stencil, exchanged with DPP
-// lane shifts; densities of the rows below and above stay in registers, so
-// each population is read once per step (plus the two halo lanes and one halo
-// row at each end of the row range).  Streaming is a push: post-collision
-// populations go straight to their destination node of the other state copy.
-// In deviation form, a population that changes row picks up the constant
-// shift w_l (rho_ref(z) - rho_ref(z + c_lz)).
+// Layout.  Populations are stored structure-of-arrays, one plane per
+// (species, link), x fastest, rows padded to 64 elements.  What is stored at
+// node r for link l is the post-collision population of r (streaming is a
+// pull: the next step reads link l of node r from r - c_l, or from the
+// opposite link of r itself where c_l leaves through a wall, which is mid-way
+// bounce-back).  Values are deviations from w_l rho_ref^S(z_dest) of the row
+// they stream to, with rho_ref^A = rho_bar c_0(z), rho_ref^B = rho_bar
+// (1 - c_0(z)); the writer adds the constant w_l (rho_ref(z) - rho_ref(z +
+// c_lz)) for links that change row.  The state of rest on the imposed profile
+// is all zeros.
+//
+// Mapping.  A block of four wavefronts owns a 256-column segment of one row
+// range and marches up the rows.  Every lane pulls its node's 18 populations
+// of the next row, sums its densities into a four-row ring in LDS (plus the
+// two segment-edge columns, pulled by 36 lanes of the first wavefront with one
+// load, or wrapped when the segment is a whole periodic row), and after one
+// barrier per row reads the eight neighbour densities of the non-local force
+// from LDS.  Stores are the node's own 18 post-collision values: full,
+// aligned cache lines.
 #include "fnlb.h"
 #include "fnlb_device.hpp"
 #include "fnlb_internal.hpp"
@@ -32,10 +39,10 @@
 namespace fnlb {
 namespace {
 
-// Addressing: populations are read and written with buffer instructions on
-// one descriptor per replica state block; the plane offset is a scalar and
-// the lane offset a 32-bit byte offset, so no per-lane 64-bit address math is
-// needed.  Dword 3 of the descriptor is the gfx9-family raw-buffer format.
+// Populations are read and written with buffer instructions on one
+// descriptor per replica state block; the plane offset is a scalar and the
+// lane offset a 32-bit byte offset.  Dword 3 of the descriptor is the
+// gfx9-family raw-buffer format.
 using Rsrc = __amdgpu_buffer_rsrc_t;
 constexpr int kRsrcWord3 = 0x00020000;
 
@@ -67,15 +74,44 @@ __device__ __forceinline__ void bstore<double>(Rsrc r, uint32_t voff, uint32_t s
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
 }
 
-// Rows are loaded as 18 raw values: species A links 0..8 then species B.
+// Pull of the 18 populations f_l(x, jr) of one node: link l comes from
+// (x - c_lx, jr - c_lz), or, where that lies beyond a wall, from link opp(l)
+// of the node itself.  xb, xmb, xpb: byte offsets of columns x, x-1, x+1.
 template <typename Store>
-__device__ __forceinline__ void load_row(Rsrc r, uint32_t plane_b, uint32_t off, Store (&o)[18]) {
+__device__ __forceinline__ void load_pulled(Rsrc r, uint32_t plane_b, uint32_t row_b, int jr,
+                                            int Lz, uint32_t xb, uint32_t xmb, uint32_t xpb,
+                                            Store (&o)[18]) {
+  const uint32_t r0 = (uint32_t)jr * row_b;
+  const uint32_t rdn = r0 - row_b, rup = r0 + row_b;
 #pragma unroll
-  for (int q = 0; q < 18; ++q) o[q] = bload<Store>(r, off, (uint32_t)q * plane_b);
+  for (int s = 0; s < 2; ++s) {
+    const uint32_t p = (uint32_t)(9 * s) * plane_b;
+    o[9 * s + 0] = bload<Store>(r, r0 + xb, p);
+    o[9 * s + 1] = bload<Store>(r, r0 + xmb, p + plane_b);
+    o[9 * s + 3] = bload<Store>(r, r0 + xpb, p + 3 * plane_b);
+    if (jr > 0) {
+      o[9 * s + 2] = bload<Store>(r, rdn + xb, p + 2 * plane_b);
+      o[9 * s + 5] = bload<Store>(r, rdn + xmb, p + 5 * plane_b);
+      o[9 * s + 6] = bload<Store>(r, rdn + xpb, p + 6 * plane_b);
+    } else {
+      o[9 * s + 2] = bload<Store>(r, r0 + xb, p + 4 * plane_b);
+      o[9 * s + 5] = bload<Store>(r, r0 + xb, p + 7 * plane_b);
+      o[9 * s + 6] = bload<Store>(r, r0 + xb, p + 8 * plane_b);
+    }
+    if (jr < Lz - 1) {
+      o[9 * s + 4] = bload<Store>(r, rup + xb, p + 4 * plane_b);
+      o[9 * s + 7] = bload<Store>(r, rup + xpb, p + 7 * plane_b);
+      o[9 * s + 8] = bload<Store>(r, rup + xmb, p + 8 * plane_b);
+    } else {
+      o[9 * s + 4] = bload<Store>(r, r0 + xb, p + 2 * plane_b);
+      o[9 * s + 7] = bload<Store>(r, r0 + xb, p + 5 * plane_b);
+      o[9 * s + 8] = bload<Store>(r, r0 + xb, p + 6 * plane_b);
+    }
+  }
 }
 
 template <typename DT, typename Store>
-__device__ __forceinline__ void row_density(const Store (&o)[18], DT& da, DT& db) {
+__device__ __forceinline__ void density(const Store (&o)[18], DT& da, DT& db) {
   DT a = (DT)o[0], b = (DT)o[9];
 #pragma unroll
   for (int l = 1; l < 9; ++l) {
@@ -86,43 +122,124 @@ __device__ __forceinline__ void row_density(const Store (&o)[18], DT& da, DT& db
   db = b;
 }
 
+// density deviations of one column pulled at row jr (segment-edge column)
+template <typename DT, typename Store>
+__device__ __forceinline__ void edge_density(Rsrc r, uint32_t plane_b, uint32_t row_b, int jr,
+                                             int Lz, int Lx, int col, DT& da, DT& db) {
+  constexpr uint32_t SB = sizeof(Store);
+  const int cm = col == 0 ? Lx - 1 : col - 1, cp = col == Lx - 1 ? 0 : col + 1;
+  Store o[18];
+  load_pulled(r, plane_b, row_b, jr, Lz, (uint32_t)col * SB, (uint32_t)cm * SB,
+              (uint32_t)cp * SB, o);
+  density<DT>(o, da, db);
+}
+
 template <typename Real, typename Store, int MODE>
 __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   using DT = typename std::conditional<MODE == kStep, Real, double>::type;
+  constexpr int kRow = kSeg + 2;
+  __shared__ DT ring[4][2][kRow];  // density deviations: row slot, species, column + 1
+  __shared__ DT edge[2][36];       // pulled populations of the two edge columns
 
   // XCD-aware block order: consecutive hardware blocks go to different XCDs,
-  // so give each XCD a contiguous range of work items (neighbouring strips and
-  // row ranges share halo data in that XCD's L2).
+  // so give each XCD a contiguous range of work items (neighbouring segments
+  // of the same rows share their edge columns in that XCD's L2).
   const int nb = a.n_blocks;
   const int b = blockIdx.x;
   const int per_xcd = nb >> 3;
   const int blk = (b & 7) * per_xcd + (b >> 3);
-  const int wave = blk * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (wave >= a.n_items) return;
-  const int lane = threadIdx.x & (kWave - 1);
+  if (blk >= a.n_items) return;  // whole block: no barrier is skipped by part of it
 
-  const Item it = a.items[wave];
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const Item it = a.items[blk];
   const RepInfo& R = a.reps[it.rep];
   const int Lx = R.Lx, Lz = R.Lz;
-  const int64_t plane = R.plane;
-  const int pitch = R.pitch;
   constexpr uint32_t SB = sizeof(Store);
-  const uint32_t plane_b = (uint32_t)(plane * SB);
+  const uint32_t plane_b = (uint32_t)(R.plane * SB);
+  const uint32_t row_b = (uint32_t)R.pitch * SB;
   const Rsrc in = make_rsrc((const char*)a.state_in + R.state_off * SB, 18u * plane_b);
   const Rsrc out = make_rsrc((char*)a.state_out + R.state_off * SB, 18u * plane_b);
-  const uint32_t row_b = (uint32_t)pitch * SB;
   const int flags = R.flags;
 
-  // columns: lane 0 = strip*62 - 1, ..., wrapped periodically
-  const int xc = it.strip * kStrip + lane - 1;
-  int xs = xc % Lx;
-  if (xs < 0) xs += Lx;
-  const bool upd = lane >= 1 && lane <= kStrip && xc < Lx;
-  int xe = xs + 1;
-  if (xe == Lx) xe = 0;
-  int xw = xs - 1;
-  if (xw < 0) xw = Lx - 1;
-  const uint32_t xs_b = (uint32_t)xs * SB, xe_b = (uint32_t)xe * SB, xw_b = (uint32_t)xw * SB;
+  // columns of this segment
+  const int X0 = it.strip * kSeg;
+  const int width = min(kSeg, Lx - X0);
+  const bool act = tid < width;
+  const int x = act ? X0 + tid : X0;
+  const int xm = x == 0 ? Lx - 1 : x - 1, xp = x == Lx - 1 ? 0 : x + 1;
+  const uint32_t xb = (uint32_t)x * SB, xmb = (uint32_t)xm * SB, xpb = (uint32_t)xp * SB;
+  const bool whole_row = (X0 == 0 && width == Lx);
+  const int hl = X0 == 0 ? Lx - 1 : X0 - 1;          // left edge column
+  const int hr = X0 + width == Lx ? 0 : X0 + width;  // right edge column
+  const int c = tid + 1;                             // ring column of this lane
+  // wavefronts entirely beyond the last column of a narrow lattice only take
+  // part in the barriers
+  const bool wave_act = X0 + kWave * wv < Lx;
+
+  // writes the density deviations of row jr of this lane into the ring (and,
+  // for a whole periodic row, the wrapped edge columns)
+  auto put_row = [&](int jr, const Store(&o)[18]) {
+    DT da, db;
+    density<DT>(o, da, db);
+    DT* ra = ring[jr & 3][0];
+    DT* rb = ring[jr & 3][1];
+    if (act) {
+      ra[c] = da;
+      rb[c] = db;
+      if (whole_row) {
+        if (x == Lx - 1) {
+          ra[0] = da;
+          rb[0] = db;
+        }
+        if (x == 0) {
+          ra[width + 1] = da;
+          rb[width + 1] = db;
+        }
+      }
+    }
+  };
+
+  // Edge columns of a partial segment: lane 18 e + 9 s + l of wavefront 0
+  // pulls link l of species s of edge column e (0: left, 1: right) with one
+  // load instruction; after the row barrier the lane that needs the edge sums
+  // the nine values of each species.
+  // c_x + 1, c_z + 1 (2 bits each) and opp(l) (4 bits) of link l, packed
+  constexpr uint32_t kCXp = 0x20919u, kCZp = 0x02865u;
+  constexpr uint64_t kOppP = 0x658721430ull;
+  const bool edge_lane = !whole_row && wv == 0 && lane < 36;
+  const int el = lane % 9, es = (lane % 18) / 9;
+  const int ecx = (int)((kCXp >> (2 * el)) & 3u) - 1;
+  const int ecz = (int)((kCZp >> (2 * el)) & 3u) - 1;
+  const int eopp = (int)((kOppP >> (4 * el)) & 15u);
+  const int ecol = lane < 18 ? hl : hr;
+  int exs = ecol - ecx;
+  exs = exs < 0 ? exs + Lx : (exs >= Lx ? exs - Lx : exs);
+  auto pull_edges = [&](int jr) {
+    if (edge_lane) {
+      const int js = jr - ecz;
+      const bool bounce = js < 0 || js >= Lz;
+      const uint32_t pl = (uint32_t)(9 * es + (bounce ? eopp : el)) * plane_b;
+      const uint32_t off = pl + (uint32_t)(bounce ? jr : js) * row_b +
+                           (uint32_t)(bounce ? ecol : exs) * SB;
+      edge[jr & 1][lane] = (DT)bload<Store>(in, off, 0);
+    }
+  };
+  auto sum_edges = [&](int jr) {
+    if (!whole_row && (tid == 0 || tid == width - 1)) {
+      const DT* e = edge[jr & 1] + (tid == 0 ? 0 : 18);
+      DT da = e[0], db = e[9];
+#pragma unroll
+      for (int l = 1; l < 9; ++l) {
+        da += e[l];
+        db += e[9 + l];
+      }
+      const int col = tid == 0 ? 0 : width + 1;
+      ring[jr & 3][0][col] = da;
+      ring[jr & 3][1][col] = db;
+    }
+  };
 
   const int64_t t = *a.t_base + a.t_off;
   const uint32_t k0 = R.seed_lo, k1 = R.seed_hi;
@@ -135,57 +252,66 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   const Real fac_d = (Real)R.fac[1], fac_e = (Real)R.fac[3], fac_s = (Real)R.fac[4];
   const Real w1 = (Real)(1.0 / 9.0), w5 = (Real)(1.0 / 36.0), w0 = (Real)(4.0 / 9.0);
   const double rA0 = R.rA_mid, rAs = R.rA_step, rho0 = R.rho0;
-  // shift of a deviation moving up one row, species A: w_l (rho_ref^A(j) -
-  // rho_ref^A(j+1)) = -w_l rho_bar grad_c0; species B has the opposite sign.
+  // shift of a deviation that moves up one row, species A: w_l (rho_ref^A(j)
+  // - rho_ref^A(j+1)) = -w_l rho_bar grad_c0; species B has the opposite sign
   const Real shA1 = (Real)(-rAs / 9.0), shA5 = (Real)(-rAs / 36.0);
 
   const int j0 = it.j0, j1 = it.j1;
-
-  // rolling densities (deviations) of rows j-1 (m), j (c), j+1 (p)
-  DT dAm, dBm, dAc, dBc, dAp, dBp;
   Store cur[18], nxt[18];
-  load_row(in, plane_b, (uint32_t)j0 * row_b + xs_b, cur);
-  row_density<DT>(cur, dAc, dBc);
+  load_pulled(in, plane_b, row_b, j0, Lz, xb, xmb, xpb, cur);
+  put_row(j0, cur);
   if (j0 > 0) {
     Store tmp[18];
-    load_row(in, plane_b, (uint32_t)(j0 - 1) * row_b + xs_b, tmp);
-    row_density<DT>(tmp, dAm, dBm);
-  } else {
-    dAm = dAc;
-    dBm = dBc;
+    load_pulled(in, plane_b, row_b, j0 - 1, Lz, xb, xmb, xpb, tmp);
+    put_row(j0 - 1, tmp);
+  }
+  if (!whole_row && (tid == 0 || tid == width - 1)) {
+    const int col = tid == 0 ? hl : hr, rc = tid == 0 ? 0 : width + 1;
+    for (int jr = max(j0 - 1, 0); jr <= j0; ++jr)
+      edge_density<DT, Store>(in, plane_b, row_b, jr, Lz, Lx, col, ring[jr & 3][0][rc],
+                              ring[jr & 3][1][rc]);
   }
 
   for (int j = j0; j < j1; ++j) {
     const bool top = (j == Lz - 1), bot = (j == 0);
-    if (!top) load_row(in, plane_b, (uint32_t)(j + 1) * row_b + xs_b, nxt);
+    if (!top) {
+      load_pulled(in, plane_b, row_b, j + 1, Lz, xb, xmb, xpb, nxt);
+      pull_edges(j + 1);
+    }
 
     // thermal noise of this node: 14 standard normals (independent of loads)
-    Real g[14];
+    // (species A uses g_0..g_7 from calls 0 and 1; species B uses g_8..g_13
+    // from calls 2 and 3, drawn after the collision of A)
+    const uint32_t node = (uint32_t)(j * Lx + x);
+    Real gA0[4], gA1[4];
     if constexpr (MODE != kSampleOnly) {
-      uint32_t wd[16];
-      node_words((uint32_t)(j * Lx + xs), (uint64_t)t, k0, k1, wd);
-#pragma unroll
-      for (int i = 0; i < 7; ++i) box_muller(wd[2 * i], wd[2 * i + 1], g[2 * i], g[2 * i + 1]);
+      if (wave_act) {
+        node_normals(node, (uint64_t)t, 0u, k0, k1, gA0);
+        node_normals(node, (uint64_t)t, 1u, k0, k1, gA1);
+      }
     }
 
-    if (!top) {
-      row_density<DT>(nxt, dAp, dBp);
-    } else {
-      dAp = dAc;  // ghost row above the top wall
-      dBp = dBc;
-    }
+    if (!top) put_row(j + 1, nxt);
+    __syncthreads();
+    if (!top) sum_edges(j + 1);
 
-    // x-neighbours of the three rows
-    const DT aWm = from_left(dAm), aEm = from_right(dAm);
-    const DT bWm = from_left(dBm), bEm = from_right(dBm);
-    const DT aWc = from_left(dAc), aEc = from_right(dAc);
-    const DT bWc = from_left(dBc), bEc = from_right(dBc);
-    const DT aWp = from_left(dAp), aEp = from_right(dAp);
-    const DT bWp = from_left(dBp), bEp = from_right(dBp);
+    // the 3 x 3 density stencil; ghost rows beyond the walls repeat the wall row
+    const int jU = top ? j : j + 1, jD = bot ? j : j - 1;
+    const DT* aU = ring[jU & 3][0];
+    const DT* bU = ring[jU & 3][1];
+    const DT* aC = ring[j & 3][0];
+    const DT* bC = ring[j & 3][1];
+    const DT* aD = ring[jD & 3][0];
+    const DT* bD = ring[jD & 3][1];
+    const DT dAc = aC[c], dBc = bC[c];
+    const DT aWc = aC[c - 1], aEc = aC[c + 1], bWc = bC[c - 1], bEc = bC[c + 1];
+    const DT dAp = aU[c], aWp = aU[c - 1], aEp = aU[c + 1];
+    const DT dBp = bU[c], bWp = bU[c - 1], bEp = bU[c + 1];
+    const DT dAm = aD[c], aWm = aD[c - 1], aEm = aD[c + 1];
+    const DT dBm = bD[c], bWm = bD[c - 1], bEm = bD[c + 1];
 
     // reference densities of this row and of the rows the stencil reaches
     const double rAj = rA0 + rAs * j;
-    const int jU = top ? j : j + 1, jD = bot ? j : j - 1;
     const double szref = rAs * (double)(jU - jD) * (1.0 / 6.0);  // species A
 
     if constexpr (MODE != kStep) {
@@ -206,20 +332,23 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
                                        (rBu + (double)dBp) + (rBd + (double)dBm)) +
                         (1.0 / 18.0) * ((rBu + (double)bEp) + (rBu + (double)bWp) +
                                         (rBd + (double)bEm) + (rBd + (double)bWm));
-      const double dP = drho * (1.0 / 3.0) + R.G * 0.25 * (rhoA * sB + rhoB * sA) - (R.p_ref - rho0 / 3.0);
-      if (upd) {
+      const double dP =
+          drho * (1.0 / 3.0) + R.G * 0.25 * (rhoA * sB + rhoB * sA) - (R.p_ref - rho0 / 3.0);
+      if (act) {
         double* fld = a.fields + R.field_off;
-        fld[(int64_t)j * Lx + xc] = dc;
-        fld[(int64_t)(Lz + j) * Lx + xc] = drho;
+        fld[(int64_t)j * Lx + x] = dc;
+        fld[(int64_t)(Lz + j) * Lx + x] = drho;
         const bool bad = !(rhoA > 0.0) || !(rhoB > 0.0) || !(dc + c0 > 0.0) ||
                          !(dc + c0 < 1.0) || !isfinite(dP);
         if (bad) atomicOr(a.watchdog, 1);
       }
-      const double tot = wave_sum(upd ? dP : 0.0);
-      if (lane == 0) a.ppart[R.ppart_off + (int64_t)it.strip * Lz + j] = tot;
+      const double tot = wave_sum(act ? dP : 0.0);
+      const int strip = X0 / kWave + wv;
+      if (lane == 0 && strip * kWave < Lx) a.ppart[R.ppart_off + (int64_t)strip * Lz + j] = tot;
     }
 
     if constexpr (MODE != kSampleOnly) {
+     if (wave_act) {
       Real dA[9], dB[9];
 #pragma unroll
       for (int l = 0; l < 9; ++l) {
@@ -234,8 +363,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
       // s^S = sum_l w_l c_l rho^S(r + c_l) (deviation part + reference part)
       const Real sAx = w1 * (Real)(aEc - aWc) + w5 * (Real)((aEp - aWp) + (aEm - aWm));
       const Real sBx = w1 * (Real)(bEc - bWc) + w5 * (Real)((bEp - bWp) + (bEm - bWm));
-      const Real sAz = w1 * (Real)(dAp - dAm) + w5 * (Real)((aEp + aWp) - (aEm + aWm)) + (Real)szref;
-      const Real sBz = w1 * (Real)(dBp - dBm) + w5 * (Real)((bEp + bWp) - (bEm + bWm)) - (Real)szref;
+      const Real sAz =
+          w1 * (Real)(dAp - dAm) + w5 * (Real)((aEp + aWp) - (aEm + aWm)) + (Real)szref;
+      const Real sBz =
+          w1 * (Real)(dBp - dBm) + w5 * (Real)((bEp + bWp) - (bEm + bWm)) - (Real)szref;
 
       // non-ideal forces (Eq. (11)); with a_* both species share
       // a_bar = (rho^A a^A_NI + rho^B a^B_NI) / rho
@@ -290,11 +421,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
 
       // noise amplitudes (reference densities, or local ones)
       Real sd = (Real)R.sig[0][1];
-      Real sA3 = (Real)R.sig[0][3], sA4 = (Real)R.sig[0][4], sA6 = (Real)R.sig[0][6],
-           sA8 = (Real)R.sig[0][8];
-      Real sB3 = (Real)R.sig[1][3], sB4 = (Real)R.sig[1][4], sB6 = (Real)R.sig[1][6],
-           sB8 = (Real)R.sig[1][8];
-      Real sA5 = (Real)R.sig[0][5], sB5 = (Real)R.sig[1][5];
+      Real sA3 = (Real)R.sig[0][3], sA4 = (Real)R.sig[0][4], sA5 = (Real)R.sig[0][5],
+           sA6 = (Real)R.sig[0][6], sA8 = (Real)R.sig[0][8];
+      Real sB3 = (Real)R.sig[1][3], sB4 = (Real)R.sig[1][4], sB5 = (Real)R.sig[1][5],
+           sB6 = (Real)R.sig[1][6], sB8 = (Real)R.sig[1][8];
       if (flags & FNLB_NOISE_LOC) {
         const Real qa = sqrt(rhoA), qb = sqrt(rhoB);
         sd = (Real)R.sig_base[1] * sqrt(rhoA * rhoB * inv_rho);
@@ -309,11 +439,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
         sB6 = (Real)R.sig_base[6] * qb;
         sB8 = (Real)R.sig_base[8] * qb;
       }
-      const Real xi1 = sd * g[0], xi2 = sd * g[1];
+      const Real xi1 = sd * gA0[0], xi2 = sd * gA0[1];
 
-      // collision of one species in moment space; returns the increments
-      // R_l = w_l sum_a T_al dm_a / N_a added to the populations
-      auto collide = [&](Real (&d)[9], Real rs, Real jx, Real jz, Real Fx, Real Fz, Real x1,
+      // collision of one species in moment space: adds the increments
+      // R_l = w_l sum_a T_al dm_a / N_a to the populations
+      auto collide = [&](Real(&d)[9], Real rs, Real jx, Real jz, Real Fx, Real Fz, Real x1,
                          Real x2, Real x3, Real x4, Real x5, Real x6, Real x7, Real x8) {
         const Real s14 = (d[1] + d[2]) + (d[3] + d[4]);
         const Real s58 = (d[5] + d[6]) + (d[7] + d[8]);
@@ -349,49 +479,37 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
         d[6] += w5 * (b38 - p1 + p2 - e5);
         d[8] += w5 * (b38 + p1 - p2 - e5);
       };
-      collide(dA, rhoA, jAx, jAz, FAx, FAz, xi1, xi2, sA3 * g[2], sA4 * g[3], sA5 * g[4],
-              sA6 * g[5], sA6 * g[6], sA8 * g[7]);
-      collide(dB, rhoB, jBx, jBz, FBx, FBz, -xi1, -xi2, sB3 * g[8], sB4 * g[9], sB5 * g[10],
-              sB6 * g[11], sB6 * g[12], sB8 * g[13]);
+      collide(dA, rhoA, jAx, jAz, FAx, FAz, xi1, xi2, sA3 * gA0[2], sA4 * gA0[3],
+              sA5 * gA1[0], sA6 * gA1[1], sA6 * gA1[2], sA8 * gA1[3]);
+      Real gB0[4], gB1[4];
+      node_normals(node, (uint64_t)t, 2u, k0, k1, gB0);
+      node_normals(node, (uint64_t)t, 3u, k0, k1, gB1);
+      collide(dB, rhoB, jBx, jBz, FBx, FBz, -xi1, -xi2, sB3 * gB0[0], sB4 * gB0[1],
+              sB5 * gB0[2], sB6 * gB0[3], sB6 * gB1[0], sB8 * gB1[1]);
 
-      // streaming (push) with mid-way bounce-back
-      if (upd) {
-        const uint32_t rj = (uint32_t)j * row_b;
-        const uint32_t ru = rj + row_b, rd = rj - row_b;
-        auto emit = [&](int s, const Real (&d)[9], Real sh1, Real sh5) {
-          const uint32_t o = (uint32_t)(9 * s) * plane_b;
-          bstore<Store>(out, rj + xs_b, o + 0 * plane_b, (Store)d[0]);
-          bstore<Store>(out, rj + xe_b, o + 1 * plane_b, (Store)d[1]);
-          bstore<Store>(out, rj + xw_b, o + 3 * plane_b, (Store)d[3]);
-          if (!top) {
-            bstore<Store>(out, ru + xs_b, o + 2 * plane_b, (Store)(d[2] + sh1));
-            bstore<Store>(out, ru + xe_b, o + 5 * plane_b, (Store)(d[5] + sh5));
-            bstore<Store>(out, ru + xw_b, o + 6 * plane_b, (Store)(d[6] + sh5));
-          } else {
-            bstore<Store>(out, rj + xs_b, o + 4 * plane_b, (Store)d[2]);
-            bstore<Store>(out, rj + xs_b, o + 7 * plane_b, (Store)d[5]);
-            bstore<Store>(out, rj + xs_b, o + 8 * plane_b, (Store)d[6]);
-          }
-          if (!bot) {
-            bstore<Store>(out, rd + xs_b, o + 4 * plane_b, (Store)(d[4] - sh1));
-            bstore<Store>(out, rd + xw_b, o + 7 * plane_b, (Store)(d[7] - sh5));
-            bstore<Store>(out, rd + xe_b, o + 8 * plane_b, (Store)(d[8] - sh5));
-          } else {
-            bstore<Store>(out, rj + xs_b, o + 2 * plane_b, (Store)d[4]);
-            bstore<Store>(out, rj + xs_b, o + 5 * plane_b, (Store)d[7]);
-            bstore<Store>(out, rj + xs_b, o + 6 * plane_b, (Store)d[8]);
-          }
+      // store the node's post-collision populations, each shifted to the
+      // reference of the row it streams to (bounced-back links stay in row)
+      if (act) {
+        const uint32_t off = (uint32_t)j * row_b + xb;
+        const Real up = top ? (Real)0 : (Real)1, dn = bot ? (Real)0 : (Real)1;
+        auto emit = [&](int s, const Real(&d)[9], Real sh1, Real sh5) {
+          const uint32_t p = (uint32_t)(9 * s) * plane_b;
+          bstore<Store>(out, off, p, (Store)d[0]);
+          bstore<Store>(out, off, p + plane_b, (Store)d[1]);
+          bstore<Store>(out, off, p + 2 * plane_b, (Store)(d[2] + up * sh1));
+          bstore<Store>(out, off, p + 3 * plane_b, (Store)d[3]);
+          bstore<Store>(out, off, p + 4 * plane_b, (Store)(d[4] - dn * sh1));
+          bstore<Store>(out, off, p + 5 * plane_b, (Store)(d[5] + up * sh5));
+          bstore<Store>(out, off, p + 6 * plane_b, (Store)(d[6] + up * sh5));
+          bstore<Store>(out, off, p + 7 * plane_b, (Store)(d[7] - dn * sh5));
+          bstore<Store>(out, off, p + 8 * plane_b, (Store)(d[8] - dn * sh5));
         };
         emit(0, dA, shA1, shA5);
         emit(1, dB, -shA1, -shA5);
       }
+     }
     }
 
-    // rotate the row window
-    dAm = dAc;
-    dBm = dBc;
-    dAc = dAp;
-    dBc = dBp;
 #pragma unroll
     for (int q = 0; q < 18; ++q) cur[q] = nxt[q];
   }

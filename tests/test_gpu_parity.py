@@ -73,6 +73,10 @@ VARIANTS = {
     "tiny_3x5": (W.Replica(Lx=3, Lz=5, grad_c0=0.05, kT=1e-4, G=0.5, seed=18), None, 300, 3),
     "one_strip_plus_one": (W.Replica(Lx=63, Lz=9, grad_c0=0.02, kT=1e-4, G=0.2, seed=19),
                            None, 200, 4),
+    "two_segments_ragged": (W.Replica(Lx=300, Lz=13, grad_c0=5e-3, kT=1e-4, G=0.5, tau_s=0.8,
+                                      seed=23), None, 200, 5),
+    "three_segments": (W.Replica(Lx=600, Lz=8, grad_c0=1e-2, kT=1e-4, G=0.3, seed=24),
+                       W.ASTAR, 150, 5),
     "noiseless": (W.Replica(Lx=32, Lz=16, grad_c0=0.01, kT=0.0, G=0.5, seed=20), None, 500, 50),
     "large_seed_and_time": (W.Replica(Lx=32, Lz=8, grad_c0=0.0, kT=1e-4, seed=(1 << 63) + 5),
                             None, 50, 5),
