@@ -40,22 +40,76 @@ def _events_time(lat, nsteps):
     return e0.elapsed_time(e1)
 
 
+STEP_SOURCES = ("k_step.hip", "fnlb_device.hpp", "fnlb_internal.hpp")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_k_step_batched96_fp32dev.json")
+
+
+def _step_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for n in STEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_1808_05168_amd", "csrc", n), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def _traffic_from_profiles():
     """HBM bytes per step launch from the committed counter summary, if it was
-    taken on the current kernel build (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic_k_step_batched96_fp32dev.json")
-    lib = os.path.join(ROOT, "paper_1808_05168_amd", "libfnlb.so")
+    taken on the current kernel sources (else None)."""
     try:
-        with open(path) as fh:
+        with open(TRAFFIC_JSON) as fh:
             d = json.load(fh)
-        import hashlib
-        src = b"".join(open(os.path.join(ROOT, "paper_1808_05168_amd", "csrc", n), "rb").read()
-                       for n in ("k_step.hip", "fnlb_device.hpp", "fnlb_internal.hpp"))
-        if d.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        if d.get("source_sha256") != _step_source_hash():
             return None
         return d["bytes_per_launch"]
     except (OSError, KeyError, ValueError):
         return None
+
+
+def summarize_profile(trace_dir, fetch_dir, write_dir, out_md, command):
+    """Turns rocprofv3 outputs of this benchmark into the committed summary:
+    kernel-trace statistics, and HBM bytes per step launch from FETCH_SIZE and
+    WRITE_SIZE scaled by what the same counters read for the plain 1 GiB copy
+    that --copy-calibration-mb 1024 runs first."""
+    import csv
+    from collections import defaultdict
+    stats = list(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_stats.csv"))))
+
+    def counters(d, name):
+        acc = defaultdict(list)
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            if r["Counter_Name"] == name:
+                acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    fetch, write = counters(fetch_dir, "FETCH_SIZE"), counters(write_dir, "WRITE_SIZE")
+    copy = [k for k in fetch if "copyBuffer" in k][0]
+    step = [k for k in fetch if "k_step<float, float, 0>" in k][0]
+    copy_kib = 1024 * 1024
+    f_scale, w_scale = copy_kib / fetch[copy], copy_kib / write[copy]
+    rd = fetch[step] * f_scale * 1024
+    wr = write[step] * w_scale * 1024
+    import workloads as W
+    nodes = sum(r.Lx * r.Lz for r in W.batched_ensemble(96))
+    alg = 144 * nodes
+    lines = ["# k_step (fused collide-stream), batched 96-replica FP32-deviation workload", "",
+             "Command:", "", "```", command, "```", "",
+             "| kernel | calls | average us | share % |", "|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs'])/1e3:.1f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    lines += ["", "HBM bytes per step launch (counters scaled by the 1 GiB copy: FETCH x"
+              f"{f_scale:.4f}, WRITE x{w_scale:.4f}):", "",
+              f"- read {rd/1e6:.1f} MB, write {wr/1e6:.1f} MB, total {(rd+wr)/1e6:.1f} MB",
+              f"- algorithmic (144 B/node x {nodes} nodes): {alg/1e6:.1f} MB",
+              f"- ratio {(rd+wr)/alg:.3f}"]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump({"bytes_per_launch": round(rd + wr), "read_bytes": round(rd),
+                   "write_bytes": round(wr), "algorithmic_bytes": alg,
+                   "source_sha256": _step_source_hash(), "command": command}, fh, indent=1)
+    print("\n".join(lines))
 
 
 def cpu_baseline(reps, budget_s: float):
@@ -101,7 +155,16 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device copy of this size (3 times), the "
                          "reference for scaling HBM byte counters")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--summarize-profile", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
+                    help="summarise rocprofv3 output directories into profiles/ (CPU only)")
+    ap.add_argument("--profile-command", default="")
     args = ap.parse_args()
+
+    if args.summarize_profile:
+        out = os.path.join(ROOT, "profiles", "k_step_batched96_fp32dev.md")
+        summarize_profile(*args.summarize_profile, out, args.profile_command)
+        return
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -141,6 +204,7 @@ def main():
     bytes_per_node = 36 * store_bytes
 
     lat = F.Lattice(reps, precision=prec, sample_every=every)
+    chunk = lat.autotune(20) if not args.no_autotune else 0
     lat.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -175,7 +239,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "nodes": nodes,
                    "storage": "fp32-deviation" if prec == F.FP32_DEV else "fp64",
-                   "sample_every": every, "parallelism": "single GPU"},
+                   "sample_every": every, "chunk_rows": chunk, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_step (fused collide-stream)",
@@ -187,6 +251,8 @@ def main():
     if not args.no_compare and args.workload != "single512x256":
         ref = W.single_512x256()
         lat64 = F.Lattice([ref], precision=F.FP64, sample_every=10)
+        if not args.no_autotune:
+            lat64.autotune(20)
         lat64.step(args.warmup)
         n64 = args.steps
         ms64 = _events_time(lat64, n64)

@@ -57,6 +57,8 @@ extern "C" {
                                 densities instead of the reference values */
 #define FNLB_FORCE_LITERAL 8 /* first-order forcing moments rho^S a^S without
                                 the (1 - lambda_d/2) factor (diagnostic) */
+#define FNLB_NO_GRAPH 16      /* execution only: launch every step directly
+                                instead of replaying captured graphs */
 #define FNLB_DEFAULT_FLAGS (FNLB_ASTAR | FNLB_WALL_UZ_FIX)
 
 /* ---- fields of the structure factor ---- */
@@ -118,8 +120,21 @@ int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep,
  * densities, non-ideal and non-equilibrium forces, wall U_z fix, barycentric
  * velocity (Eq. (10)), MRT collision with forcing moments and noise (Eq. (14)),
  * then streaming with mid-way bounce-back at the walls and periodic x.
- * Samples according to options->sample_every.  Asynchronous. */
+ * Samples according to options->sample_every.  All replicas advance in one
+ * kernel launch per step.  Whole sampling periods (sample_every steps, or 16
+ * steps without sampling) that start on a period boundary are replayed from a
+ * HIP graph captured on first use (unless FNLB_NO_GRAPH); results are
+ * identical either way.  Asynchronous. */
 int fnlb_step(fnlb_handle* h, int64_t n);
+
+/* Chooses the number of rows each work item of the step kernel covers by
+ * timing steps_per_trial >= 1 launches of each candidate (4 to 128 rows) and
+ * keeps the fastest for this handle and, for the rest of the process, for
+ * any handle with the same precision and set of lattice shapes created with
+ * options->chunk_rows = 0.  Trial steps read the current state and write the
+ * spare copy, so the state and the time are unchanged.  Synchronises the
+ * stream; *chunk_rows_out (nullable) receives the choice. */
+int fnlb_autotune(fnlb_handle* h, int32_t steps_per_trial, int32_t* chunk_rows_out);
 
 /* Samples the current state f(t) of every replica now: adds |Phi(q)|^2,
  * Re Phi(q), Im Phi(q) of delta c and delta rho, with

@@ -7,7 +7,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 using namespace fnlb;
@@ -30,7 +33,8 @@ int validate(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options*
   if (!reps || !opt || n_rep <= 0) return FNLB_EINVAL;
   if (opt->precision != FNLB_FP64 && opt->precision != FNLB_FP32_DEV) return FNLB_EINVAL;
   if (opt->sample_every < 0 || opt->chunk_rows < 0) return FNLB_EINVAL;
-  if (opt->flags & ~(FNLB_ASTAR | FNLB_WALL_UZ_FIX | FNLB_NOISE_LOC | FNLB_FORCE_LITERAL))
+  if (opt->flags &
+      ~(FNLB_ASTAR | FNLB_WALL_UZ_FIX | FNLB_NOISE_LOC | FNLB_FORCE_LITERAL | FNLB_NO_GRAPH))
     return FNLB_EINVAL;
   for (int r = 0; r < n_rep; ++r) {
     const fnlb_replica_params& p = reps[r];
@@ -61,8 +65,44 @@ struct Plan {
   // work-buffer offsets (bytes)
   size_t o_reps = 0, o_items = 0, o_rows = 0, o_cols = 0, o_misc = 0, o_tw = 0, o_fields = 0,
          o_spec = 0, o_ppart = 0;
+  size_t item_capacity = 0;  // items the work buffer holds (row ranges of one row)
   int max_lx = 0, max_lz = 0, max_col_lds = 0, chunk = 0;
 };
+
+// work items for a row-range length: (replica, row range, segment), with
+// neighbouring segments of the same rows adjacent
+void make_items(Plan& P, int chunk) {
+  P.chunk = chunk;
+  P.items.clear();
+  for (size_t r = 0; r < P.info.size(); ++r) {
+    const RepInfo& R = P.info[r];
+    const int nseg = (R.Lx + kSeg - 1) / kSeg;
+    for (int j0 = 0; j0 < R.Lz; j0 += chunk)
+      for (int s = 0; s < nseg; ++s)
+        P.items.push_back(Item{(int32_t)r, s, j0, std::min(R.Lz, j0 + chunk)});
+  }
+}
+
+// Row-range lengths found by fnlb_autotune, per precision and set of lattice
+// shapes, for the life of the process.
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+
+std::string tune_key(const fnlb_replica_params* reps, int n_rep, int precision) {
+  std::map<std::pair<int, int>, int> shapes;
+  for (int r = 0; r < n_rep; ++r) ++shapes[{reps[r].Lx, reps[r].Lz}];
+  std::string k = std::to_string(precision);
+  for (const auto& e : shapes)
+    k += "|" + std::to_string(e.first.first) + "x" + std::to_string(e.first.second) + "*" +
+         std::to_string(e.second);
+  return k;
+}
+
+int cached_chunk(const fnlb_replica_params* reps, int n_rep, int precision) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune_cache.find(tune_key(reps, n_rep, precision));
+  return it == g_tune_cache.end() ? 0 : it->second;
+}
 
 int auto_chunk(const fnlb_replica_params* reps, int n_rep) {
   int64_t seg_rows = 0;
@@ -77,7 +117,9 @@ int auto_chunk(const fnlb_replica_params* reps, int n_rep) {
 
 void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* opt, Plan& P) {
   P.store_size = opt->precision == FNLB_FP64 ? 8 : 4;
-  P.chunk = opt->chunk_rows > 0 ? opt->chunk_rows : auto_chunk(reps, n_rep);
+  int chunk = opt->chunk_rows;
+  if (chunk <= 0) chunk = cached_chunk(reps, n_rep, opt->precision);
+  if (chunk <= 0) chunk = auto_chunk(reps, n_rep);
   P.info.assign(n_rep, RepInfo{});
   int64_t state_elems = 0, field_d = 0, spec_c = 0, acc_d = 0, ppart_d = 0, tw_c = 0;
   const int64_t elem_align = (int64_t)(kAlign / P.store_size);
@@ -141,15 +183,9 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
     P.max_lx = std::max(P.max_lx, p.Lx);
     P.max_lz = std::max(P.max_lz, p.Lz);
   }
-  // work items: (replica, row range, segment), neighbouring segments adjacent
-  P.items.clear();
-  for (int r = 0; r < n_rep; ++r) {
-    const RepInfo& R = P.info[r];
-    const int nseg = (R.Lx + kSeg - 1) / kSeg;
-    for (int j0 = 0; j0 < R.Lz; j0 += P.chunk)
-      for (int s = 0; s < nseg; ++s)
-        P.items.push_back(Item{r, s, j0, std::min(R.Lz, j0 + P.chunk)});
-  }
+  make_items(P, chunk);
+  P.item_capacity = 0;
+  for (const RepInfo& R : P.info) P.item_capacity += (size_t)((R.Lx + kSeg - 1) / kSeg) * R.Lz;
   // rows and column tiles of the transforms
   P.rows.clear();
   P.cols.clear();
@@ -173,7 +209,7 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
   P.o_reps = o;
   o = align_up(o + P.info.size() * sizeof(RepInfo));
   P.o_items = o;
-  o = align_up(o + P.items.size() * sizeof(Item));
+  o = align_up(o + P.item_capacity * sizeof(Item));
   P.o_rows = o;
   o = align_up(o + P.rows.size() * sizeof(RowRef));
   P.o_cols = o;
@@ -206,6 +242,10 @@ struct fnlb_handle {
   int64_t t_dev = 0;     // value held by the device time base
   int64_t nsamples = 0;
   int error = FNLB_OK;   // sticky error
+  // one sampling period captured as a graph, per parity of the starting copy
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  int64_t period = 0;
 
   RepInfo* d_reps() { return (RepInfo*)(work + plan.o_reps); }
   Item* d_items() { return (Item*)(work + plan.o_items); }
@@ -246,16 +286,73 @@ StepArgs step_args(fnlb_handle* h, int64_t t_off) {
 }
 
 // Structure-factor transforms and pressure reduction of the sample fields.
-hipError_t observe(fnlb_handle* h) {
+hipError_t observe(fnlb_handle* h, hipStream_t s) {
   const Plan& P = h->plan;
   hipError_t e = launch_row_transform(h->d_reps(), h->d_rows(), (int)P.rows.size(), P.max_lx,
-                                      h->d_fields(), h->d_spec(), h->d_tw(), h->stream);
+                                      h->d_fields(), h->d_spec(), h->d_tw(), s);
   if (e != hipSuccess) return e;
   e = launch_col_transform(h->d_reps(), h->d_cols(), (int)P.cols.size(), P.max_col_lds,
-                           h->d_spec(), (double*)h->accum, h->d_tw(), h->stream);
+                           h->d_spec(), (double*)h->accum, h->d_tw(), s);
   if (e != hipSuccess) return e;
   return launch_pressure_reduce(h->d_reps(), (int)P.info.size(), P.max_lz, h->d_ppart(),
-                                (double*)h->accum, h->stream);
+                                (double*)h->accum, s);
+}
+
+void drop_graphs(fnlb_handle* h) {
+  for (auto& g : h->graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+// Captures one period of `period` steps starting at a period start, from
+// state copy `parity`: the first step samples when sampling is on, and the
+// last node advances the device time counter by the period.  Kernels read
+// their time as counter + offset, so one graph serves every period.
+hipError_t capture_period(fnlb_handle* h, int parity) {
+  hipError_t e = hipSuccess;
+  if (!h->cap_stream) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  hipStream_t s = h->cap_stream;
+  e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  const bool sampling = h->opt.sample_every > 0;
+  const int saved = h->cur;
+  h->cur = parity;
+  hipError_t le = hipSuccess;
+  for (int64_t k = 0; k < h->period && le == hipSuccess; ++k) {
+    const bool smp = sampling && k == 0;
+    StepArgs a = step_args(h, k);
+    le = launch_step(h->opt.precision, smp ? kStepSample : kStep, a, s);
+    if (le == hipSuccess && smp) le = observe(h, s);
+    h->cur ^= 1;
+  }
+  if (le == hipSuccess) le = launch_advance_time(h->d_time(), h->period, s);
+  h->cur = saved;
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(s, &g);
+  if (le != hipSuccess) e = le;
+  if (e == hipSuccess) e = hipGraphInstantiate(&h->graph[parity], g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  return e;
+}
+
+// Runs one captured period on the caller's stream.
+int replay_period(fnlb_handle* h) {
+  hipError_t e = hipSuccess;
+  if (h->t_dev != h->t) {  // bring the device time counter to the period start
+    e = launch_advance_time(h->d_time(), h->t - h->t_dev, h->stream);
+    h->t_dev = h->t;
+  }
+  if (e == hipSuccess && !h->graph[h->cur]) e = capture_period(h, h->cur);
+  if (e == hipSuccess) e = hipGraphLaunch(h->graph[h->cur], h->stream);
+  if (e != hipSuccess) return dev_err(h, e);
+  h->t += h->period;
+  h->t_dev += h->period;
+  if (h->period & 1) h->cur ^= 1;
+  if (h->opt.sample_every > 0) ++h->nsamples;
+  return FNLB_OK;
 }
 
 int check_watchdog(fnlb_handle* h) {
@@ -326,6 +423,7 @@ int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options
   h->accum = (char*)d_accum;
   h->work = (char*)d_work;
   h->stream = (hipStream_t)hip_stream;
+  h->period = h->opt.sample_every > 0 ? h->opt.sample_every : 16;
   hipStream_t s = h->stream;
   hipError_t e = hipSuccess;
   auto up = [&](size_t off, const void* src, size_t n) {
@@ -354,17 +452,77 @@ int fnlb_step(fnlb_handle* h, int64_t n) {
   if (!h || n < 0) return FNLB_EINVAL;
   if (h->error) return h->error;
   const int every = h->opt.sample_every;
-  for (int64_t i = 0; i < n; ++i) {
+  const bool use_graph = !(h->opt.flags & FNLB_NO_GRAPH);
+  while (n > 0) {
     const int64_t t = h->t;
+    // whole sampling periods from a period start replay the captured graph
+    if (use_graph && n >= h->period && t % h->period == 0 && (every == 0 || t >= 1)) {
+      const int rc = replay_period(h);
+      if (rc) return rc;
+      n -= h->period;
+      continue;
+    }
     const bool smp = every > 0 && t >= 1 && t % every == 0;
     StepArgs a = step_args(h, t - h->t_dev);
     hipError_t e = launch_step(h->opt.precision, smp ? kStepSample : kStep, a, h->stream);
-    if (e == hipSuccess && smp) e = observe(h);
+    if (e == hipSuccess && smp) e = observe(h, h->stream);
     if (e != hipSuccess) return dev_err(h, e);
     if (smp) ++h->nsamples;
     h->cur ^= 1;
     ++h->t;
+    --n;
   }
+  return FNLB_OK;
+}
+
+int fnlb_autotune(fnlb_handle* h, int32_t steps_per_trial, int32_t* chunk_rows_out) {
+  if (!h || steps_per_trial < 1) return FNLB_EINVAL;
+  if (h->error) return h->error;
+  Plan& P = h->plan;
+  int max_lz = 0;
+  for (const RepInfo& R : P.info) max_lz = std::max(max_lz, R.Lz);
+  const int cands[] = {4, 8, 16, 32, 64, 128};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  int best = P.chunk;
+  float best_ms = 1e30f;
+  for (int c : cands) {
+    if (e != hipSuccess) break;
+    if (c > 2 * max_lz && c != 4) continue;
+    make_items(P, c);
+    e = hipMemcpyAsync(h->d_items(), P.items.data(), P.items.size() * sizeof(Item),
+                       hipMemcpyHostToDevice, h->stream);
+    // trial steps read the current copy and write the spare one: the state
+    // and the time are unchanged
+    StepArgs a = step_args(h, h->t - h->t_dev);
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step(h->opt.precision, kStep, a, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+    for (int k = 0; k < steps_per_trial && e == hipSuccess; ++k)
+      e = launch_step(h->opt.precision, kStep, a, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  make_items(P, best);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->d_items(), P.items.data(), P.items.size() * sizeof(Item),
+                       hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return dev_err(h, e);
+  drop_graphs(h);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[tune_key(h->reps.data(), (int)h->reps.size(), h->opt.precision)] = best;
+  }
+  if (chunk_rows_out) *chunk_rows_out = best;
   return FNLB_OK;
 }
 
@@ -373,7 +531,7 @@ int fnlb_accumulate_structure_factor(fnlb_handle* h) {
   if (h->error) return h->error;
   StepArgs a = step_args(h, h->t - h->t_dev);
   hipError_t e = launch_step(h->opt.precision, kSampleOnly, a, h->stream);
-  if (e == hipSuccess) e = observe(h);
+  if (e == hipSuccess) e = observe(h, h->stream);
   if (e != hipSuccess) return dev_err(h, e);
   ++h->nsamples;
   return FNLB_OK;
@@ -493,6 +651,9 @@ int fnlb_set_time(fnlb_handle* h, int64_t t) {
 }
 
 int fnlb_destroy(fnlb_handle* h) {
+  if (!h) return FNLB_OK;
+  drop_graphs(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
   return FNLB_OK;
 }

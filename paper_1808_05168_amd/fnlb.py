@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libfnlb.so")
 
 FNLB_OK = 0
 FP64, FP32_DEV = 0, 1
-ASTAR, WALL_UZ_FIX, NOISE_LOC, FORCE_LITERAL = 1, 2, 4, 8
+ASTAR, WALL_UZ_FIX, NOISE_LOC, FORCE_LITERAL, NO_GRAPH = 1, 2, 4, 8, 16
 DEFAULT_FLAGS = ASTAR | WALL_UZ_FIX
 FIELD_C, FIELD_RHO = 0, 1
 
@@ -42,7 +42,7 @@ class FnlbError(RuntimeError):
 
 
 _lib = None
-EXPORTS = ["fnlb_bytes_required", "fnlb_init", "fnlb_step",
+EXPORTS = ["fnlb_bytes_required", "fnlb_init", "fnlb_step", "fnlb_autotune",
            "fnlb_accumulate_structure_factor", "fnlb_read_structure_factor",
            "fnlb_read_pressure", "fnlb_read_populations", "fnlb_write_populations",
            "fnlb_reset_accumulators", "fnlb_get_time", "fnlb_set_time", "fnlb_destroy",
@@ -65,6 +65,7 @@ def load(path: str = LIB_PATH):
     lib.fnlb_init.argtypes = [rp, ctypes.c_int32, op, vp, ctypes.c_size_t, vp, ctypes.c_size_t,
                               vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     lib.fnlb_step.argtypes = [vp, ctypes.c_int64]
+    lib.fnlb_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.fnlb_accumulate_structure_factor.argtypes = [vp]
     lib.fnlb_read_structure_factor.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, dp, dp, dp,
                                                i64p]
@@ -162,6 +163,13 @@ class Lattice:
     # -- the method --
     def step(self, n: int = 1) -> None:
         _check(self._lib.fnlb_step(self._h, int(n)), "fnlb_step")
+
+    def autotune(self, steps_per_trial: int = 20) -> int:
+        """Picks the fastest row-range length of the step kernel; returns it."""
+        c = ctypes.c_int32()
+        _check(self._lib.fnlb_autotune(self._h, int(steps_per_trial), ctypes.byref(c)),
+               "fnlb_autotune")
+        return int(c.value)
 
     def accumulate_structure_factor(self) -> None:
         _check(self._lib.fnlb_accumulate_structure_factor(self._h),

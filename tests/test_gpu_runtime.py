@@ -1,0 +1,85 @@
+"""GPU checks of the runtime around the step kernel: graph replay of whole
+sampling periods is bit-identical to direct launches (checked after every
+chunk of steps, with host reads in between), and the autotuner leaves state
+and time untouched."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import compare_observables, dev_norm, run_oracle, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    import paper_1808_05168_amd as F
+    F.load()
+    return F
+
+
+def _same(a, b):
+    for i in range(len(a.reps)):
+        np.testing.assert_array_equal(a.read_populations(i), b.read_populations(i))
+        for fld in range(2):
+            ra, rb = a.read_structure_factor(i, fld), b.read_structure_factor(i, fld)
+            assert ra[3] == rb[3]
+            for x, y in zip(ra[:3], rb[:3]):
+                np.testing.assert_array_equal(x, y)
+        pa, pb = a.read_pressure(i), b.read_pressure(i)
+        assert pa[0] == pb[0] and pa[1] == pb[1]
+        np.testing.assert_array_equal(pa[2], pb[2])
+
+
+@pytest.mark.parametrize("every,prec", [(5, 0), (4, 1), (0, 0), (7, 1)])
+def test_graph_replay_matches_direct_launches(F, every, prec):
+    reps = [W.Replica(Lx=96, Lz=20, grad_c0=2e-3, kT=1e-4, G=0.5, seed=51),
+            W.Replica(Lx=300, Lz=9, grad_c0=1e-2, kT=1e-4, seed=52)]
+    say(f"case: graph vs direct, every={every} precision={prec}")
+    g = F.Lattice(reps, precision=prec, sample_every=every)
+    d = F.Lattice(reps, precision=prec, sample_every=every, flags=F.DEFAULT_FLAGS | F.NO_GRAPH)
+    for n in (3, 7, 20, 1, 13, 40, 0, 17):
+        g.step(n)
+        d.step(n)
+        assert g.time == d.time
+        _same(g, d)
+    if prec == 0:
+        for i, rep in enumerate(reps):
+            f_o, acc = run_oracle(rep, g.time, every=every)
+            assert dev_norm(g.read_populations(i), f_o, rep) <= 1e-12
+            compare_observables(g, acc, i, rep, 1e-12)
+
+
+def test_graph_after_time_reset_and_write(F):
+    rep = W.Replica(Lx=64, Lz=16, grad_c0=5e-3, kT=1e-4, G=0.5, seed=53)
+    say("case: graph after set_time/write_populations")
+    g = F.Lattice([rep], sample_every=4)
+    d = F.Lattice([rep], sample_every=4, flags=F.DEFAULT_FLAGS | F.NO_GRAPH)
+    g.step(11)
+    d.step(11)
+    f = g.read_populations(0)
+    for lat in (g, d):
+        lat.write_populations(0, f)
+        lat.time = 40
+        lat.step(12)
+    _same(g, d)
+
+
+def test_autotune_keeps_state_and_results(F):
+    rep = W.large_4096x1024()
+    say("case: autotune 4096x1024 fp32-dev")
+    a = F.Lattice([rep], precision=F.FP32_DEV, sample_every=10)
+    b = F.Lattice([rep], precision=F.FP32_DEV, sample_every=10, chunk_rows=16)
+    a.step(12)
+    b.step(12)
+    before = a.read_populations(0)
+    chunk = a.autotune(5)
+    assert chunk in (4, 8, 16, 32, 64, 128)
+    assert a.time == 12
+    np.testing.assert_array_equal(a.read_populations(0), before)
+    a.step(21)
+    b.step(21)
+    _same(a, b)

@@ -19,6 +19,7 @@ ASTAR = 1            # a_* correction of the footnote to Eq. (13)
 WALL_UZ_FIX = 2      # U_z = 0 on the wall rows (Sec. III.A)
 NOISE_LOC = 4        # local instead of reference densities in the noise
 FORCE_LITERAL = 8    # first-order forcing without (1 - lambda_d/2) (tests only)
+NO_GRAPH = 16        # execution only: no graph replay
 DEFAULT_FLAGS = ASTAR | WALL_UZ_FIX
 
 
