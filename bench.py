@@ -68,38 +68,56 @@ def _traffic_from_profiles():
 
 def summarize_profile(trace_dir, fetch_dir, write_dir, out_md, command):
     """Turns rocprofv3 outputs of this benchmark into the committed summary:
-    kernel-trace statistics, and HBM bytes per step launch from FETCH_SIZE and
-    WRITE_SIZE scaled by what the same counters read for the plain 1 GiB copy
-    that --copy-calibration-mb 1024 runs first."""
+    kernel-trace statistics, the average duration of the step kernel in the
+    timed configuration (its most frequent grid size; autotuning trials use
+    other grids), and HBM bytes per step launch from FETCH_SIZE and WRITE_SIZE
+    scaled by what the same counters read for the plain 1 GiB copies that
+    --copy-calibration-mb 1024 runs first."""
     import csv
-    from collections import defaultdict
+    from collections import Counter, defaultdict
+    step_name = "k_step<float, float, 0>"
     stats = list(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_stats.csv"))))
+    trace = [r for r in csv.DictReader(open(os.path.join(trace_dir, "run_kernel_trace.csv")))
+             if step_name in r["Kernel_Name"]]
+    grid = Counter(r["Grid_Size_X"] for r in trace).most_common(1)[0][0]
+    durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace
+            if r["Grid_Size_X"] == grid]
+    avg_us = sum(durs) / len(durs) / 1e3
 
     def counters(d, name):
-        acc = defaultdict(list)
+        step, copy = [], []
         for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
-            if r["Counter_Name"] == name:
-                acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
-        return {k: sum(v) / len(v) for k, v in acc.items()}
+            if r["Counter_Name"] != name:
+                continue
+            if step_name in r["Kernel_Name"] and r["Grid_Size"] == grid:
+                step.append(float(r["Counter_Value"]))
+            elif "copyBuffer" in r["Kernel_Name"]:
+                copy.append(float(r["Counter_Value"]))
+        big = [v for v in copy if v >= 0.5 * max(copy)]
+        return sum(step) / len(step), sum(big) / len(big), len(step)
 
-    fetch, write = counters(fetch_dir, "FETCH_SIZE"), counters(write_dir, "WRITE_SIZE")
-    copy = [k for k in fetch if "copyBuffer" in k][0]
-    step = [k for k in fetch if "k_step<float, float, 0>" in k][0]
+    f_step, f_copy, nf = counters(fetch_dir, "FETCH_SIZE")
+    w_step, w_copy, nw = counters(write_dir, "WRITE_SIZE")
     copy_kib = 1024 * 1024
-    f_scale, w_scale = copy_kib / fetch[copy], copy_kib / write[copy]
-    rd = fetch[step] * f_scale * 1024
-    wr = write[step] * w_scale * 1024
+    f_scale, w_scale = copy_kib / f_copy, copy_kib / w_copy
+    rd = f_step * f_scale * 1024
+    wr = w_step * w_scale * 1024
     import workloads as W
     nodes = sum(r.Lx * r.Lz for r in W.batched_ensemble(96))
     alg = 144 * nodes
     lines = ["# k_step (fused collide-stream), batched 96-replica FP32-deviation workload", "",
-             "Command:", "", "```", command, "```", "",
+             "Commands (run from the repository root; <out> is any output directory):", "",
+             "```", command, "```", "",
+             "## Kernel trace (rocprofv3 --stats)", "",
              "| kernel | calls | average us | share % |", "|---|---|---|---|"]
     for r in stats:
         lines.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs'])/1e3:.1f} | "
                      f"{float(r['Percentage']):.2f} |")
-    lines += ["", "HBM bytes per step launch (counters scaled by the 1 GiB copy: FETCH x"
-              f"{f_scale:.4f}, WRITE x{w_scale:.4f}):", "",
+    lines += ["", f"Step kernel in the timed configuration (grid {grid} threads, "
+              f"{len(durs)} dispatches): average {avg_us:.1f} us.", "",
+              "## HBM traffic per step launch", "",
+              f"FETCH_SIZE and WRITE_SIZE (KiB per dispatch, {nf} and {nw} step dispatches) "
+              f"scaled by the 1 GiB copy: FETCH x{f_scale:.4f}, WRITE x{w_scale:.4f}.", "",
               f"- read {rd/1e6:.1f} MB, write {wr/1e6:.1f} MB, total {(rd+wr)/1e6:.1f} MB",
               f"- algorithmic (144 B/node x {nodes} nodes): {alg/1e6:.1f} MB",
               f"- ratio {(rd+wr)/alg:.3f}"]
@@ -108,6 +126,7 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, out_md, command):
     with open(TRAFFIC_JSON, "w") as fh:
         json.dump({"bytes_per_launch": round(rd + wr), "read_bytes": round(rd),
                    "write_bytes": round(wr), "algorithmic_bytes": alg,
+                   "step_avg_us": round(avg_us, 2), "grid": int(grid),
                    "source_sha256": _step_source_hash(), "command": command}, fh, indent=1)
     print("\n".join(lines))
 
