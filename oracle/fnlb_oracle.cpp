@@ -725,6 +725,70 @@ int ora_velocity(const ora_params* p, const double* f, double* U) {
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Structure-factor misfit over a horizon, for the gradient checks.
+// From the rest state on the imposed profile at t = 0, run `horizon` steps with
+// sampling per reading R9 (p->sample_every), form S(q) = <|Phi|^2> - |<Phi>|^2
+// of `field` (0: delta c, 1: delta rho) over the half spectrum [k_z][k_x], and
+// return J = sum_q weight_q (S(q) - S_target(q))^2.  The Gaussian variates do
+// not depend on the parameters (the noise stream is held fixed).
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+template <typename T>
+T sq_misfit(const ora_params& p, const Theta<T>& th, int64_t horizon, int field,
+            const double* S_target, const double* weight) {
+  Sim<T> sim(p, th);
+  const int nkx = p.Lx / 2 + 1;
+  const size_t plane = (size_t)p.Lz * nkx;
+  std::vector<T> f((size_t)2 * Q * sim.n), sq(6 * plane, T(0));
+  sim.init(f.data());
+  int64_t ns = 0;
+  sim.run(f.data(), 0, horizon, sq.data(), nullptr, nullptr, nullptr, &ns);
+  const T* a2 = sq.data() + (size_t)field * 3 * plane;
+  const T* re = a2 + plane;
+  const T* im = a2 + 2 * plane;
+  const double n = ns > 0 ? (double)ns : 1.0;
+  T J = T(0);
+  for (size_t q = 0; q < plane; ++q) {
+    const T mr = re[q] / n, mi = im[q] / n;
+    const T S = a2[q] / n - (mr * mr + mi * mi);
+    const T d = S - S_target[q];
+    J += weight[q] * d * d;
+  }
+  return J;
+}
+}  // namespace
+
+extern "C" {
+
+int ora_sq_misfit(const ora_params* p, int64_t horizon, int field, const double* S_target,
+                  const double* weight, double* J) {
+  if (check_params(p) || horizon < 0 || (field != 0 && field != 1)) return -1;
+  Theta<double> th{p->tau_d, p->tau_s, p->G};
+  *J = sq_misfit<double>(*p, th, horizon, field, S_target, weight);
+  return 0;
+}
+
+// Complex-step derivative dJ/dtheta_which (0: tau_s, 1: tau_d, 2: G):
+// Im J(theta + i h e_which) / h, exact to rounding for small h.
+int ora_sq_misfit_cs(const ora_params* p, int64_t horizon, int field, const double* S_target,
+                     const double* weight, int which, double h, double* dJ) {
+  if (check_params(p) || horizon < 0 || (field != 0 && field != 1) || which < 0 || which > 2 ||
+      !(h > 0))
+    return -1;
+  typedef std::complex<double> C;
+  Theta<C> th{C(p->tau_d), C(p->tau_s), C(p->G)};
+  const C ih(0.0, h);
+  if (which == 0) th.tau_s += ih;
+  if (which == 1) th.tau_d += ih;
+  if (which == 2) th.G += ih;
+  const C J = sq_misfit<C>(*p, th, horizon, field, S_target, weight);
+  *dJ = J.imag() / h;
+  return 0;
+}
+
 }  // extern "C"
 
 // The complex instantiation is what complex-step differentiation runs on.

@@ -26,7 +26,8 @@ DEFAULT_FLAGS = ASTAR | WALL_UZ_FIX
 
 def build(force: bool = False) -> str:
     """Compile the oracle with g++ -O2 (plain C++, OpenMP over nodes)."""
-    if force or not os.path.exists(_LIB):
+    stale = (not os.path.exists(_LIB)) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC",
                                "-shared", _SRC, "-o", tmp])
@@ -204,3 +205,41 @@ def velocity(rep, f: np.ndarray, flags: int = DEFAULT_FLAGS) -> np.ndarray:
     if lib().ora_velocity(ctypes.byref(p), _dp(f), _dp(U)) != 0:
         raise ValueError("oracle: invalid parameters")
     return U
+
+
+def _misfit_argtypes():
+    dp = ctypes.POINTER(ctypes.c_double)
+    pp = ctypes.POINTER(OraParams)
+    lib().ora_sq_misfit.argtypes = [pp, ctypes.c_int64, ctypes.c_int, dp, dp, dp]
+    lib().ora_sq_misfit_cs.argtypes = [pp, ctypes.c_int64, ctypes.c_int, dp, dp, ctypes.c_int,
+                                       ctypes.c_double, dp]
+
+
+def sq_misfit(rep, horizon: int, every: int, field: int, S_target: np.ndarray,
+              weight: np.ndarray, flags: int = DEFAULT_FLAGS) -> float:
+    """J = sum_q weight_q (S(q) - S_target(q))^2 over a run of `horizon` steps
+    from the rest state, sampled every `every` steps (half spectrum [kz][kx])."""
+    _misfit_argtypes()
+    p = params(rep, flags, every)
+    St = np.ascontiguousarray(S_target, dtype=np.float64)
+    w = np.ascontiguousarray(weight, dtype=np.float64)
+    J = ctypes.c_double()
+    if lib().ora_sq_misfit(ctypes.byref(p), horizon, field, _dp(St), _dp(w), ctypes.byref(J)):
+        raise ValueError("oracle: invalid arguments")
+    return J.value
+
+
+def sq_misfit_complex_step(rep, horizon: int, every: int, field: int, S_target: np.ndarray,
+                           weight: np.ndarray, which: int, h: float = 1e-20,
+                           flags: int = DEFAULT_FLAGS) -> float:
+    """dJ/d(tau_s, tau_d, G)[which] by complex-step differentiation of the
+    oracle (the simulation templated on std::complex<double>)."""
+    _misfit_argtypes()
+    p = params(rep, flags, every)
+    St = np.ascontiguousarray(S_target, dtype=np.float64)
+    w = np.ascontiguousarray(weight, dtype=np.float64)
+    d = ctypes.c_double()
+    if lib().ora_sq_misfit_cs(ctypes.byref(p), horizon, field, _dp(St), _dp(w), which, h,
+                              ctypes.byref(d)):
+        raise ValueError("oracle: invalid arguments")
+    return d.value
