@@ -40,7 +40,7 @@ def _events_time(lat, nsteps):
     return e0.elapsed_time(e1)
 
 
-STEP_SOURCES = ("k_step.hip", "fnlb_device.hpp", "fnlb_internal.hpp")
+STEP_SOURCES = ("k_step.hip", "fnlb_device.hpp", "fnlb_internal.hpp", "fnlb_state.hpp")
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_k_step_batched96_fp32dev.json")
 
 

@@ -183,6 +183,35 @@ int fnlb_get_time(const fnlb_handle* h, int64_t* t);
  * continue a run after fnlb_write_populations.  t >= 0. */
 int fnlb_set_time(fnlb_handle* h, int64_t t);
 
+/* Bytes of the device workspace fnlb_sq_misfit_gradient needs for a horizon
+ * of `horizon` steps with populations checkpointed every `ckpt_every` steps:
+ * ceil(horizon/ckpt_every) + ckpt_every + 2 state copies plus O(Lx Lz)
+ * adjoint fields.  FNLB_EINVAL when the handle does not meet the
+ * requirements of fnlb_sq_misfit_gradient. */
+int fnlb_adjoint_bytes_required(const fnlb_handle* h, int64_t horizon, int32_t ckpt_every,
+                                size_t* bytes);
+
+/* Structure-factor misfit and its gradient by the discrete adjoint of the
+ * step, with the noise stream held fixed (the Gaussian variates of every node
+ * and step are the same at any parameter value).  From the handle's current
+ * state and time, runs `horizon` steps sampling per options.sample_every,
+ * forms S(q) = <|Phi|^2> - |<Phi>|^2 of `field` over the half spectrum
+ * [k_z][k_x] (k_x = 0..Lx/2) and
+ *   J = sum_q weight_q (S(q) - S_target(q))^2,
+ * then sweeps the adjoint backwards over checkpointed segments (populations
+ * stored every ckpt_every steps and recomputed within a segment) and returns
+ * J and grad = dJ/d(tau_s, tau_d, G) (tau_s = 1/lambda_s of Eq. (17),
+ * tau_d = 1/lambda_d of Eq. (16), G of Eq. (11)).  Requirements: one replica,
+ * FNLB_FP64, options.sample_every > 0, flags FNLB_ASTAR | FNLB_WALL_UZ_FIX,
+ * Lx Lz <= 2^20, at least one sample in the horizon.  S_target and weight:
+ * host arrays of Lz (Lx/2 + 1) doubles.  d_adj: caller-owned device
+ * workspace of adj_bytes >= fnlb_adjoint_bytes_required, 256-byte aligned.
+ * The handle's state, time and accumulators are unchanged.  Synchronises
+ * the stream. */
+int fnlb_sq_misfit_gradient(fnlb_handle* h, int32_t field, const double* S_target,
+                            const double* weight, int64_t horizon, int32_t ckpt_every,
+                            void* d_adj, size_t adj_bytes, double* J, double* grad);
+
 /* Frees the handle's host metadata.  Caller buffers are untouched. */
 int fnlb_destroy(fnlb_handle* h);
 

@@ -5,7 +5,8 @@ pressure accumulation) runs in the HIP library ``libfnlb.so`` behind the C ABI
 of ``include/fnlb.h``; this package is its thin Python binding.
 """
 from .fnlb import (ASTAR, DEFAULT_FLAGS, FIELD_C, FIELD_RHO, FORCE_LITERAL, FP32_DEV, FP64,
-                   NO_GRAPH, NOISE_LOC, WALL_UZ_FIX, FnlbError, Lattice, bytes_required, load)
+                   NO_GRAPH, NOISE_LOC, WALL_UZ_FIX, FnlbError, Lattice, bytes_required, load,
+                   sq_misfit)
 
 __all__ = ["ASTAR", "DEFAULT_FLAGS", "FIELD_C", "FIELD_RHO", "FORCE_LITERAL", "FP32_DEV",
-           "FP64", "NO_GRAPH", "NOISE_LOC", "WALL_UZ_FIX", "FnlbError", "Lattice", "bytes_required", "load"]
+           "FP64", "NO_GRAPH", "NOISE_LOC", "WALL_UZ_FIX", "FnlbError", "Lattice", "bytes_required", "load", "sq_misfit"]

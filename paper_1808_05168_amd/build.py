@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfnlb.so")
-SOURCES = ["k_step.hip", "k_observe.hip", "fnlb_api.hip"]
+SOURCES = ["k_step.hip", "k_observe.hip", "k_adjoint.hip", "fnlb_api.hip"]
 ARCH = os.environ.get("FNLB_OFFLOAD_ARCH", "gfx950")
 
 

@@ -286,16 +286,17 @@ StepArgs step_args(fnlb_handle* h, int64_t t_off) {
 }
 
 // Structure-factor transforms and pressure reduction of the sample fields.
-hipError_t observe(fnlb_handle* h, hipStream_t s) {
+hipError_t observe(fnlb_handle* h, hipStream_t s, double* acc = nullptr) {
   const Plan& P = h->plan;
+  if (!acc) acc = (double*)h->accum;
   hipError_t e = launch_row_transform(h->d_reps(), h->d_rows(), (int)P.rows.size(), P.max_lx,
                                       h->d_fields(), h->d_spec(), h->d_tw(), s);
   if (e != hipSuccess) return e;
   e = launch_col_transform(h->d_reps(), h->d_cols(), (int)P.cols.size(), P.max_col_lds,
-                           h->d_spec(), (double*)h->accum, h->d_tw(), s);
+                           h->d_spec(), acc, h->d_tw(), s);
   if (e != hipSuccess) return e;
-  return launch_pressure_reduce(h->d_reps(), (int)P.info.size(), P.max_lz, h->d_ppart(),
-                                (double*)h->accum, s);
+  return launch_pressure_reduce(h->d_reps(), (int)P.info.size(), P.max_lz, h->d_ppart(), acc,
+                                s);
 }
 
 void drop_graphs(fnlb_handle* h) {
@@ -647,6 +648,166 @@ int fnlb_set_time(fnlb_handle* h, int64_t t) {
   if (!h || t < 0) return FNLB_EINVAL;
   if (h->error) return h->error;
   h->t = t;
+  return FNLB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device workspace of the adjoint (byte offsets).
+struct AdjPlan {
+  size_t ckpt = 0, seg = 0, mu = 0, gf = 0, gs = 0, dens = 0, adjf = 0, acc = 0, target = 0,
+         weight = 0, Wq = 0, mean = 0, rows = 0, Gq = 0, tpart = 0, jpart = 0, small = 0,
+         total = 0;
+  int64_t nck = 0;
+};
+
+int adj_plan(const fnlb_handle* h, int64_t horizon, int32_t K, AdjPlan& A) {
+  if (h->reps.size() != 1 || h->opt.precision != FNLB_FP64 || h->opt.sample_every <= 0)
+    return FNLB_EINVAL;
+  if ((h->opt.flags & ~FNLB_NO_GRAPH) != (FNLB_ASTAR | FNLB_WALL_UZ_FIX)) return FNLB_EINVAL;
+  if (horizon < 1 || K < 1) return FNLB_EINVAL;
+  const RepInfo& R = h->plan.info[0];
+  const size_t N = (size_t)R.Lx * R.Lz, P = (size_t)R.Lz * (R.Lx / 2 + 1);
+  if (N > ((size_t)1 << 20)) return FNLB_EINVAL;  // direct spectral sums
+  const size_t SH = h->plan.state_half;
+  A.nck = (horizon + K - 1) / K;
+  size_t o = 0;
+  auto take = [&](size_t& off, size_t bytes) {
+    off = o;
+    o = align_up(o + bytes);
+  };
+  take(A.ckpt, (size_t)A.nck * SH);
+  take(A.seg, (size_t)K * SH);
+  take(A.mu, 2 * SH);
+  take(A.gf, 18 * N * 8);
+  take(A.gs, 4 * N * 8);
+  take(A.dens, 2 * N * 8);
+  take(A.adjf, N * 8);
+  take(A.acc, h->plan.accum_bytes);
+  take(A.target, P * 8);
+  take(A.weight, P * 8);
+  take(A.Wq, P * 8);
+  take(A.mean, P * 16);
+  take(A.rows, P * 16);
+  take(A.Gq, P * 16);
+  take(A.tpart, ((N + 255) / 256) * 3 * 8);
+  take(A.jpart, ((P + 255) / 256) * 8);
+  take(A.small, 64);  // theta accumulator [3], J
+  A.total = o;
+  return FNLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fnlb_adjoint_bytes_required(const fnlb_handle* h, int64_t horizon, int32_t ckpt_every,
+                                size_t* bytes) {
+  if (!h || !bytes) return FNLB_EINVAL;
+  AdjPlan A;
+  const int rc = adj_plan(h, horizon, ckpt_every, A);
+  if (rc) return rc;
+  *bytes = A.total;
+  return FNLB_OK;
+}
+
+int fnlb_sq_misfit_gradient(fnlb_handle* h, int32_t field, const double* S_target,
+                            const double* weight, int64_t horizon, int32_t ckpt_every,
+                            void* d_adj, size_t adj_bytes, double* J, double* grad) {
+  if (!h || !S_target || !weight || !d_adj || !J || !grad || (field != 0 && field != 1))
+    return FNLB_EINVAL;
+  if (h->error) return h->error;
+  AdjPlan A;
+  int rc = adj_plan(h, horizon, ckpt_every, A);
+  if (rc) return rc;
+  if (adj_bytes < A.total) return FNLB_ENOMEM;
+  if ((uintptr_t)d_adj % kAlign) return FNLB_EINVAL;
+  char* W = (char*)d_adj;
+  hipStream_t s = h->stream;
+  const RepInfo& R = h->plan.info[0];
+  const RepInfo* dR = h->d_reps();
+  const size_t SH = h->plan.state_half, N = (size_t)R.Lx * R.Lz;
+  const size_t P = (size_t)R.Lz * (R.Lx / 2 + 1);
+  const int every = h->opt.sample_every;
+  const int64_t t0 = h->t;
+  const int K = ckpt_every;
+  auto ckpt = [&](int64_t k) { return W + A.ckpt + (size_t)k * SH; };
+  auto seg = [&](int64_t k) { return W + A.seg + (size_t)k * SH; };
+  char* mu[2] = {W + A.mu, W + A.mu + SH};
+  double* acc = (double*)(W + A.acc);
+  double* theta = (double*)(W + A.small);
+  double* dJ = theta + 4;
+  auto sampled = [&](int64_t t) { return t >= 1 && t % every == 0; };
+  auto step_from = [&](const char* in, char* out, int64_t t, bool smp) {
+    StepArgs a = step_args(h, t - h->t_dev);
+    a.state_in = in;
+    a.state_out = out;
+    hipError_t e = launch_step(FNLB_FP64, smp ? kStepSample : kStep, a, s);
+    if (e == hipSuccess && smp) e = observe(h, s, acc);
+    return e;
+  };
+
+  hipError_t e = hipMemcpyAsync(W + A.target, S_target, P * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(W + A.weight, weight, P * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_fill_zero(acc, h->plan.accum_bytes, s);
+  if (e == hipSuccess) e = launch_fill_zero(W + A.small, 64, s);
+  // forward sweep: checkpoints every K steps, samples into private sums
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(mu[0], h->state_copy(h->cur), SH, hipMemcpyDeviceToDevice, s);
+  int64_t nsamp = 0;
+  int cur = 0;
+  for (int64_t k = 0; k < horizon && e == hipSuccess; ++k) {
+    if (k % K == 0) e = hipMemcpyAsync(ckpt(k / K), mu[cur], SH, hipMemcpyDeviceToDevice, s);
+    const bool smp = sampled(t0 + k);
+    if (e == hipSuccess) e = step_from(mu[cur], mu[cur ^ 1], t0 + k, smp);
+    if (smp) ++nsamp;
+    cur ^= 1;
+  }
+  if (nsamp == 0) return e == hipSuccess ? FNLB_EINVAL : dev_err(h, e);
+  const double ns = (double)nsamp;
+  if (e == hipSuccess)
+    e = launch_adj_misfit(dR, R, h->d_tw(), acc, (const double*)(W + A.target),
+                          (const double*)(W + A.weight), (double*)(W + A.Wq),
+                          (double2*)(W + A.mean), (double*)(W + A.jpart), field, ns, s);
+  if (e == hipSuccess) e = launch_sum((const double*)(W + A.jpart), (int)((P + 255) / 256), dJ, s);
+  // reverse sweep over the checkpointed segments
+  if (e == hipSuccess) e = launch_fill_zero(mu[0], 2 * SH, s);
+  int nx = 0;  // mu[nx] holds dJ/dS_{t+1}
+  for (int64_t sgi = A.nck - 1; sgi >= 0 && e == hipSuccess; --sgi) {
+    const int64_t ts = sgi * K, te = std::min<int64_t>(horizon, ts + K);
+    e = hipMemcpyAsync(seg(0), ckpt(sgi), SH, hipMemcpyDeviceToDevice, s);
+    for (int64_t k = ts; k + 1 < te && e == hipSuccess; ++k)
+      e = step_from(seg(k - ts), seg(k - ts + 1), t0 + k, false);
+    for (int64_t k = te - 1; k >= ts && e == hipSuccess; --k) {
+      const double* S = (const double*)seg(k - ts);
+      e = launch_adj_density(dR, R, S, (double*)(W + A.dens), s);
+      const double* adjf = nullptr;
+      if (e == hipSuccess && sampled(t0 + k)) {
+        e = launch_adj_sample(dR, R, h->d_tw(), (const double*)(W + A.Wq),
+                              (const double2*)(W + A.mean), field, ns,
+                              (const double*)(W + A.dens), (double2*)(W + A.rows),
+                              (double2*)(W + A.Gq), (double*)(W + A.adjf), s);
+        adjf = (const double*)(W + A.adjf);
+      }
+      if (e == hipSuccess)
+        e = launch_adj_step(dR, R, S, (const double*)mu[nx], (double*)mu[nx ^ 1],
+                            (double*)(W + A.dens), (double*)(W + A.gf), (double*)(W + A.gs),
+                            adjf, field, t0 + k, (double*)(W + A.tpart), theta, s);
+      nx ^= 1;
+    }
+  }
+  double out[5] = {0, 0, 0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(out, theta, 5 * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dev_err(h, e);
+  // dJ/dlambda -> dJ/dtau with lambda = 1/tau
+  const double ls = R.lam[4], ld = R.lam[1];
+  *J = out[4];
+  grad[0] = -ls * ls * out[0];
+  grad[1] = -ld * ld * out[1];
+  grad[2] = out[2];
   return FNLB_OK;
 }
 

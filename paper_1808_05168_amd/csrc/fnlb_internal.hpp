@@ -98,4 +98,21 @@ hipError_t launch_pressure_reduce(const RepInfo* reps, int n_rep, int max_lz,
                                   const double* ppart, double* acc, hipStream_t stream);
 hipError_t launch_advance_time(int64_t* t_base, int64_t dt, hipStream_t stream);
 
+// Adjoint of the step (single replica, FP64 storage); see k_adjoint.hip.
+hipError_t launch_adj_density(const RepInfo* d_rep, const RepInfo& h_rep, const double* state,
+                              double* dens, hipStream_t s);
+hipError_t launch_adj_step(const RepInfo* d_rep, const RepInfo& h_rep, const double* state,
+                           const double* mu_next, double* mu, double* dens, double* gf,
+                           double* gs, const double* adjfield, int field, int64_t t,
+                           double* tpart, double* theta_acc, hipStream_t s);
+hipError_t launch_adj_misfit(const RepInfo* d_rep, const RepInfo& h_rep, const double2* tw,
+                             const double* acc, const double* target, const double* weight,
+                             double* Wq, double2* mean, double* Jpart, int field, double nsamp,
+                             hipStream_t s);
+hipError_t launch_adj_sample(const RepInfo* d_rep, const RepInfo& h_rep, const double2* tw,
+                             const double* Wq, const double2* mean, int field, double nsamp,
+                             const double* dens, double2* rows, double2* Gq, double* adjfield,
+                             hipStream_t s);
+hipError_t launch_sum(const double* parts, int n, double* out, hipStream_t s);
+
 }  // namespace fnlb

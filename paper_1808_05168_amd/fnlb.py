@@ -46,7 +46,7 @@ EXPORTS = ["fnlb_bytes_required", "fnlb_init", "fnlb_step", "fnlb_autotune",
            "fnlb_accumulate_structure_factor", "fnlb_read_structure_factor",
            "fnlb_read_pressure", "fnlb_read_populations", "fnlb_write_populations",
            "fnlb_reset_accumulators", "fnlb_get_time", "fnlb_set_time", "fnlb_destroy",
-           "fnlb_strerror"]
+           "fnlb_strerror", "fnlb_adjoint_bytes_required", "fnlb_sq_misfit_gradient"]
 
 
 def load(path: str = LIB_PATH):
@@ -76,6 +76,9 @@ def load(path: str = LIB_PATH):
     lib.fnlb_get_time.argtypes = [vp, i64p]
     lib.fnlb_set_time.argtypes = [vp, ctypes.c_int64]
     lib.fnlb_destroy.argtypes = [vp]
+    lib.fnlb_adjoint_bytes_required.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, szp]
+    lib.fnlb_sq_misfit_gradient.argtypes = [vp, ctypes.c_int32, dp, dp, ctypes.c_int64,
+                                            ctypes.c_int32, vp, ctypes.c_size_t, dp, dp]
     lib.fnlb_strerror.argtypes = [ctypes.c_int]
     lib.fnlb_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -171,6 +174,29 @@ class Lattice:
                "fnlb_autotune")
         return int(c.value)
 
+    def sq_misfit_gradient(self, S_target: np.ndarray, weight: np.ndarray, horizon: int,
+                           ckpt_every: int = 100, field: int = FIELD_C):
+        """(J, dJ/d(tau_s, tau_d, G)) of J = sum_q w_q (S(q) - S*(q))^2 over
+        `horizon` steps from the current state, by the adjoint of the step."""
+        import torch
+        r = self.reps[0]
+        St = np.ascontiguousarray(S_target, dtype=np.float64).reshape(r.Lz, r.Lx // 2 + 1)
+        w = np.ascontiguousarray(weight, dtype=np.float64).reshape(r.Lz, r.Lx // 2 + 1)
+        nb = ctypes.c_size_t()
+        _check(self._lib.fnlb_adjoint_bytes_required(self._h, int(horizon), int(ckpt_every),
+                                                     ctypes.byref(nb)),
+               "fnlb_adjoint_bytes_required")
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        J = ctypes.c_double()
+        g = np.zeros(3)
+        _check(self._lib.fnlb_sq_misfit_gradient(self._h, field, _dp(St), _dp(w), int(horizon),
+                                                 int(ckpt_every),
+                                                 ctypes.c_void_p(ws.data_ptr()), nb.value,
+                                                 ctypes.byref(J), _dp(g)),
+               "fnlb_sq_misfit_gradient")
+        del ws
+        return J.value, g
+
     def accumulate_structure_factor(self) -> None:
         _check(self._lib.fnlb_accumulate_structure_factor(self._h),
                "fnlb_accumulate_structure_factor")
@@ -224,3 +250,49 @@ class Lattice:
     @time.setter
     def time(self, t: int) -> None:
         _check(self._lib.fnlb_set_time(self._h, int(t)), "fnlb_set_time")
+
+
+def sq_misfit(theta, rep, S_target, weight, horizon: int, sample_every: int,
+              ckpt_every: int = 100, field: int = FIELD_C, device: str = "cuda:0"):
+    """Differentiable structure-factor misfit: theta = tensor([tau_s, tau_d, G]).
+    Forward runs the step from the rest state on the imposed profile; backward
+    returns the adjoint gradient (noise held fixed)."""
+    return _SqMisfit.apply(theta, rep, S_target, weight, horizon, sample_every, ckpt_every,
+                           field, device)
+
+
+def _make_fn():
+    import dataclasses
+
+    import torch
+
+    class SqMisfit(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, theta, rep, S_target, weight, horizon, sample_every, ckpt_every,
+                    field, device):
+            t = [float(v) for v in theta.detach().cpu().tolist()]
+            r = dataclasses.replace(rep, tau_s=t[0], tau_d=t[1], G=t[2])
+            lat = Lattice([r], precision=FP64, sample_every=sample_every, device=device)
+            J, g = lat.sq_misfit_gradient(S_target, weight, horizon, ckpt_every, field)
+            lat.close()
+            ctx.save_for_backward(torch.as_tensor(g, dtype=theta.dtype))
+            return theta.new_tensor(J)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            (g,) = ctx.saved_tensors
+            return (gJ.cpu() * g).to(gJ.device), None, None, None, None, None, None, None, None
+
+    return SqMisfit
+
+
+class _Lazy:
+    fn = None
+
+    def apply(self, *a):
+        if _Lazy.fn is None:
+            _Lazy.fn = _make_fn()
+        return _Lazy.fn.apply(*a)
+
+
+_SqMisfit = _Lazy()

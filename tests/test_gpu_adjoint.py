@@ -1,0 +1,118 @@
+"""GPU adjoint of the step (noise held fixed) against the oracle's
+complex-step derivative and against central finite differences of the GPU
+forward: gradient of J = sum_q w_q (S(q) - S*(q))^2 with respect to
+(tau_s, tau_d, G), S* from a twin run at (tau_s, tau_d, G) x (1.05, 0.95, 1.1)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import say
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    import paper_1808_05168_amd as F
+    F.load()
+    return F
+
+
+def target(rep, horizon, every, field):
+    twin = dataclasses.replace(rep, tau_s=rep.tau_s * 1.05, tau_d=rep.tau_d * 0.95, G=rep.G * 1.1)
+    f = O.init_state(twin)
+    acc = O.Accum(twin.Lx, twin.Lz)
+    O.run(twin, f, 0, horizon, acc, sample_every=every)
+    S = O.structure_factor(acc)[field]
+    w = np.ones_like(S)
+    w[:, 0] = 0.0
+    return S, w
+
+
+SMALL = W.Replica(Lx=32, Lz=16, grad_c0=5e-3, kT=1e-4, G=0.5, tau_s=0.7, tau_d=0.8, seed=3)
+
+
+@pytest.mark.parametrize("field", [0, 1])
+def test_adjoint_matches_complex_step_small(F, field):
+    rep, H, every = SMALL, 120, 10
+    say(f"case: adjoint 32x16 horizon {H} field {field}")
+    S_t, w = target(rep, H, every, field)
+    lat = F.Lattice([rep], precision=F.FP64, sample_every=every)
+    J, g = lat.sq_misfit_gradient(S_t, w, H, ckpt_every=25, field=field)
+    J_o = O.sq_misfit(rep, H, every, field, S_t, w)
+    assert abs(J - J_o) <= 1e-10 * abs(J_o)
+    cs = np.array([O.sq_misfit_complex_step(rep, H, every, field, S_t, w, k) for k in range(3)])
+    say(f"  adjoint {g}  complex-step {cs}")
+    np.testing.assert_allclose(g, cs, rtol=1e-7, atol=1e-9 * np.abs(cs).max())
+
+
+def test_adjoint_independent_of_checkpoint_interval(F):
+    rep, H, every = SMALL, 60, 5
+    S_t, w = target(rep, H, every, 0)
+    res = []
+    for K in (1, 7, 25, 60, 100):
+        lat = F.Lattice([rep], precision=F.FP64, sample_every=every)
+        res.append(lat.sq_misfit_gradient(S_t, w, H, ckpt_every=K))
+    for J, g in res[1:]:
+        assert J == res[0][0]
+        np.testing.assert_array_equal(g, res[0][1])
+
+
+def test_adjoint_leaves_handle_untouched(F):
+    rep, H, every = SMALL, 40, 5
+    S_t, w = target(rep, H, every, 0)
+    lat = F.Lattice([rep], precision=F.FP64, sample_every=every)
+    lat.step(13)
+    f = lat.read_populations(0)
+    a2 = lat.read_structure_factor(0, 0)[0]
+    lat.sq_misfit_gradient(S_t, w, H, ckpt_every=10)
+    assert lat.time == 13
+    np.testing.assert_array_equal(lat.read_populations(0), f)
+    np.testing.assert_array_equal(lat.read_structure_factor(0, 0)[0], a2)
+
+
+def test_autograd_function(F):
+    import torch
+    rep, H, every = SMALL, 60, 10
+    S_t, w = target(rep, H, every, 0)
+    theta = torch.tensor([rep.tau_s, rep.tau_d, rep.G], dtype=torch.float64, requires_grad=True)
+    J = F.sq_misfit(theta, rep, S_t, w, H, every, ckpt_every=20)
+    J.backward()
+    lat = F.Lattice([rep], precision=F.FP64, sample_every=every)
+    J2, g = lat.sq_misfit_gradient(S_t, w, H, ckpt_every=20)
+    assert float(J) == J2
+    np.testing.assert_array_equal(theta.grad.numpy(), g)
+
+
+def test_adjoint_256x128_horizon_2000(F):
+    """256 x 128, G = 0.5, grad c0 = 1e-3, kT = 1e-5, tau_s = 0.7, tau_d = 0.8,
+    2000 steps sampled every 10, checkpoints every 100: adjoint vs central
+    differences of the GPU forward (h = 1e-6 relative) and vs the oracle's
+    complex-step derivative."""
+    rep, H, every = W.adjoint_256x128(), 2000, 10
+    say("case: adjoint 256x128 horizon 2000")
+    S_t, w = target(rep, H, every, 0)
+    lat = F.Lattice([rep], precision=F.FP64, sample_every=every)
+    J, g = lat.sq_misfit_gradient(S_t, w, H, ckpt_every=100)
+    fd = []
+    for name in ("tau_s", "tau_d", "G"):
+        v = getattr(rep, name)
+        h = 1e-6 * v
+        Js = []
+        for sgn in (1, -1):
+            r = dataclasses.replace(rep, **{name: v + sgn * h})
+            lt = F.Lattice([r], precision=F.FP64, sample_every=every)
+            Js.append(lt.sq_misfit_gradient(S_t, w, H, ckpt_every=100)[0])
+        fd.append((Js[0] - Js[1]) / (2 * h))
+    fd = np.array(fd)
+    say(f"  adjoint {g}  central differences {fd}")
+    np.testing.assert_allclose(g, fd, rtol=1e-5)
+    cs = np.array([O.sq_misfit_complex_step(rep, H, every, 0, S_t, w, k) for k in range(3)])
+    say(f"  complex-step {cs}")
+    np.testing.assert_allclose(g, cs, rtol=1e-7)
