@@ -43,6 +43,9 @@
 //       the non-local interaction part (G/4) sum_l w_l |c_l|^2
 //       [rho^A(r) rho^B(r+c_l) + rho^B(r) rho^A(r+c_l)].
 //   R12 the z-transform runs over the L fluid rows with q_z = 2 pi k_z / L.
+//   R17 the velocity fields of S_U(q) (Sec. IV.A, Eq. (25)) are the
+//       barycentric U of Eq. (10) of f(t), after the wall fix, as it enters
+//       the collision of the sampled step (flag ORA_VELOCITY).
 //
 // The simulation is a template on the scalar type so that the same code can
 // be run with std::complex<double> for complex-step differentiation.  The
@@ -162,6 +165,7 @@ enum {
   ORA_WALL_UZ_FIX = 2,    // R7: wall U_z = 0 fix on
   ORA_NOISE_LOC = 4,      // R5: local instead of reference densities in noise
   ORA_FORCE_LITERAL = 8,  // R1: drop (1 - lambda_d/2) on first-order forcing
+  ORA_VELOCITY = 32,      // also sample U_x and U_z (fields 2 and 3)
 };
 
 typedef struct {
@@ -233,9 +237,15 @@ struct Sim {
   // ---------------------------------------------------------------------
   // Observables of one sample (Appendix and Sec. IV.C).
   // ---------------------------------------------------------------------
-  // delta-fields: field 0 = c - c_0(z), field 1 = rho - rho_bar
-  void delta_fields(const std::vector<T>& rho, std::vector<T>& phi) const {
-    phi.assign(2 * n, T(0));
+  // number of sampled fields: delta c and delta rho, plus U_x and U_z when
+  // the velocity structure factors are requested
+  int nfields() const { return (p.flags & ORA_VELOCITY) ? 4 : 2; }
+
+  // delta-fields: field 0 = c - c_0(z), field 1 = rho - rho_bar; with
+  // ORA_VELOCITY also field 2 = U_x, field 3 = U_z (the mean velocity is zero,
+  // so U itself is the fluctuation; reading R17)
+  void delta_fields(const T* f, const std::vector<T>& rho, std::vector<T>& phi) const {
+    phi.assign((size_t)nfields() * n, T(0));
     for (int j = 0; j < Lz; ++j)
       for (int x = 0; x < Lx; ++x) {
         const size_t k = (size_t)j * Lx + x;
@@ -243,6 +253,14 @@ struct Sim {
         const T r = ra + rb;
         phi[k] = ra / r - c0_of(j);
         phi[n + k] = r - p.rho0;
+        if (nfields() == 4) {
+          T fl[2][Q], F[2][2], ux, uz;
+          for (int s = 0; s < 2; ++s)
+            for (int l = 0; l < Q; ++l) fl[s][l] = f[idx(s, l, j, x)];
+          macros(rho, x, j, fl, F, ux, uz);
+          phi[2 * n + k] = ux;
+          phi[3 * n + k] = uz;
+        }
       }
   }
 
@@ -267,7 +285,7 @@ struct Sim {
       sz[m] = std::sin(two_pi * m / Lz);
     }
     const size_t plane = (size_t)Lz * nkx;
-    for (int fld = 0; fld < 2; ++fld) {
+    for (int fld = 0; fld < nfields(); ++fld) {
       const T* d = phi.data() + (size_t)fld * n;
       // row transform: R(kx, j) = sum_x d(x,j) e^{-i 2 pi kx x / Lx}
       std::vector<T> rr((size_t)Lz * nkx), ri((size_t)Lz * nkx);
@@ -432,7 +450,7 @@ struct Sim {
 
     if (sample) {
       std::vector<T> phi;
-      delta_fields(rho, phi);
+      delta_fields(f, rho, phi);
       if (sq) accumulate_sq(phi, sq);
       if (psum) accumulate_pressure(rho, psum, psum2, prof);
       if (nsamp) ++*nsamp;
@@ -654,7 +672,8 @@ int ora_check_params(const ora_params* p) { return check_params(p); }
 // --- whole-lattice entry points ---
 
 // Layouts: f[s][l][j][x] (s = A,B; l = 0..8; j = 0..Lz-1; x = 0..Lx-1).
-// sq[field][kind][kz][kx], field 0 = delta c, 1 = delta rho;
+// sq[field][kind][kz][kx], field 0 = delta c, 1 = delta rho, and with
+// ORA_VELOCITY 2 = U_x, 3 = U_z;
 // kind 0 = sum |Phi|^2, 1 = sum Re Phi, 2 = sum Im Phi; kx = 0..Lx/2.
 // pr = {sum_dP, sum_dP2}, prof[Lz] = sum of row means of P - P_ref.
 
@@ -683,7 +702,7 @@ int ora_sample(const ora_params* p, const double* f, double* sq, double* pr,
   Sim<double> sim(*p, th);
   std::vector<double> rho, phi;
   sim.densities(f, rho);
-  sim.delta_fields(rho, phi);
+  sim.delta_fields(f, rho, phi);
   if (sq) sim.accumulate_sq(phi, sq);
   if (pr) sim.accumulate_pressure(rho, pr, pr + 1, prof);
   if (nsamp) ++*nsamp;
@@ -691,7 +710,7 @@ int ora_sample(const ora_params* p, const double* f, double* sq, double* pr,
 }
 
 // Fields of the current state: rho[s][j][x] (2 planes) and
-// dphi[field][j][x] (delta c, delta rho).
+// dphi[field][j][x] (delta c, delta rho, and U_x, U_z with ORA_VELOCITY).
 int ora_fields(const ora_params* p, const double* f, double* rho_out,
                double* dphi_out) {
   if (check_params(p)) return -1;
@@ -699,7 +718,7 @@ int ora_fields(const ora_params* p, const double* f, double* rho_out,
   Sim<double> sim(*p, th);
   std::vector<double> rho, phi;
   sim.densities(f, rho);
-  sim.delta_fields(rho, phi);
+  sim.delta_fields(f, rho, phi);
   if (rho_out) std::memcpy(rho_out, rho.data(), sizeof(double) * rho.size());
   if (dphi_out) std::memcpy(dphi_out, phi.data(), sizeof(double) * phi.size());
   return 0;
@@ -742,7 +761,7 @@ T sq_misfit(const ora_params& p, const Theta<T>& th, int64_t horizon, int field,
   Sim<T> sim(p, th);
   const int nkx = p.Lx / 2 + 1;
   const size_t plane = (size_t)p.Lz * nkx;
-  std::vector<T> f((size_t)2 * Q * sim.n), sq(6 * plane, T(0));
+  std::vector<T> f((size_t)2 * Q * sim.n), sq((size_t)3 * sim.nfields() * plane, T(0));
   sim.init(f.data());
   int64_t ns = 0;
   sim.run(f.data(), 0, horizon, sq.data(), nullptr, nullptr, nullptr, &ns);

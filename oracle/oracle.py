@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
 CPU-baseline leg of the benchmark, never by the GPU library.  All arrays are
 numpy float64 in the oracle's own layouts:
   f     [2 species][9 links][Lz][Lx]
-  sq    [2 fields (delta c, delta rho)][3 (sum |Phi|^2, sum Re, sum Im)][Lz][Lx//2+1]
+  sq    [fields][3 (sum |Phi|^2, sum Re, sum Im)][Lz][Lx//2+1]; fields are
+        (delta c, delta rho), plus (U_x, U_z) when VELOCITY is set
   pr    [2] = (sum of spatial means of P - P_ref, sum of their squares)
   prof  [Lz] = sum of row means of P - P_ref
 """
@@ -20,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fnlb_oracle.cpp")
 _LIB = os.path.join(_HERE, "libfnlb_oracle.so")
 
-ASTAR, WALL_UZ_FIX, NOISE_LOC, FORCE_LITERAL = 1, 2, 4, 8
+ASTAR, WALL_UZ_FIX, NOISE_LOC, FORCE_LITERAL, VELOCITY = 1, 2, 4, 8, 32
 DEFAULT_FLAGS = ASTAR | WALL_UZ_FIX
 
 
@@ -88,8 +89,8 @@ def params(rep, flags: int = DEFAULT_FLAGS, sample_every: int = 0) -> OraParams:
 class Accum:
     """Oracle-side accumulators for one lattice."""
 
-    def __init__(self, Lx: int, Lz: int):
-        self.sq = np.zeros((2, 3, Lz, Lx // 2 + 1))
+    def __init__(self, Lx: int, Lz: int, nfields: int = 2):
+        self.sq = np.zeros((nfields, 3, Lz, Lx // 2 + 1))
         self.pr = np.zeros(2)
         self.prof = np.zeros(Lz)
         self.n = ctypes.c_int64(0)
@@ -136,11 +137,12 @@ def sample(rep, f: np.ndarray, acc: Accum, flags: int = DEFAULT_FLAGS) -> None:
         raise ValueError("oracle: invalid parameters")
 
 
-def fields(rep, f: np.ndarray):
-    """Returns (rho[2][Lz][Lx], dphi[2][Lz][Lx]) of the state f."""
-    p = params(rep)
+def fields(rep, f: np.ndarray, flags: int = DEFAULT_FLAGS):
+    """Returns (rho[2][Lz][Lx], dphi[nf][Lz][Lx]) of the state f, nf = 4 with
+    VELOCITY in flags (delta c, delta rho, U_x, U_z), else 2."""
+    p = params(rep, flags)
     rho = np.zeros((2, rep.Lz, rep.Lx))
-    dphi = np.zeros((2, rep.Lz, rep.Lx))
+    dphi = np.zeros((4 if flags & VELOCITY else 2, rep.Lz, rep.Lx))
     if lib().ora_fields(ctypes.byref(p), _dp(f), _dp(rho), _dp(dphi)) != 0:
         raise ValueError("oracle: invalid parameters")
     return rho, dphi
@@ -187,7 +189,7 @@ def forcing_moments(ux: float, uz: float, fx: float, fz: float) -> np.ndarray:
 
 
 def structure_factor(acc: Accum) -> np.ndarray:
-    """S = mean |Phi|^2 - |mean Phi|^2 per field, shape [2][Lz][Lx//2+1]."""
+    """S = mean |Phi|^2 - |mean Phi|^2 per field, shape [nf][Lz][Lx//2+1]."""
     n = max(acc.n_samples, 1)
     m2 = acc.sq[:, 0] / n
     mr = acc.sq[:, 1] / n

@@ -22,11 +22,12 @@ def _random_state(ora, rep, seed):
 def test_structure_factor_matches_fft_and_parseval(ora, Lx, Lz):
     rep = W.Replica(Lx=Lx, Lz=Lz, grad_c0=0.01)
     f = _random_state(ora, rep, Lx * Lz)
-    acc = ora.Accum(Lx, Lz)
-    ora.sample(rep, f, acc)
-    _, dphi = ora.fields(rep, f)
+    flags = ora.DEFAULT_FLAGS | ora.VELOCITY
+    acc = ora.Accum(Lx, Lz, nfields=4)
+    ora.sample(rep, f, acc, flags=flags)
+    _, dphi = ora.fields(rep, f, flags=flags)
     nkx = Lx // 2 + 1
-    for fld in range(2):
+    for fld in range(4):
         Phi = np.fft.fft2(dphi[fld]) / np.sqrt(Lx * Lz)   # [kz][kx]
         np.testing.assert_allclose(acc.sq[fld, 1], Phi.real[:, :nkx], atol=1e-15)
         np.testing.assert_allclose(acc.sq[fld, 2], Phi.imag[:, :nkx], atol=1e-15)
