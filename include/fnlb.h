@@ -59,11 +59,16 @@ extern "C" {
                                 the (1 - lambda_d/2) factor (diagnostic) */
 #define FNLB_NO_GRAPH 16      /* execution only: launch every step directly
                                 instead of replaying captured graphs */
+#define FNLB_SAMPLE_VELOCITY 32 /* also sample U_x and U_z (fields 2, 3): the
+                                barycentric velocity of Eq. (10) after the wall
+                                fix, for S_U(q) of Sec. IV.A, Eq. (31) */
 #define FNLB_DEFAULT_FLAGS (FNLB_ASTAR | FNLB_WALL_UZ_FIX)
 
 /* ---- fields of the structure factor ---- */
 #define FNLB_FIELD_C 0   /* delta c   = rho^A/rho - c_0(z) */
 #define FNLB_FIELD_RHO 1 /* delta rho = rho - rho_bar */
+#define FNLB_FIELD_UX 2  /* U_x (needs FNLB_SAMPLE_VELOCITY) */
+#define FNLB_FIELD_UZ 3  /* U_z (needs FNLB_SAMPLE_VELOCITY) */
 
 /* One lattice ("replica").  Sec. III.A: Lx x Lz nodes, x periodic, walls half
  * a link outside rows 0 and Lz-1, reference density rho_bar, c_bar0 = 1/2. */
@@ -137,15 +142,17 @@ int fnlb_step(fnlb_handle* h, int64_t n);
 int fnlb_autotune(fnlb_handle* h, int32_t steps_per_trial, int32_t* chunk_rows_out);
 
 /* Samples the current state f(t) of every replica now: adds |Phi(q)|^2,
- * Re Phi(q), Im Phi(q) of delta c and delta rho, with
+ * Re Phi(q), Im Phi(q) of delta c and delta rho (and of U_x, U_z with
+ * FNLB_SAMPLE_VELOCITY), with
  * Phi(q) = (Lx Lz)^{-1/2} sum_{x,j} delta phi(x,j) exp(-i (q_x x + q_z j)),
  * q_x = 2 pi k_x / Lx, q_z = 2 pi k_z / Lz, to the structure-factor
  * accumulators, and the spatial mean of P - P_ref (its square, and its row
  * means) to the pressure accumulators.  Asynchronous. */
 int fnlb_accumulate_structure_factor(fnlb_handle* h);
 
-/* Copies the structure-factor sums of replica rep, field FNLB_FIELD_C or
- * FNLB_FIELD_RHO, into host arrays of Lz * (Lx/2 + 1) doubles laid out
+/* Copies the structure-factor sums of replica rep, field FNLB_FIELD_C,
+ * FNLB_FIELD_RHO, or (with FNLB_SAMPLE_VELOCITY, else FNLB_EINVAL)
+ * FNLB_FIELD_UX / FNLB_FIELD_UZ, into host arrays of Lz * (Lx/2 + 1) doubles laid out
  * [k_z][k_x] (k_x = 0..Lx/2); any of the three may be NULL.  S(q) =
  * sum_abs2/n - (sum_re/n)^2 - (sum_im/n)^2.  Synchronises the stream. */
 int fnlb_read_structure_factor(fnlb_handle* h, int32_t rep, int32_t field,

@@ -4,9 +4,10 @@ The hot path (collision, forcing, noise, streaming, structure-factor and
 pressure accumulation) runs in the HIP library ``libfnlb.so`` behind the C ABI
 of ``include/fnlb.h``; this package is its thin Python binding.
 """
-from .fnlb import (ASTAR, DEFAULT_FLAGS, FIELD_C, FIELD_RHO, FORCE_LITERAL, FP32_DEV, FP64,
-                   NO_GRAPH, NOISE_LOC, WALL_UZ_FIX, FnlbError, Lattice, bytes_required, load,
-                   sq_misfit)
+from .fnlb import (ASTAR, DEFAULT_FLAGS, FIELD_C, FIELD_RHO, FIELD_UX, FIELD_UZ, FORCE_LITERAL,
+                   FP32_DEV, FP64, NO_GRAPH, NOISE_LOC, SAMPLE_VELOCITY, WALL_UZ_FIX, FnlbError,
+                   Lattice, bytes_required, load, sq_misfit)
 
-__all__ = ["ASTAR", "DEFAULT_FLAGS", "FIELD_C", "FIELD_RHO", "FORCE_LITERAL", "FP32_DEV",
-           "FP64", "NO_GRAPH", "NOISE_LOC", "WALL_UZ_FIX", "FnlbError", "Lattice", "bytes_required", "load", "sq_misfit"]
+__all__ = ["ASTAR", "DEFAULT_FLAGS", "FIELD_C", "FIELD_RHO", "FIELD_UX", "FIELD_UZ",
+           "FORCE_LITERAL", "FP32_DEV", "FP64", "NO_GRAPH", "NOISE_LOC", "SAMPLE_VELOCITY",
+           "WALL_UZ_FIX", "FnlbError", "Lattice", "bytes_required", "load", "sq_misfit"]

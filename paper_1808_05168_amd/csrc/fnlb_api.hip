@@ -34,7 +34,8 @@ int validate(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options*
   if (opt->precision != FNLB_FP64 && opt->precision != FNLB_FP32_DEV) return FNLB_EINVAL;
   if (opt->sample_every < 0 || opt->chunk_rows < 0) return FNLB_EINVAL;
   if (opt->flags &
-      ~(FNLB_ASTAR | FNLB_WALL_UZ_FIX | FNLB_NOISE_LOC | FNLB_FORCE_LITERAL | FNLB_NO_GRAPH))
+      ~(FNLB_ASTAR | FNLB_WALL_UZ_FIX | FNLB_NOISE_LOC | FNLB_FORCE_LITERAL | FNLB_NO_GRAPH |
+        FNLB_SAMPLE_VELOCITY))
     return FNLB_EINVAL;
   for (int r = 0; r < n_rep; ++r) {
     const fnlb_replica_params& p = reps[r];
@@ -67,6 +68,7 @@ struct Plan {
          o_spec = 0, o_ppart = 0;
   size_t item_capacity = 0;  // items the work buffer holds (row ranges of one row)
   int max_lx = 0, max_lz = 0, max_col_lds = 0, chunk = 0;
+  int n_pairs = 1;  // complex row transforms per row: (dc, drho) [, (Ux, Uz)]
 };
 
 // work items for a row-range length: (replica, row range, segment), with
@@ -122,6 +124,9 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
   if (chunk <= 0) chunk = auto_chunk(reps, n_rep);
   P.info.assign(n_rep, RepInfo{});
   int64_t state_elems = 0, field_d = 0, spec_c = 0, acc_d = 0, ppart_d = 0, tw_c = 0;
+  // sampled fields: (delta c, delta rho) and, on request, (U_x, U_z)
+  const int nf = n_fields(opt->flags);
+  P.n_pairs = nf / 2;
   const int64_t elem_align = (int64_t)(kAlign / P.store_size);
   for (int r = 0; r < n_rep; ++r) {
     const fnlb_replica_params& p = reps[r];
@@ -135,11 +140,11 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
     state_elems += 18 * R.plane;
     const int nkx = p.Lx / 2 + 1;
     R.field_off = field_d;
-    field_d += 2LL * p.Lz * p.Lx;
+    field_d += (int64_t)nf * p.Lz * p.Lx;
     R.spec_off = spec_c;
-    spec_c += 2LL * p.Lz * nkx;
+    spec_c += (int64_t)nf * p.Lz * nkx;
     R.acc_off = acc_d;
-    acc_d += 6LL * p.Lz * nkx;
+    acc_d += 3LL * nf * p.Lz * nkx;
     R.pacc_off = acc_d;
     acc_d += 2 + p.Lz;
     R.ppart_off = ppart_d;
@@ -195,7 +200,7 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
     for (int j = 0; j < R.Lz; ++j) P.rows.push_back(RowRef{r, j});
     const int nkx = R.Lx / 2 + 1;
     const int tile = std::max(1, std::min(16, kColTile / R.Lz));
-    for (int f = 0; f < 2; ++f)
+    for (int f = 0; f < nf; ++f)
       for (int k0 = 0; k0 < nkx; k0 += tile) {
         const int nc = std::min(tile, nkx - k0);
         P.cols.push_back(ColRef{r, f, k0, nc});
@@ -289,8 +294,8 @@ StepArgs step_args(fnlb_handle* h, int64_t t_off) {
 hipError_t observe(fnlb_handle* h, hipStream_t s, double* acc = nullptr) {
   const Plan& P = h->plan;
   if (!acc) acc = (double*)h->accum;
-  hipError_t e = launch_row_transform(h->d_reps(), h->d_rows(), (int)P.rows.size(), P.max_lx,
-                                      h->d_fields(), h->d_spec(), h->d_tw(), s);
+  hipError_t e = launch_row_transform(h->d_reps(), h->d_rows(), (int)P.rows.size(), P.n_pairs,
+                                      P.max_lx, h->d_fields(), h->d_spec(), h->d_tw(), s);
   if (e != hipSuccess) return e;
   e = launch_col_transform(h->d_reps(), h->d_cols(), (int)P.cols.size(), P.max_col_lds,
                            h->d_spec(), acc, h->d_tw(), s);
@@ -540,7 +545,8 @@ int fnlb_accumulate_structure_factor(fnlb_handle* h) {
 
 int fnlb_read_structure_factor(fnlb_handle* h, int32_t rep, int32_t field, double* sum_abs2,
                                double* sum_re, double* sum_im, int64_t* n_samples) {
-  if (!h || rep < 0 || rep >= (int)h->reps.size() || (field != 0 && field != 1))
+  if (!h || rep < 0 || rep >= (int)h->reps.size() || field < 0 ||
+      field >= n_fields(h->opt.flags))
     return FNLB_EINVAL;
   if (h->error) return h->error;
   const RepInfo& R = h->plan.info[rep];
@@ -740,12 +746,16 @@ int fnlb_sq_misfit_gradient(fnlb_handle* h, int32_t field, const double* S_targe
   double* theta = (double*)(W + A.small);
   double* dJ = theta + 4;
   auto sampled = [&](int64_t t) { return t >= 1 && t % every == 0; };
-  auto step_from = [&](const char* in, char* out, int64_t t, bool smp) {
+  // The step of a sample time runs the sampling variant of the step kernel
+  // both in the forward sweep and when a segment is recomputed, so that every
+  // recomputed state is bit-identical to the forward one whatever the
+  // checkpoint interval (the two kernel variants may round differently).
+  auto step_from = [&](const char* in, char* out, int64_t t, bool observe_sample) {
     StepArgs a = step_args(h, t - h->t_dev);
     a.state_in = in;
     a.state_out = out;
-    hipError_t e = launch_step(FNLB_FP64, smp ? kStepSample : kStep, a, s);
-    if (e == hipSuccess && smp) e = observe(h, s, acc);
+    hipError_t e = launch_step(FNLB_FP64, sampled(t) ? kStepSample : kStep, a, s);
+    if (e == hipSuccess && observe_sample && sampled(t)) e = observe(h, s, acc);
     return e;
   };
 
@@ -760,9 +770,8 @@ int fnlb_sq_misfit_gradient(fnlb_handle* h, int32_t field, const double* S_targe
   int cur = 0;
   for (int64_t k = 0; k < horizon && e == hipSuccess; ++k) {
     if (k % K == 0) e = hipMemcpyAsync(ckpt(k / K), mu[cur], SH, hipMemcpyDeviceToDevice, s);
-    const bool smp = sampled(t0 + k);
-    if (e == hipSuccess) e = step_from(mu[cur], mu[cur ^ 1], t0 + k, smp);
-    if (smp) ++nsamp;
+    if (e == hipSuccess) e = step_from(mu[cur], mu[cur ^ 1], t0 + k, true);
+    if (sampled(t0 + k)) ++nsamp;
     cur ^= 1;
   }
   if (nsamp == 0) return e == hipSuccess ? FNLB_EINVAL : dev_err(h, e);

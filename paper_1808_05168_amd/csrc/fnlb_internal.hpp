@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "fnlb.h"
+
 #include <cstddef>
 #include <cstdint>
 
@@ -19,6 +21,9 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kSeg = kBlock;
 constexpr int kRowAlign = 64;
+
+// sampled real fields: delta c, delta rho, and U_x, U_z on request
+inline int n_fields(int flags) { return (flags & FNLB_SAMPLE_VELOCITY) ? 4 : 2; }
 
 // Everything a kernel needs about one replica.  Filled on the host, copied to
 // the work buffer once at init, read by the kernels with scalar loads.
@@ -89,7 +94,7 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t stream);
 hipError_t launch_twiddles(const RepInfo* d_reps, const RepInfo* h_reps, int n_rep,
                            double2* tw_base, hipStream_t stream);
 hipError_t launch_row_transform(const RepInfo* reps, const RowRef* rows, int n_rows,
-                                int max_lx, const double* fields, double2* spec,
+                                int n_pairs, int max_lx, const double* fields, double2* spec,
                                 const double2* tw, hipStream_t stream);
 hipError_t launch_col_transform(const RepInfo* reps, const ColRef* cols, int n_cols,
                                 int max_lds_cols, const double2* spec, double* acc,

@@ -1,10 +1,11 @@
-// Observables of a sample: structure factors of delta c and delta rho
-// (Appendix, Eqs. (A1)-(A4): Phi(q) = (Lx Lz)^{-1/2} sum_{x,j} dphi e^{-i q.r},
-// S(q) = <|Phi(q)|^2> on the lattice) and the mean pressure (Sec. IV.C).
+// Observables of a sample: structure factors of delta c and delta rho, and
+// optionally of U_x and U_z (Appendix, Eqs. (A1)-(A4): Phi(q) = (Lx Lz)^{-1/2}
+// sum_{x,j} dphi e^{-i q.r}, S(q) = <|Phi(q)|^2> on the lattice; Sec. IV.A for
+// S_U) and the mean pressure (Sec. IV.C).
 //
-// The step kernel writes the real fields delta c and delta rho of a sample.
-// A row pass transforms both fields of a row at once as one complex sequence
-// z = delta c + i delta rho and splits the result by Hermitian symmetry into
+// The step kernel writes the real fields of a sample.  A row pass transforms
+// two fields of a row at once as one complex sequence (z = delta c + i delta
+// rho, and z = U_x + i U_z) and splits the result by Hermitian symmetry into
 // the half spectra k_x = 0..Lx/2; a column pass transforms each k_x column
 // over the Lz rows and adds |Phi|^2, Re Phi and Im Phi to the FP64
 // accumulators.  Power-of-two lengths use an in-LDS radix-2 FFT; other
@@ -76,17 +77,18 @@ __device__ void lds_fft(double2* buf, int N, int ncol, const double2* tw) {
   __syncthreads();
 }
 
-// Row pass: one block per (replica, row).
+// Row pass: one block per (replica, row) and field pair (blockIdx.y).
 __global__ void k_row_transform(const RepInfo* reps, const RowRef* rows, const double* fields,
                                 double2* spec, const double2* tw_base) {
   extern __shared__ double2 lds[];
   const RowRef rr = rows[blockIdx.x];
   const RepInfo& R = reps[rr.rep];
   const int N = R.Lx, Lz = R.Lz, nkx = N / 2 + 1;
-  const double* fc = fields + R.field_off + (size_t)rr.j * N;
+  const size_t row = (size_t)(2 * blockIdx.y) * Lz + rr.j;  // first field of the pair
+  const double* fc = fields + R.field_off + row * N;
   const double* fr = fc + (size_t)Lz * N;
   const double2* tw = tw_base + R.tw_off;
-  double2* out_c = spec + R.spec_off + (size_t)rr.j * nkx;
+  double2* out_c = spec + R.spec_off + row * nkx;
   double2* out_r = out_c + (size_t)Lz * nkx;
   if (R.pow2) {
     const int bits = __ffs(N) - 1;
@@ -241,13 +243,13 @@ hipError_t launch_twiddles(const RepInfo* d_reps, const RepInfo* h_reps, int n_r
   return hipGetLastError();
 }
 
-hipError_t launch_row_transform(const RepInfo* reps, const RowRef* rows, int n_rows, int max_lx,
-                                const double* fields, double2* spec, const double2* tw,
-                                hipStream_t stream) {
+hipError_t launch_row_transform(const RepInfo* reps, const RowRef* rows, int n_rows, int n_pairs,
+                                int max_lx, const double* fields, double2* spec,
+                                const double2* tw, hipStream_t stream) {
   if (n_rows <= 0) return hipSuccess;
   const size_t lds = (size_t)max_lx * sizeof(double2);
-  hipLaunchKernelGGL(k_row_transform, dim3(n_rows), dim3(256), lds, stream, reps, rows, fields,
-                     spec, tw);
+  hipLaunchKernelGGL(k_row_transform, dim3(n_rows, n_pairs), dim3(256), lds, stream, reps, rows,
+                     fields, spec, tw);
   return hipGetLastError();
 }
 

@@ -264,10 +264,38 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
                                         (rBd + (double)bEm) + (rBd + (double)bWm));
       const double dP =
           drho * (1.0 / 3.0) + R.G * 0.25 * (rhoA * sB + rhoB * sA) - (R.p_ref - rho0 / 3.0);
+      // barycentric velocity of Eq. (10) as the collision sees it (after the
+      // wall fix, which zeroes U_z on the wall rows and leaves j_x alone); the
+      // total force is the non-ideal one, -G (rho^A s^B + rho^B s^A), since
+      // the a_* and non-equilibrium parts cancel between the species
+      double ux = 0.0, uz = 0.0;
+      if (flags & FNLB_SAMPLE_VELOCITY) {
+        double d[9];
+#pragma unroll
+        for (int l = 0; l < 9; ++l) d[l] = (double)cur[l] + (double)cur[9 + l];
+        const double jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+        const double jz = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+        const double vAx = (1.0 / 9.0) * (double)(aEc - aWc) +
+                           (1.0 / 36.0) * (double)((aEp - aWp) + (aEm - aWm));
+        const double vBx = (1.0 / 9.0) * (double)(bEc - bWc) +
+                           (1.0 / 36.0) * (double)((bEp - bWp) + (bEm - bWm));
+        const double vAz = (1.0 / 9.0) * (double)(dAp - dAm) +
+                           (1.0 / 36.0) * (double)((aEp + aWp) - (aEm + aWm)) + szref;
+        const double vBz = (1.0 / 9.0) * (double)(dBp - dBm) +
+                           (1.0 / 36.0) * (double)((bEp + bWp) - (bEm + bWm)) - szref;
+        const double Fx = -R.G * (rhoA * vBx + rhoB * vAx);
+        const double Fz = -R.G * (rhoA * vBz + rhoB * vAz);
+        ux = (jx + 0.5 * Fx) / rho;
+        uz = ((flags & FNLB_WALL_UZ_FIX) && (bot || top)) ? 0.0 : (jz + 0.5 * Fz) / rho;
+      }
       if (act) {
         double* fld = a.fields + R.field_off;
         fld[(int64_t)j * Lx + x] = dc;
         fld[(int64_t)(Lz + j) * Lx + x] = drho;
+        if (flags & FNLB_SAMPLE_VELOCITY) {
+          fld[(int64_t)(2 * Lz + j) * Lx + x] = ux;
+          fld[(int64_t)(3 * Lz + j) * Lx + x] = uz;
+        }
         const bool bad = !(rhoA > 0.0) || !(rhoB > 0.0) || !(dc + c0 > 0.0) ||
                          !(dc + c0 < 1.0) || !isfinite(dP);
         if (bad) atomicOr(a.watchdog, 1);

@@ -18,9 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libfnlb.so")
 
 FNLB_OK = 0
 FP64, FP32_DEV = 0, 1
-ASTAR, WALL_UZ_FIX, NOISE_LOC, FORCE_LITERAL, NO_GRAPH = 1, 2, 4, 8, 16
+ASTAR, WALL_UZ_FIX, NOISE_LOC, FORCE_LITERAL, NO_GRAPH, SAMPLE_VELOCITY = 1, 2, 4, 8, 16, 32
 DEFAULT_FLAGS = ASTAR | WALL_UZ_FIX
-FIELD_C, FIELD_RHO = 0, 1
+FIELD_C, FIELD_RHO, FIELD_UX, FIELD_UZ = 0, 1, 2, 3
 
 
 class ReplicaParams(ctypes.Structure):

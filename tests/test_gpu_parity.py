@@ -80,6 +80,15 @@ VARIANTS = {
     "noiseless": (W.Replica(Lx=32, Lz=16, grad_c0=0.01, kT=0.0, G=0.5, seed=20), None, 500, 50),
     "large_seed_and_time": (W.Replica(Lx=32, Lz=8, grad_c0=0.0, kT=1e-4, seed=(1 << 63) + 5),
                             None, 50, 5),
+    # velocity structure factors: direct-sum (non-power-of-two) and FFT paths,
+    # with and without the wall fix and the a_* correction
+    "velocity_ragged": (W.Replica(Lx=100, Lz=20, grad_c0=5e-3, kT=1e-4, G=0.5, tau_s=0.7,
+                                  tau_d=0.8, seed=25), W.DEFAULT_FLAGS | W.SAMPLE_VELOCITY, 300, 7),
+    "velocity_pow2_two_segments": (W.Replica(Lx=512, Lz=32, grad_c0=2e-3, kT=1e-4, G=0.5,
+                                             seed=26), W.DEFAULT_FLAGS | W.SAMPLE_VELOCITY,
+                                   150, 5),
+    "velocity_no_wall_fix_no_astar": (W.Replica(Lx=64, Lz=16, grad_c0=5e-3, kT=1e-4, G=0.8,
+                                                seed=27), W.SAMPLE_VELOCITY, 200, 5),
 }
 
 
@@ -176,6 +185,16 @@ def test_zero_steps_is_a_no_op(F):
     assert lat.time == 0
 
 
+def test_velocity_fields_need_the_flag(F):
+    rep = W.Replica(Lx=16, Lz=8, kT=1e-4, seed=44)
+    lat = F.Lattice([rep], precision=F.FP64, sample_every=2)
+    lat.step(4)
+    lat.read_structure_factor(0, F.FIELD_RHO)
+    for fld in (F.FIELD_UX, F.FIELD_UZ, 4, -1):
+        with pytest.raises(F.FnlbError):
+            lat.read_structure_factor(0, fld)
+
+
 def test_watchdog_reports_bad_state(F):
     # a state with negative density is an input the kernels process normally;
     # the sample flags it and the next read reports it
@@ -191,15 +210,16 @@ def test_watchdog_reports_bad_state(F):
 
 # ---------------------------------------------------------------- FP32 form
 
-@pytest.mark.parametrize("case", ["64x32_full", "nonideal_ragged"])
+@pytest.mark.parametrize("case", ["64x32_full", "nonideal_ragged", "velocity_ragged"])
 def test_parity_fp32_deviation(F, case):
     if case == "64x32_full":
-        rep, nsteps, every = W.parity_small(), 5000, 10
+        rep, flags, nsteps, every = W.parity_small(), None, 5000, 10
     else:
-        rep, _, nsteps, every = VARIANTS["nonideal_ragged"]
+        rep, flags, nsteps, every = VARIANTS[case]
+    flags = W.DEFAULT_FLAGS if flags is None else flags
     say(f"case: fp32-dev {case}")
-    lat = _gpu_run(F, [rep], nsteps, F.FP32_DEV, every)
-    f_o, acc = run_oracle(rep, nsteps, every=every)
+    lat = _gpu_run(F, [rep], nsteps, F.FP32_DEV, every, flags)
+    f_o, acc = run_oracle(rep, nsteps, every=every, flags=flags)
     err = dev_norm(lat.read_populations(0), f_o, rep)
     say(f"  fp32 population deviation error {err:.3e}")
     assert err <= TOL32

@@ -20,6 +20,7 @@ WALL_UZ_FIX = 2      # U_z = 0 on the wall rows (Sec. III.A)
 NOISE_LOC = 4        # local instead of reference densities in the noise
 FORCE_LITERAL = 8    # first-order forcing without (1 - lambda_d/2) (tests only)
 NO_GRAPH = 16        # execution only: no graph replay
+SAMPLE_VELOCITY = 32 # also sample U_x, U_z for the velocity structure factors
 DEFAULT_FLAGS = ASTAR | WALL_UZ_FIX
 
 
