@@ -1,0 +1,278 @@
+"""Experiments composed from the library, and post-processing of its sums.
+
+* ``ne_pressure``: the non-equilibrium pressure protocol of Sec. IV.C
+  (Eqs. (41)-(42)): for each wall-to-wall size L, runs at kT = 0 and at the
+  chosen kT, at grad c0 = 0 and at each chosen gradient, and
+  P_NE(L, kT, grad c0) = P(L, kT, grad c0) - P(L, 0, grad c0) - Delta P_eq(L, kT)
+  with Delta P_eq(L, kT) = P(L, kT, 0) - P(L, 0, 0).  All runs of a scan are
+  replicas of one batch (one launch per step); the thermal ones are repeated
+  over independent seeds for an error estimate.
+* ``ne_spectrum``: the concentration structure factor along q = (q, 0) over an
+  ensemble of independent replicas, reduced as in Eqs. (36)-(37):
+  phi S_NE(q~) = S_c(q, 0) / (3 kT c(1-c) / rho_bar) - 1 against phi q~^-4, with
+  phi from the imposed gradient and from the measured bulk gradient.
+* ``mean_row_profile``: time-averaged row means of a sampled field, read out of
+  the k_x = 0 column of the accumulated Fourier sums (no extra accumulator).
+* ``correlation``: the translation-averaged two-point correlation of a sampled
+  field's fluctuations from its structure factor (Wiener-Khinchin on the
+  lattice), for the real-space correlations of Sec. IV.B.
+
+Every time step, sample, transform and reduction runs in the GPU library; this
+module chooses replicas, drives runs and combines the sums it reads back.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, Iterable, List, Tuple
+
+import numpy as np
+
+from . import fnlb as _f
+
+
+def mean_row_profile(sum_re: np.ndarray, sum_im: np.ndarray, n: int, Lx: int) -> np.ndarray:
+    """Row means r(j), averaged over the n samples, of the field whose Fourier
+    sums are given ([k_z][k_x] half spectrum).  With
+    Phi(0, k_z) = (Lx Lz)^{-1/2} Lx sum_j r(j) e^{-2 pi i k_z j / Lz}, the
+    inverse transform over k_z of the k_x = 0 column returns r(j)."""
+    Lz = sum_re.shape[0]
+    phi0 = (sum_re[:, 0] + 1j * sum_im[:, 0]) / max(n, 1)
+    return (np.fft.ifft(phi0) * np.sqrt(Lx * Lz) / Lx).real
+
+
+def full_spectrum(S_half: np.ndarray, Lx: int) -> np.ndarray:
+    """The structure factor over all (k_z, k_x) from the half spectrum
+    k_x = 0..Lx/2, using S(-q) = S(q) for a real field."""
+    Lz, nkx = S_half.shape
+    S = np.empty((Lz, Lx))
+    S[:, :nkx] = S_half
+    for kx in range(nkx, Lx):
+        S[:, kx] = S_half[(-np.arange(Lz)) % Lz, Lx - kx]
+    return S
+
+
+def correlation(S_half: np.ndarray, Lx: int) -> np.ndarray:
+    """C(dz, dx) = < dphi(r) dphi(r + d) > averaged over r, for the
+    fluctuations about the time-mean field, periodic in x and cyclic over the
+    Lz rows in z: C = (1 / (Lx Lz)) sum_q S(q) e^{i q.d}.  C[0, 0] is the
+    variance; C[0, dx] is exact for every dx (it needs no periodicity in z)."""
+    return np.fft.ifft2(full_spectrum(S_half, Lx)).real
+
+
+@dataclasses.dataclass
+class _Run:
+    """One replica of a scan, with the fields of ``fnlb_replica_params``."""
+    Lx: int
+    Lz: int
+    grad_c0: float
+    kT: float
+    G: float
+    seed: int
+    rho0: float = 1.0
+    tau_d: float = 1.0
+    tau_s: float = 1.0
+    tau_e: float = 1.0
+    tau_q: float = 1.0
+    tau_eps: float = 1.0
+
+
+@dataclasses.dataclass
+class SpectrumRun:
+    """Outcome of ``ne_spectrum`` (k_x = 1..Lx/2 along q = (q, 0))."""
+    q_tilde: np.ndarray        # q L
+    S_c: np.ndarray            # ensemble mean of S_c(q, 0)
+    S_c_err: np.ndarray        # its standard error over the replicas
+    S_eq: float                # 3 kT c(1-c) / rho_bar at c = 1/2
+    phi_imposed: float         # Eq. (37) with the imposed gradient
+    phi_measured: float        # Eq. (37) with the measured bulk gradient
+    grad_measured: float       # slope of the mean concentration profile (bulk rows)
+    S_c_wall_normal: np.ndarray  # S_c(0, q) / S_eq for k_z = 1..Lz/2
+
+
+def ne_spectrum(L: int = 32, Lx: int = 128, kT: float = 1e-5, grad_c0: float = 0.01,
+                D: float = 0.0043, nu: float = 0.0667, replicas: int = 64,
+                warmup: int = 300000, steps: int = 400000, sample_every: int = 50,
+                precision: int = _f.FP32_DEV, seed0: int = 100, edge_rows: int = 4,
+                device: str = "cuda:0") -> SpectrumRun:
+    """Non-equilibrium concentration spectrum of Sec. IV.B.
+
+    `replicas` independent lattices (seeds seed0, seed0 + 1, ...) with
+    tau_d = 3 D + 1/2 and tau_s = 3 nu + 1/2 (Eqs. (28)-(29)) run `warmup`
+    steps, then `steps` sampled steps.  The measured gradient is the slope of
+    the time-averaged concentration profile over the rows away from the walls
+    (`edge_rows` dropped at each side); in two dimensions fluctuations renormalise
+    the diffusivity, so at larger kT it falls below grad c0."""
+    reps = [_Run(Lx=Lx, Lz=L, grad_c0=grad_c0, kT=kT, G=0.0, seed=seed0 + i,
+                 tau_d=3.0 * D + 0.5, tau_s=3.0 * nu + 0.5) for i in range(replicas)]
+    lat = _f.Lattice(reps, precision=precision, sample_every=sample_every, device=device)
+    lat.step(warmup)
+    lat.reset_accumulators()
+    lat.step(steps)
+    S, prof = [], []
+    z = np.arange(L) - (L - 1) / 2.0
+    for i in range(replicas):
+        a2, re, im, n = lat.read_structure_factor(i, _f.FIELD_C)
+        n = max(n, 1)
+        S.append(a2 / n - ((re / n) ** 2 + (im / n) ** 2))
+        prof.append(mean_row_profile(re, im, n, Lx) + 0.5 + z * grad_c0)
+    lat.close()
+    S = np.array(S)
+    c = np.mean(prof, axis=0)
+    bulk = slice(edge_rows, L - edge_rows)
+    g_meas = float(np.polyfit(z[bulk], c[bulk], 1)[0])
+    S_eq = 3.0 * kT * 0.25
+    k = np.arange(1, Lx // 2 + 1)
+
+    def phi(g):
+        return (1.0 / 3.0) * L ** 4 * g * g / (0.25 * (nu + D) * D)
+
+    return SpectrumRun(q_tilde=2.0 * np.pi * k / Lx * L, S_c=S[:, 0, 1:].mean(axis=0),
+                       S_c_err=S[:, 0, 1:].std(axis=0, ddof=1) / np.sqrt(replicas)
+                       if replicas > 1 else np.zeros(len(k)),
+                       S_eq=S_eq, phi_imposed=phi(grad_c0), phi_measured=phi(g_meas),
+                       grad_measured=g_meas,
+                       S_c_wall_normal=S[:, 1:L // 2 + 1, 0].mean(axis=0) / S_eq)
+
+
+@dataclasses.dataclass
+class PressureScan:
+    """Outcome of ``ne_pressure``.  Keys of the dictionaries are (L, grad c0)."""
+    kT: float
+    G: float
+    P_thermal: Dict[Tuple[int, float], Tuple[float, float]]   # (mean, std. error)
+    P_cold: Dict[Tuple[int, float], float]                    # kT = 0 (deterministic)
+    dP_eq: Dict[int, Tuple[float, float]]                     # Eq. (41)
+    P_ne: Dict[Tuple[int, float], Tuple[float, float]]        # Eq. (42)
+    profiles: Dict[Tuple[int, float, float], Dict[str, np.ndarray]]  # (L, grad, kT)
+    steps: int
+    warmup: int
+    seeds: int
+
+
+def scan_replicas(Ls: Iterable[int], grads: Iterable[float], kT: float, G: float,
+                  aspect: int = 4, seeds: int = 8, tau: Dict[str, float] | None = None,
+                  seed0: int = 1000):
+    """The replicas of a pressure scan and their (L, grad c0, kT, seed index)
+    labels: for every L (Lx = aspect * L) and grad c0 in {0} + grads, one run
+    at kT = 0 and `seeds` runs at kT, with Philox seeds seed0, seed0 + 1, ..."""
+    if not kT > 0:
+        raise ValueError("the protocol compares kT > 0 with kT = 0")
+    tau = dict(tau or {})
+    gset = [0.0] + [float(g) for g in grads if float(g) != 0.0]
+    cfgs: List[Tuple[int, float, float, int]] = []
+    reps = []
+    for L in (int(L) for L in Ls):
+        for g in gset:
+            if abs(g) * L >= 1.0:
+                raise ValueError(f"L * grad c0 must stay below 1 (L={L}, grad={g})")
+            for T, ns in ((0.0, 1), (kT, seeds)):
+                for s in range(ns):
+                    cfgs.append((L, g, T, s))
+                    reps.append(_Run(Lx=aspect * L, Lz=L, grad_c0=g, kT=T, G=G,
+                                     seed=seed0 + len(reps), **tau))
+    return cfgs, reps
+
+
+def ne_pressure(Ls: Iterable[int], grads: Iterable[float], kT: float = 1e-4, G: float = 0.3,
+                aspect: int = 4, seeds: int = 8, warmup: int = 20000, steps: int = 100000,
+                sample_every: int = 10, precision: int = _f.FP32_DEV,
+                tau: Dict[str, float] | None = None, seed0: int = 1000,
+                device: str = "cuda:0") -> PressureScan:
+    """Non-equilibrium pressure protocol of Sec. IV.C.
+
+    All runs of ``scan_replicas`` form one batch.  After `warmup` steps the
+    accumulators are cleared and `steps` more steps are sampled every
+    `sample_every` steps.  P(L, kT, grad c0) is the time average of the spatial
+    mean of P - P_ref (the pressure accumulator), averaged over the seeds;
+    Eqs. (41)-(42) combine them.  The mean pressure, total-density and
+    concentration row profiles of each configuration (the profiles of Sec.
+    IV.C) are returned as well."""
+    Ls = [int(L) for L in Ls]
+    gset = [0.0] + [float(g) for g in grads if float(g) != 0.0]
+    cfgs, reps = scan_replicas(Ls, grads, kT, G, aspect, seeds, tau, seed0)
+    lat = _f.Lattice(reps, precision=precision, sample_every=sample_every, device=device)
+    lat.step(warmup)
+    lat.reset_accumulators()
+    lat.step(steps)
+
+    groups: Dict[Tuple[int, float, float], List[int]] = {}
+    for i, c in enumerate(cfgs):
+        groups.setdefault(c[:3], []).append(i)
+    P_thermal, P_cold, profiles = {}, {}, {}
+    for key, idx in groups.items():
+        L, g, T = key
+        vals, prof_p, prof_r, prof_c = [], [], [], []
+        for i in idx:
+            s, _, prof, n = lat.read_pressure(i)
+            vals.append(s / n)
+            prof_p.append(prof / n)
+            _, re, im, n2 = lat.read_structure_factor(i, _f.FIELD_RHO)
+            prof_r.append(mean_row_profile(re, im, n2, aspect * L))
+            _, re, im, n2 = lat.read_structure_factor(i, _f.FIELD_C)
+            prof_c.append(mean_row_profile(re, im, n2, aspect * L))
+        vals = np.array(vals)
+        profiles[key] = {"pressure": np.mean(prof_p, axis=0),
+                         "density": np.mean(prof_r, axis=0),
+                         "concentration": np.mean(prof_c, axis=0)}
+        if T == 0.0:
+            P_cold[(L, g)] = float(vals[0])
+        else:
+            sem = float(vals.std(ddof=1) / np.sqrt(len(vals))) if len(vals) > 1 else 0.0
+            P_thermal[(L, g)] = (float(vals.mean()), sem)
+    dP_eq = {L: (P_thermal[(L, 0.0)][0] - P_cold[(L, 0.0)], P_thermal[(L, 0.0)][1])
+             for L in Ls}
+    P_ne = {}
+    for L in Ls:
+        for g in gset:
+            if g == 0.0:
+                continue
+            m = P_thermal[(L, g)][0] - P_cold[(L, g)] - dP_eq[L][0]
+            e = float(np.hypot(P_thermal[(L, g)][1], dP_eq[L][1]))
+            P_ne[(L, g)] = (m, e)
+    lat.close()
+    return PressureScan(kT=kT, G=G, P_thermal=P_thermal, P_cold=P_cold, dP_eq=dP_eq, P_ne=P_ne,
+                        profiles=profiles, steps=steps, warmup=warmup, seeds=seeds)
+
+
+def _main(argv=None) -> None:
+    import argparse
+    ap = argparse.ArgumentParser(prog="python -m paper_1808_05168_amd.experiments",
+                                 description="experiments of Sec. IV on the GPU")
+    sub = ap.add_subparsers(dest="what", required=True)
+    a = sub.add_parser("spectrum", help="q^-4 non-equilibrium spectrum (Sec. IV.B)")
+    a.add_argument("--L", type=int, default=32)
+    a.add_argument("--Lx", type=int, default=128)
+    a.add_argument("--kT", type=float, default=1e-5)
+    a.add_argument("--grad", type=float, default=0.01)
+    a.add_argument("--replicas", type=int, default=64)
+    a.add_argument("--warmup", type=int, default=300000)
+    a.add_argument("--steps", type=int, default=400000)
+    b = sub.add_parser("pressure", help="non-equilibrium pressure scans (Sec. IV.C)")
+    b.add_argument("--L", type=int, nargs="+", default=[32])
+    b.add_argument("--grad", type=float, nargs="+", default=[0.01])
+    b.add_argument("--kT", type=float, default=1e-4)
+    b.add_argument("--G", type=float, default=0.3)
+    b.add_argument("--seeds", type=int, default=16)
+    b.add_argument("--warmup", type=int, default=150000)
+    b.add_argument("--steps", type=int, default=400000)
+    args = ap.parse_args(argv)
+    if args.what == "spectrum":
+        r = ne_spectrum(L=args.L, Lx=args.Lx, kT=args.kT, grad_c0=args.grad,
+                        replicas=args.replicas, warmup=args.warmup, steps=args.steps)
+        print(f"measured bulk gradient {r.grad_measured:.5g} (imposed {args.grad})")
+        for i, qt in enumerate(r.q_tilde):
+            ne = r.S_c[i] / r.S_eq - 1.0
+            print(f"q~ {qt:8.3f}  phi S_NE {ne:11.4e} +- {r.S_c_err[i] / r.S_eq:9.2e}  "
+                  f"phi q~^-4 {r.phi_imposed * qt ** -4:11.4e} (imposed) "
+                  f"{r.phi_measured * qt ** -4:11.4e} (measured)")
+    else:
+        r = ne_pressure(args.L, args.grad, kT=args.kT, G=args.G, seeds=args.seeds,
+                        warmup=args.warmup, steps=args.steps)
+        for L in sorted(r.dP_eq):
+            print(f"L {L:4d}  Delta P_eq {r.dP_eq[L][0]:11.4e} +- {r.dP_eq[L][1]:.1e}")
+        for (L, g), (m, e) in sorted(r.P_ne.items()):
+            print(f"L {L:4d}  grad c0 {g:.4g}  P_NE {m:11.4e} +- {e:.1e}")
+
+
+if __name__ == "__main__":
+    _main()
