@@ -190,6 +190,23 @@ int fnlb_get_time(const fnlb_handle* h, int64_t* t);
  * continue a run after fnlb_write_populations.  t >= 0. */
 int fnlb_set_time(fnlb_handle* h, int64_t t);
 
+/* Checkpoint / resume.  The noise is a function of (seed, node, time) only
+ * (Eqs. (22)-(23) with a counter-based generator), so a run resumed from a
+ * checkpoint continues bit-identically to an uninterrupted one.
+ * fnlb_checkpoint_bytes: size of the image fnlb_save writes (a small header,
+ * the stored populations of every replica as raw stored values, the
+ * accumulators).
+ * fnlb_save: copies the image into the caller's host buffer of n bytes
+ * (FNLB_ENOMEM if smaller); synchronises the stream; returns the watchdog
+ * status like the read calls.
+ * fnlb_load: restores populations, accumulators, time and sample count from
+ * an image made by a handle with the same replicas (parameters and seeds),
+ * precision, physics flags and sampling interval, else FNLB_EINVAL (a
+ * truncated image: FNLB_ENOMEM).  Synchronises the stream. */
+int fnlb_checkpoint_bytes(const fnlb_handle* h, size_t* bytes);
+int fnlb_save(fnlb_handle* h, void* host_buf, size_t n);
+int fnlb_load(fnlb_handle* h, const void* host_buf, size_t n);
+
 /* Bytes of the device workspace fnlb_sq_misfit_gradient needs for a horizon
  * of `horizon` steps with populations checkpointed every `ckpt_every` steps:
  * ceil(horizon/ckpt_every) + ckpt_every + 2 state copies plus O(Lx Lz)

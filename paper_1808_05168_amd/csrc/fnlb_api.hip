@@ -661,6 +661,104 @@ int fnlb_set_time(fnlb_handle* h, int64_t t) {
 
 namespace {
 
+// Checkpoint image: this header, then the current state copy (raw stored
+// values), then the accumulators.
+struct CkptHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t precision, flags, sample_every, n_rep, reserved;
+  int64_t t, nsamples;
+  uint64_t state_bytes, accum_bytes, key;
+};
+constexpr char kCkptMagic[8] = {'F', 'N', 'L', 'B', 'C', 'K', 'P', 'T'};
+
+// FNV-1a over everything that fixes the layout and the dynamics of a handle:
+// replica parameters (seeds included), precision, physics flags, sampling.
+uint64_t ckpt_key(const fnlb_handle* h) {
+  uint64_t k = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) k = (k ^ c[i]) * 1099511628211ull;
+  };
+  for (const fnlb_replica_params& p : h->reps) {
+    mix(&p.Lx, 4);
+    mix(&p.Lz, 4);
+    const double d[9] = {p.rho0, p.grad_c0, p.kT, p.G, p.tau_d, p.tau_s, p.tau_e, p.tau_q,
+                         p.tau_eps};
+    mix(d, sizeof d);
+    mix(&p.seed, 8);
+  }
+  const int32_t o[3] = {h->opt.precision, h->opt.flags & ~FNLB_NO_GRAPH, h->opt.sample_every};
+  mix(o, sizeof o);
+  return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fnlb_checkpoint_bytes(const fnlb_handle* h, size_t* bytes) {
+  if (!h || !bytes) return FNLB_EINVAL;
+  *bytes = sizeof(CkptHeader) + h->plan.state_half + h->plan.accum_bytes;
+  return FNLB_OK;
+}
+
+int fnlb_save(fnlb_handle* h, void* host_buf, size_t n) {
+  if (!h || !host_buf) return FNLB_EINVAL;
+  if (h->error) return h->error;
+  const size_t need = sizeof(CkptHeader) + h->plan.state_half + h->plan.accum_bytes;
+  if (n < need) return FNLB_ENOMEM;
+  CkptHeader hd{};
+  std::memcpy(hd.magic, kCkptMagic, 8);
+  hd.version = 1;
+  hd.precision = h->opt.precision;
+  hd.flags = h->opt.flags;
+  hd.sample_every = h->opt.sample_every;
+  hd.n_rep = (int32_t)h->reps.size();
+  hd.t = h->t;
+  hd.nsamples = h->nsamples;
+  hd.state_bytes = h->plan.state_half;
+  hd.accum_bytes = h->plan.accum_bytes;
+  hd.key = ckpt_key(h);
+  char* out = (char*)host_buf;
+  std::memcpy(out, &hd, sizeof hd);
+  hipError_t e = hipMemcpyAsync(out + sizeof hd, h->state_copy(h->cur), h->plan.state_half,
+                                hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out + sizeof hd + h->plan.state_half, h->accum, h->plan.accum_bytes,
+                       hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return dev_err(h, e);
+  return check_watchdog(h);
+}
+
+int fnlb_load(fnlb_handle* h, const void* host_buf, size_t n) {
+  if (!h || !host_buf || n < sizeof(CkptHeader)) return FNLB_EINVAL;
+  if (h->error) return h->error;
+  CkptHeader hd;
+  std::memcpy(&hd, host_buf, sizeof hd);
+  if (std::memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 1) return FNLB_EINVAL;
+  if (hd.state_bytes != h->plan.state_half || hd.accum_bytes != h->plan.accum_bytes ||
+      hd.key != ckpt_key(h) || hd.t < 0 || hd.nsamples < 0)
+    return FNLB_EINVAL;
+  if (n < sizeof hd + hd.state_bytes + hd.accum_bytes) return FNLB_ENOMEM;
+  const char* in = (const char*)host_buf + sizeof hd;
+  hipError_t e = hipMemcpyAsync(h->state_copy(h->cur), in, h->plan.state_half,
+                                hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->accum, in + h->plan.state_half, h->plan.accum_bytes,
+                       hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return dev_err(h, e);
+  h->t = hd.t;
+  h->nsamples = hd.nsamples;
+  return FNLB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
 // Device workspace of the adjoint (byte offsets).
 struct AdjPlan {
   size_t ckpt = 0, seg = 0, mu = 0, gf = 0, gs = 0, dens = 0, adjf = 0, acc = 0, target = 0,

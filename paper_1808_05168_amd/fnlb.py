@@ -46,7 +46,8 @@ EXPORTS = ["fnlb_bytes_required", "fnlb_init", "fnlb_step", "fnlb_autotune",
            "fnlb_accumulate_structure_factor", "fnlb_read_structure_factor",
            "fnlb_read_pressure", "fnlb_read_populations", "fnlb_write_populations",
            "fnlb_reset_accumulators", "fnlb_get_time", "fnlb_set_time", "fnlb_destroy",
-           "fnlb_strerror", "fnlb_adjoint_bytes_required", "fnlb_sq_misfit_gradient"]
+           "fnlb_strerror", "fnlb_adjoint_bytes_required", "fnlb_sq_misfit_gradient",
+           "fnlb_checkpoint_bytes", "fnlb_save", "fnlb_load"]
 
 
 def load(path: str = LIB_PATH):
@@ -79,6 +80,9 @@ def load(path: str = LIB_PATH):
     lib.fnlb_adjoint_bytes_required.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, szp]
     lib.fnlb_sq_misfit_gradient.argtypes = [vp, ctypes.c_int32, dp, dp, ctypes.c_int64,
                                             ctypes.c_int32, vp, ctypes.c_size_t, dp, dp]
+    lib.fnlb_checkpoint_bytes.argtypes = [vp, szp]
+    lib.fnlb_save.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.fnlb_load.argtypes = [vp, vp, ctypes.c_size_t]
     lib.fnlb_strerror.argtypes = [ctypes.c_int]
     lib.fnlb_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -237,6 +241,22 @@ class Lattice:
         r = self.reps[rep]
         assert f.shape == (2, 9, r.Lz, r.Lx)
         _check(self._lib.fnlb_write_populations(self._h, rep, _dp(f)), "fnlb_write_populations")
+
+    def save(self) -> np.ndarray:
+        """Checkpoint image (populations, accumulators, time) as a byte array."""
+        nb = ctypes.c_size_t()
+        _check(self._lib.fnlb_checkpoint_bytes(self._h, ctypes.byref(nb)),
+               "fnlb_checkpoint_bytes")
+        buf = np.empty(nb.value, dtype=np.uint8)
+        _check(self._lib.fnlb_save(self._h, buf.ctypes.data_as(ctypes.c_void_p), nb.value),
+               "fnlb_save")
+        return buf
+
+    def load(self, image: np.ndarray) -> None:
+        """Restores a checkpoint image made by a handle of the same replicas."""
+        buf = np.ascontiguousarray(image, dtype=np.uint8)
+        _check(self._lib.fnlb_load(self._h, buf.ctypes.data_as(ctypes.c_void_p), buf.size),
+               "fnlb_load")
 
     def reset_accumulators(self) -> None:
         _check(self._lib.fnlb_reset_accumulators(self._h), "fnlb_reset_accumulators")

@@ -83,3 +83,39 @@ def test_autotune_keeps_state_and_results(F):
     a.step(21)
     b.step(21)
     _same(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_checkpoint_resume_is_bit_identical(F, prec):
+    """Save after 73 steps, continue 41 steps; a fresh handle loaded from the
+    image and stepped 41 steps matches bit for bit (populations, structure-factor
+    and pressure sums, sample count, time)."""
+    import dataclasses
+    precision = F.FP64 if prec == "fp64" else F.FP32_DEV
+    reps = [W.Replica(Lx=70, Lz=12, grad_c0=5e-3, kT=1e-4, G=0.5, tau_s=0.7, seed=61),
+            W.Replica(Lx=300, Lz=20, grad_c0=2e-3, kT=1e-4, seed=62)]
+    say(f"case: checkpoint resume {prec}")
+    a = F.Lattice(reps, precision=precision, sample_every=5)
+    a.step(73)
+    image = a.save()
+    a.step(41)
+    b = F.Lattice(reps, precision=precision, sample_every=5)
+    b.load(image)
+    assert b.time == 73
+    b.step(41)
+    assert b.time == a.time == 114
+    for i in range(len(reps)):
+        np.testing.assert_array_equal(b.read_populations(i), a.read_populations(i))
+        for fld in range(2):
+            for x, y in zip(b.read_structure_factor(i, fld), a.read_structure_factor(i, fld)):
+                np.testing.assert_array_equal(x, y)
+        for x, y in zip(b.read_pressure(i), a.read_pressure(i)):
+            np.testing.assert_array_equal(x, y)
+    # an image only loads into a handle of the same replicas and options
+    other = [dataclasses.replace(reps[0], seed=99), reps[1]]
+    with pytest.raises(F.FnlbError):
+        F.Lattice(other, precision=precision, sample_every=5).load(image)
+    with pytest.raises(F.FnlbError):
+        F.Lattice(reps, precision=precision, sample_every=10).load(image)
+    with pytest.raises(F.FnlbError):
+        F.Lattice(reps, precision=precision, sample_every=5).load(image[:-8])
