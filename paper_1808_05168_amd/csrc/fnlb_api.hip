@@ -27,7 +27,8 @@ constexpr int kMaxDim = 4096;
 // Largest non-power-of-two dimension (direct transform, quadratic cost).
 constexpr int kMaxDirect = 2048;
 // Complex entries of the column-pass LDS tile.
-constexpr int kColTile = 4096;
+constexpr int kColTile = 2048;  // complex values per column-transform tile (32 KiB)
+constexpr int kRowGroup = 512;  // complex values per row-transform block (short rows share)
 
 int validate(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options* opt) {
   if (!reps || !opt || n_rep <= 0) return FNLB_EINVAL;
@@ -67,7 +68,7 @@ struct Plan {
   size_t o_reps = 0, o_items = 0, o_rows = 0, o_cols = 0, o_misc = 0, o_tw = 0, o_fields = 0,
          o_spec = 0, o_ppart = 0;
   size_t item_capacity = 0;  // items the work buffer holds (row ranges of one row)
-  int max_lx = 0, max_lz = 0, max_col_lds = 0, chunk = 0;
+  int max_lx = 0, max_lz = 0, max_col_lds = 0, max_row_lds = 0, chunk = 0;
   int n_pairs = 1;  // complex row transforms per row: (dc, drho) [, (Ux, Uz)]
 };
 
@@ -195,16 +196,27 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
   P.rows.clear();
   P.cols.clear();
   P.max_col_lds = 0;
+  P.max_row_lds = 0;
   for (int r = 0; r < n_rep; ++r) {
     const RepInfo& R = P.info[r];
-    for (int j = 0; j < R.Lz; ++j) P.rows.push_back(RowRef{r, j});
+    // short power-of-two rows are transformed several to a block
+    const int per = R.pow2 ? std::max(1, kRowGroup / R.Lx) : 1;
+    for (int j = 0; j < R.Lz; j += per) {
+      const int nr = std::min(per, R.Lz - j);
+      P.rows.push_back(RowRef{r, j, nr, 0});
+      // the rows, plus N/2 twiddles for the power-of-two FFT
+      P.max_row_lds = std::max(P.max_row_lds, nr * R.Lx + (R.pow2 ? R.Lx / 2 : 0));
+    }
     const int nkx = R.Lx / 2 + 1;
-    const int tile = std::max(1, std::min(16, kColTile / R.Lz));
+    int lt = 0;  // tile of 2^lt columns: at most 16 and at most kColTile values
+    while (lt < 4 && (2 << lt) * R.Lz <= kColTile) ++lt;
+    const int tile = 1 << lt;
     for (int f = 0; f < nf; ++f)
       for (int k0 = 0; k0 < nkx; k0 += tile) {
         const int nc = std::min(tile, nkx - k0);
-        P.cols.push_back(ColRef{r, f, k0, nc});
-        P.max_col_lds = std::max(P.max_col_lds, nc * R.Lz);
+        P.cols.push_back(ColRef{r, f, k0, nc, lt});
+        // the tile, plus Lz/2 twiddles for the power-of-two FFT
+        P.max_col_lds = std::max(P.max_col_lds, tile * R.Lz + (R.pow2 ? R.Lz / 2 : 0));
       }
   }
   P.state_half = align_up((size_t)state_elems * P.store_size);
@@ -295,7 +307,7 @@ hipError_t observe(fnlb_handle* h, hipStream_t s, double* acc = nullptr) {
   const Plan& P = h->plan;
   if (!acc) acc = (double*)h->accum;
   hipError_t e = launch_row_transform(h->d_reps(), h->d_rows(), (int)P.rows.size(), P.n_pairs,
-                                      P.max_lx, h->d_fields(), h->d_spec(), h->d_tw(), s);
+                                      P.max_row_lds, h->d_fields(), h->d_spec(), h->d_tw(), s);
   if (e != hipSuccess) return e;
   e = launch_col_transform(h->d_reps(), h->d_cols(), (int)P.cols.size(), P.max_col_lds,
                            h->d_spec(), acc, h->d_tw(), s);
@@ -550,15 +562,21 @@ int fnlb_read_structure_factor(fnlb_handle* h, int32_t rep, int32_t field, doubl
     return FNLB_EINVAL;
   if (h->error) return h->error;
   const RepInfo& R = h->plan.info[rep];
-  const size_t plane = (size_t)R.Lz * (R.Lx / 2 + 1);
+  const int nkx = R.Lx / 2 + 1, Lz = R.Lz;
+  const size_t plane = (size_t)Lz * nkx;
   const double* base = (const double*)h->accum + R.acc_off + (size_t)field * 3 * plane;
-  double* dst[3] = {sum_abs2, sum_re, sum_im};
-  hipError_t e = hipSuccess;
-  for (int k = 0; k < 3 && e == hipSuccess; ++k)
-    if (dst[k])
-      e = hipMemcpyAsync(dst[k], base + k * plane, plane * 8, hipMemcpyDeviceToHost, h->stream);
+  // device layout [kind][k_x][k_z]; the caller's arrays are [k_z][k_x]
+  std::vector<double> buf(3 * plane);
+  hipError_t e = hipMemcpyAsync(buf.data(), base, 3 * plane * 8, hipMemcpyDeviceToHost,
+                                h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return dev_err(h, e);
+  double* dst[3] = {sum_abs2, sum_re, sum_im};
+  for (int k = 0; k < 3; ++k)
+    if (dst[k])
+      for (int kx = 0; kx < nkx; ++kx)
+        for (int kz = 0; kz < Lz; ++kz)
+          dst[k][(size_t)kz * nkx + kx] = buf[k * plane + (size_t)kx * Lz + kz];
   if (n_samples) *n_samples = h->nsamples;
   return check_watchdog(h);
 }

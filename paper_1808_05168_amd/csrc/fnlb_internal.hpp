@@ -63,12 +63,12 @@ struct Item {
 
 // A row of one replica (row transform of the structure factor).
 struct RowRef {
-  int32_t rep, j;
+  int32_t rep, j0, nrows, pad;  // rows j0 .. j0 + nrows - 1 of one replica
 };
 
 // A tile of k_x columns of one field of one replica (column transform).
 struct ColRef {
-  int32_t rep, field, kx0, ncols;
+  int32_t rep, field, kx0, ncols, ltile;  // ncols <= 2^ltile columns from kx0
 };
 
 // Kernel modes of the fused step.
@@ -94,7 +94,7 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t stream);
 hipError_t launch_twiddles(const RepInfo* d_reps, const RepInfo* h_reps, int n_rep,
                            double2* tw_base, hipStream_t stream);
 hipError_t launch_row_transform(const RepInfo* reps, const RowRef* rows, int n_rows,
-                                int n_pairs, int max_lx, const double* fields, double2* spec,
+                                int n_pairs, int max_row_lds, const double* fields, double2* spec,
                                 const double2* tw, hipStream_t stream);
 hipError_t launch_col_transform(const RepInfo* reps, const ColRef* cols, int n_cols,
                                 int max_lds_cols, const double2* spec, double* acc,

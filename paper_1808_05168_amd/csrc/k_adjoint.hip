@@ -416,7 +416,7 @@ __global__ void k_adj_theta(const double* tpart, int nblocks, double* acc) {
 struct SpecArgs {
   const RepInfo* rep;
   const double2* tw;      // e^{-2 pi i m / Lx} (Lx entries) then e^{-2 pi i m / Lz}
-  const double* acc;      // forward sums [2][3][Lz][nkx] of the replica
+  const double* acc;      // forward sums [2][3][nkx][Lz] of the replica (column-major)
   const double* target;   // S* [Lz][nkx]
   const double* weight;   // w  [Lz][nkx]
   double* Wq;             // 2 w (S - S*)          [Lz][nkx]
@@ -440,8 +440,10 @@ __global__ void k_adj_misfit(const SpecArgs a) {
     const size_t plane = (size_t)P;
     const double* a2 = a.acc + (size_t)a.field * 3 * plane;
     const double n = a.nsamp;
-    const double mr = a2[plane + q] / n, mi = a2[2 * plane + q] / n;
-    const double S = a2[q] / n - (mr * mr + mi * mi);
+    const int kz = q / nkx, kx = q - kz * nkx;
+    const size_t qa = (size_t)kx * R.Lz + kz;  // the accumulators are [k_x][k_z]
+    const double mr = a2[plane + qa] / n, mi = a2[2 * plane + qa] / n;
+    const double S = a2[qa] / n - (mr * mr + mi * mi);
     const double d = S - a.target[q];
     a.Wq[q] = 2.0 * a.weight[q] * d;
     a.mean[q] = make_double2(mr, mi);

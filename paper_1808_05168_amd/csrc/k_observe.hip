@@ -51,23 +51,22 @@ __device__ __forceinline__ unsigned bitrev(unsigned v, int bits) {
   return __brev(v) >> (32 - bits);
 }
 
-// In-place radix-2 decimation-in-time FFT of `ncol` sequences of length N
-// stored column-major in LDS (buf[c * N + k], already in bit-reversed order);
-// tw[m] = exp(-2 pi i m / N).
-__device__ void lds_fft(double2* buf, int N, int ncol, const double2* tw) {
-  const int half = N >> 1;
+// In-place radix-2 decimation-in-time FFT of `ncol` sequences of length
+// N = 2^lg stored column-major in LDS (buf[c * N + k], already in bit-reversed
+// order); tw[m] = exp(-2 pi i m / N).  All index arithmetic is shifts and masks.
+__device__ void lds_fft(double2* buf, int lg, int ncol, const double2* tw) {
+  const int half = 1 << (lg - 1);
   const int total = half * ncol;
-  for (int len = 2; len <= N; len <<= 1) {
-    const int h = len >> 1;
-    const int tstep = N / len;
+  for (int s = 1; s <= lg; ++s) {
+    const int lgh = s - 1, h = 1 << lgh, tsh = lg - s;
     __syncthreads();
     for (int q = threadIdx.x; q < total; q += blockDim.x) {
-      const int c = q / half;
-      const int b = q - c * half;
-      const int grp = b / h, k = b - grp * h;
-      const int i0 = grp * len + k, i1 = i0 + h;
-      double2* col = buf + (size_t)c * N;
-      const double2 w = tw[k * tstep];
+      const int c = q >> (lg - 1);
+      const int b = q & (half - 1);
+      const int k = b & (h - 1);
+      const int i0 = ((b >> lgh) << s) + k, i1 = i0 + h;
+      double2* col = buf + ((size_t)c << lg);
+      const double2 w = tw[k << tsh];
       const double2 u = col[i0];
       const double2 v = cmul(col[i1], w);
       col[i0] = make_double2(u.x + v.x, u.y + v.y);
@@ -77,40 +76,70 @@ __device__ void lds_fft(double2* buf, int N, int ncol, const double2* tw) {
   __syncthreads();
 }
 
-// Row pass: one block per (replica, row) and field pair (blockIdx.y).
+// Global loads are issued kBatch per thread before their values are used, so
+// that their latencies overlap.
+constexpr int kBatch = 8;
+
+// Row pass: one block per group of consecutive rows of one replica (several
+// short rows share a block) and field pair (blockIdx.y).  LDS: the rows, then
+// (power-of-two rows) the N/2 twiddles the FFT uses.
 __global__ void k_row_transform(const RepInfo* reps, const RowRef* rows, const double* fields,
                                 double2* spec, const double2* tw_base) {
   extern __shared__ double2 lds[];
   const RowRef rr = rows[blockIdx.x];
   const RepInfo& R = reps[rr.rep];
-  const int N = R.Lx, Lz = R.Lz, nkx = N / 2 + 1;
-  const size_t row = (size_t)(2 * blockIdx.y) * Lz + rr.j;  // first field of the pair
-  const double* fc = fields + R.field_off + row * N;
+  const int N = R.Lx, Lz = R.Lz, nkx = N / 2 + 1, nr = rr.nrows;
+  const size_t row0 = (size_t)(2 * blockIdx.y) * Lz + rr.j0;  // first field of the pair
+  const double* fc = fields + R.field_off + row0 * N;
   const double* fr = fc + (size_t)Lz * N;
   const double2* tw = tw_base + R.tw_off;
-  double2* out_c = spec + R.spec_off + row * nkx;
+  double2* out_c = spec + R.spec_off + row0 * nkx;
   double2* out_r = out_c + (size_t)Lz * nkx;
+  const int total = nr * N;
+  const int bits = R.pow2 ? __ffs(N) - 1 : 0;
+  for (int base = threadIdx.x; base < total; base += kBatch * blockDim.x) {
+    double vc[kBatch], vr[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int q = base + u * blockDim.x;
+      if (q < total) {
+        vc[u] = fc[q];
+        vr[u] = fr[q];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int q = base + u * blockDim.x;
+      if (q < total) {
+        const int d = R.pow2 ? ((q >> bits) << bits) + bitrev(q & (N - 1), bits) : q;
+        lds[d] = make_double2(vc[u], vr[u]);
+      }
+    }
+  }
   if (R.pow2) {
-    const int bits = __ffs(N) - 1;
-    for (int x = threadIdx.x; x < N; x += blockDim.x)
-      lds[bitrev(x, bits)] = make_double2(fc[x], fr[x]);
-    lds_fft(lds, N, 1, tw);
+    double2* tws = lds + total;
+    for (int m = threadIdx.x; m < N / 2; m += blockDim.x) tws[m] = tw[m];
+    lds_fft(lds, bits, nr, tws);
   } else {
-    for (int x = threadIdx.x; x < N; x += blockDim.x) lds[x] = make_double2(fc[x], fr[x]);
     __syncthreads();
   }
-  for (int k = threadIdx.x; k < nkx; k += blockDim.x) {
+  // the block's threads split into one group per row
+  const int gsz = blockDim.x / nr;
+  const int r = threadIdx.x / gsz;
+  if (r >= nr) return;
+  const double2* row = lds + (size_t)r * N;
+  for (int k = threadIdx.x - r * gsz; k < nkx; k += gsz) {
     double2 Z, Zm;
     if (R.pow2) {
-      Z = lds[k];
-      Zm = lds[(N - k) & (N - 1)];
+      Z = row[k];
+      Zm = row[(N - k) & (N - 1)];
     } else {
       // direct sum for Z(k) and Z(N-k)
       double zr = 0, zi = 0, mr = 0, mi = 0;
       const int km = (N - k) % N;
       int ik = 0, im = 0;
       for (int x = 0; x < N; ++x) {
-        const double2 a = lds[x];
+        const double2 a = row[x];
         const double2 w1 = tw[ik], w2 = tw[im];
         zr += a.x * w1.x - a.y * w1.y;
         zi += a.x * w1.y + a.y * w1.x;
@@ -125,48 +154,86 @@ __global__ void k_row_transform(const RepInfo* reps, const RowRef* rows, const d
       Zm = make_double2(mr, mi);
     }
     // C(k) = (Z(k) + conj Z(N-k)) / 2, Rho(k) = (Z(k) - conj Z(N-k)) / (2i)
-    out_c[k] = make_double2(0.5 * (Z.x + Zm.x), 0.5 * (Z.y - Zm.y));
-    out_r[k] = make_double2(0.5 * (Z.y + Zm.y), 0.5 * (Zm.x - Z.x));
+    const size_t o = (size_t)r * nkx + k;
+    out_c[o] = make_double2(0.5 * (Z.x + Zm.x), 0.5 * (Z.y - Zm.y));
+    out_r[o] = make_double2(0.5 * (Z.y + Zm.y), 0.5 * (Zm.x - Z.x));
   }
 }
 
-// Column pass: one block per (replica, field, tile of k_x columns).
+// Column pass: one block per (replica, field, tile of 2^ltile k_x columns).
+// LDS: the tile's columns, then (power-of-two columns) the M/2 twiddles.
 __global__ void k_col_transform(const RepInfo* reps, const ColRef* cols, const double2* spec,
                                 double* acc, const double2* tw_base) {
   extern __shared__ double2 lds[];
   const ColRef cr = cols[blockIdx.x];
   const RepInfo& R = reps[cr.rep];
   const int Lx = R.Lx, M = R.Lz, nkx = Lx / 2 + 1;
-  const int nc = cr.ncols;
-  const double2* in = spec + R.spec_off + (size_t)cr.field * M * nkx;
+  const int nc = cr.ncols, lt = cr.ltile, tmask = (1 << lt) - 1;
+  const double2* in = spec + R.spec_off + (size_t)cr.field * M * nkx + cr.kx0;
   const double2* tw = tw_base + R.tw_off + Lx;
   const size_t plane = (size_t)M * nkx;
-  double* a2 = acc + R.acc_off + (size_t)cr.field * 3 * plane;
+  // accumulators are stored column-major, [k_x][k_z], so a tile's sums are one
+  // contiguous run per kind
+  double* a2 = acc + R.acc_off + (size_t)cr.field * 3 * plane + (size_t)cr.kx0 * M;
   double* are = a2 + plane;
   double* aim = a2 + 2 * plane;
   const double norm = R.inv_norm;
   const int bits = __ffs(M) - 1;
-  // load: row-major reads of nc consecutive k_x per row
-  for (int q = threadIdx.x; q < M * nc; q += blockDim.x) {
-    const int j = q / nc, c = q - j * nc;
-    const double2 v = in[(size_t)j * nkx + cr.kx0 + c];
-    lds[(size_t)c * M + (R.pow2 ? bitrev(j, bits) : j)] = v;
+  const int total = M << lt;
+  // load: row-major reads of the tile's consecutive k_x of each row
+  for (int base = threadIdx.x; base < total; base += kBatch * blockDim.x) {
+    double2 v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int q = base + u * blockDim.x;
+      if (q < total && (q & tmask) < nc) v[u] = in[(size_t)(q >> lt) * nkx + (q & tmask)];
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int q = base + u * blockDim.x;
+      const int j = q >> lt, c = q & tmask;
+      if (q < total && c < nc) lds[(size_t)c * M + (R.pow2 ? bitrev(j, bits) : j)] = v[u];
+    }
   }
   if (R.pow2) {
-    lds_fft(lds, M, nc, tw);
-    for (int q = threadIdx.x; q < M * nc; q += blockDim.x) {
-      const int kz = q / nc, c = q - kz * nc;
-      const double2 P = lds[(size_t)c * M + kz];
-      const double re = P.x * norm, im = P.y * norm;
-      const size_t o = (size_t)kz * nkx + cr.kx0 + c;
-      a2[o] += re * re + im * im;
-      are[o] += re;
-      aim[o] += im;
+    double2* tws = lds + ((size_t)M << lt);
+    for (int m = threadIdx.x; m < M / 2; m += blockDim.x) tws[m] = tw[m];
+    lds_fft(lds, bits, nc, tws);
+    // accumulate: the three sums of a batch of entries are read before any is
+    // written back
+    for (int base = threadIdx.x; base < total; base += kBatch * blockDim.x) {
+      double re[kBatch], im[kBatch], s2[kBatch], sr[kBatch], si[kBatch];
+      size_t o[kBatch];
+      bool ok[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int q = base + u * blockDim.x;
+        const int c = q >> bits, kz = q & (M - 1);
+        ok[u] = q < total && c < nc;
+        o[u] = (size_t)c * M + kz;
+        if (ok[u]) {
+          const double2 P = lds[(size_t)c * M + kz];
+          re[u] = P.x * norm;
+          im[u] = P.y * norm;
+          s2[u] = a2[o[u]];
+          sr[u] = are[o[u]];
+          si[u] = aim[o[u]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        if (ok[u]) {
+          a2[o[u]] = s2[u] + (re[u] * re[u] + im[u] * im[u]);
+          are[o[u]] = sr[u] + re[u];
+          aim[o[u]] = si[u] + im[u];
+        }
+      }
     }
   } else {
     __syncthreads();
-    for (int q = threadIdx.x; q < M * nc; q += blockDim.x) {
-      const int kz = q / nc, c = q - kz * nc;
+    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+      const int c = q / M, kz = q - c * M;
+      if (c >= nc) continue;
       const double2* col = lds + (size_t)c * M;
       double re = 0, im = 0;
       int ik = 0;
@@ -179,7 +246,7 @@ __global__ void k_col_transform(const RepInfo* reps, const ColRef* cols, const d
       }
       re *= norm;
       im *= norm;
-      const size_t o = (size_t)kz * nkx + cr.kx0 + c;
+      const size_t o = (size_t)c * M + kz;
       a2[o] += re * re + im * im;
       are[o] += re;
       aim[o] += im;
@@ -244,10 +311,10 @@ hipError_t launch_twiddles(const RepInfo* d_reps, const RepInfo* h_reps, int n_r
 }
 
 hipError_t launch_row_transform(const RepInfo* reps, const RowRef* rows, int n_rows, int n_pairs,
-                                int max_lx, const double* fields, double2* spec,
+                                int max_row_lds, const double* fields, double2* spec,
                                 const double2* tw, hipStream_t stream) {
   if (n_rows <= 0) return hipSuccess;
-  const size_t lds = (size_t)max_lx * sizeof(double2);
+  const size_t lds = (size_t)max_row_lds * sizeof(double2);
   hipLaunchKernelGGL(k_row_transform, dim3(n_rows, n_pairs), dim3(256), lds, stream, reps, rows,
                      fields, spec, tw);
   return hipGetLastError();

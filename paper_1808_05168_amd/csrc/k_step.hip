@@ -52,24 +52,28 @@ __device__ __forceinline__ void density(const Store (&o)[18], DT& da, DT& db) {
   db = b;
 }
 
-// density deviations of one column pulled at row jr (segment-edge column)
-template <typename DT, typename Store>
-__device__ __forceinline__ void edge_density(Rsrc r, uint32_t plane_b, uint32_t row_b, int jr,
-                                             int Lz, int Lx, int col, DT& da, DT& db) {
+// the 18 populations of one column pulled at row jr (segment-edge column)
+template <typename Store>
+__device__ __forceinline__ void edge_pull(Rsrc r, uint32_t plane_b, uint32_t row_b, int jr,
+                                          int Lz, int Lx, int col, Store (&o)[18]) {
   constexpr uint32_t SB = sizeof(Store);
   const int cm = col == 0 ? Lx - 1 : col - 1, cp = col == Lx - 1 ? 0 : col + 1;
-  Store o[18];
   load_pulled(r, plane_b, row_b, jr, Lz, (uint32_t)col * SB, (uint32_t)cm * SB,
               (uint32_t)cp * SB, o);
-  density<DT>(o, da, db);
 }
 
 template <typename Real, typename Store, int MODE>
 __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
-  using DT = typename std::conditional<MODE == kStep, Real, double>::type;
+  // Density rings in LDS (row slot, species, column + 1).  The collision reads
+  // sums in the compute type, exactly as in a step that does not sample, so
+  // sampling leaves the trajectory bit-identical; the observables read FP64
+  // sums, from a second ring when the compute type is FP32.
+  using DT = typename std::conditional<MODE == kSampleOnly, double, Real>::type;
+  constexpr bool kTwo = MODE == kStepSample && !std::is_same<Real, double>::value;
   constexpr int kRow = kSeg + 2;
-  __shared__ DT ring[4][2][kRow];  // density deviations: row slot, species, column + 1
-  __shared__ DT edge[2][36];       // pulled populations of the two edge columns
+  __shared__ DT ring[4][2][kRow];
+  __shared__ double oring[kTwo ? 4 : 1][2][kTwo ? kRow : 1];
+  __shared__ Store edge[2][36];  // pulled populations of the two edge columns
 
   // XCD-aware block order: consecutive hardware blocks go to different XCDs,
   // so give each XCD a contiguous range of work items (neighbouring segments
@@ -108,25 +112,38 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   // part in the barriers
   const bool wave_act = X0 + kWave * wv < Lx;
 
+  // writes the density deviations of 18 pulled populations into ring column
+  // col of row jr (both rings when there are two)
+  auto put_col = [&](int jr, int col, const Store(&o)[18]) {
+    DT da, db;
+    density<DT>(o, da, db);
+    ring[jr & 3][0][col] = da;
+    ring[jr & 3][1][col] = db;
+    if constexpr (kTwo) {
+      double oa, ob;
+      density<double>(o, oa, ob);
+      oring[jr & 3][0][col] = oa;
+      oring[jr & 3][1][col] = ob;
+    }
+  };
+  // FP64 density rows for the observables
+  auto orow = [&](int jr, int sp) -> const double* {
+    if constexpr (kTwo) {
+      return oring[jr & 3][sp];
+    } else if constexpr (std::is_same<DT, double>::value) {
+      return ring[jr & 3][sp];
+    } else {
+      return nullptr;
+    }
+  };
   // writes the density deviations of row jr of this lane into the ring (and,
   // for a whole periodic row, the wrapped edge columns)
   auto put_row = [&](int jr, const Store(&o)[18]) {
-    DT da, db;
-    density<DT>(o, da, db);
-    DT* ra = ring[jr & 3][0];
-    DT* rb = ring[jr & 3][1];
     if (act) {
-      ra[c] = da;
-      rb[c] = db;
+      put_col(jr, c, o);
       if (whole_row) {
-        if (x == Lx - 1) {
-          ra[0] = da;
-          rb[0] = db;
-        }
-        if (x == 0) {
-          ra[width + 1] = da;
-          rb[width + 1] = db;
-        }
+        if (x == Lx - 1) put_col(jr, 0, o);
+        if (x == 0) put_col(jr, width + 1, o);
       }
     }
   };
@@ -153,21 +170,16 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
       const uint32_t pl = (uint32_t)(9 * es + (bounce ? eopp : el)) * plane_b;
       const uint32_t off = pl + (uint32_t)(bounce ? jr : js) * row_b +
                            (uint32_t)(bounce ? ecol : exs) * SB;
-      edge[jr & 1][lane] = (DT)bload<Store>(in, off, 0);
+      edge[jr & 1][lane] = bload<Store>(in, off, 0);
     }
   };
   auto sum_edges = [&](int jr) {
     if (!whole_row && (tid == 0 || tid == width - 1)) {
-      const DT* e = edge[jr & 1] + (tid == 0 ? 0 : 18);
-      DT da = e[0], db = e[9];
+      const Store* e = edge[jr & 1] + (tid == 0 ? 0 : 18);
+      Store o[18];
 #pragma unroll
-      for (int l = 1; l < 9; ++l) {
-        da += e[l];
-        db += e[9 + l];
-      }
-      const int col = tid == 0 ? 0 : width + 1;
-      ring[jr & 3][0][col] = da;
-      ring[jr & 3][1][col] = db;
+      for (int l = 0; l < 18; ++l) o[l] = e[l];
+      put_col(jr, tid == 0 ? 0 : width + 1, o);
     }
   };
 
@@ -197,9 +209,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   }
   if (!whole_row && (tid == 0 || tid == width - 1)) {
     const int col = tid == 0 ? hl : hr, rc = tid == 0 ? 0 : width + 1;
-    for (int jr = max(j0 - 1, 0); jr <= j0; ++jr)
-      edge_density<DT, Store>(in, plane_b, row_b, jr, Lz, Lx, col, ring[jr & 3][0][rc],
-                              ring[jr & 3][1][rc]);
+    for (int jr = max(j0 - 1, 0); jr <= j0; ++jr) {
+      Store o[18];
+      edge_pull<Store>(in, plane_b, row_b, jr, Lz, Lx, col, o);
+      put_col(jr, rc, o);
+    }
   }
 
   for (int j = j0; j < j1; ++j) {
@@ -227,26 +241,27 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
 
     // the 3 x 3 density stencil; ghost rows beyond the walls repeat the wall row
     const int jU = top ? j : j + 1, jD = bot ? j : j - 1;
-    const DT* aU = ring[jU & 3][0];
-    const DT* bU = ring[jU & 3][1];
-    const DT* aC = ring[j & 3][0];
-    const DT* bC = ring[j & 3][1];
-    const DT* aD = ring[jD & 3][0];
-    const DT* bD = ring[jD & 3][1];
-    const DT dAc = aC[c], dBc = bC[c];
-    const DT aWc = aC[c - 1], aEc = aC[c + 1], bWc = bC[c - 1], bEc = bC[c + 1];
-    const DT dAp = aU[c], aWp = aU[c - 1], aEp = aU[c + 1];
-    const DT dBp = bU[c], bWp = bU[c - 1], bEp = bU[c + 1];
-    const DT dAm = aD[c], aWm = aD[c - 1], aEm = aD[c + 1];
-    const DT dBm = bD[c], bWm = bD[c - 1], bEm = bD[c + 1];
 
     // reference densities of this row and of the rows the stencil reaches
     const double rAj = rA0 + rAs * j;
     const double szref = rAs * (double)(jU - jD) * (1.0 / 6.0);  // species A
 
     if constexpr (MODE != kStep) {
-      // observables of f(t): delta c, delta rho and the pressure
-      const double rhoA = rAj + (double)dAc, rhoB = (rho0 - rAj) + (double)dBc;
+      // observables of f(t): delta c, delta rho and the pressure, from the FP64
+      // density sums
+      const double* oaU = orow(jU, 0);
+      const double* obU = orow(jU, 1);
+      const double* oaC = orow(j, 0);
+      const double* obC = orow(j, 1);
+      const double* oaD = orow(jD, 0);
+      const double* obD = orow(jD, 1);
+      const double dAc = oaC[c], dBc = obC[c];
+      const double aWc = oaC[c - 1], aEc = oaC[c + 1], bWc = obC[c - 1], bEc = obC[c + 1];
+      const double dAp = oaU[c], aWp = oaU[c - 1], aEp = oaU[c + 1];
+      const double dBp = obU[c], bWp = obU[c - 1], bEp = obU[c + 1];
+      const double dAm = oaD[c], aWm = oaD[c - 1], aEm = oaD[c + 1];
+      const double dBm = obD[c], bWm = obD[c - 1], bEm = obD[c + 1];
+      const double rhoA = rAj + dAc, rhoB = (rho0 - rAj) + dBc;
       const double rho = rhoA + rhoB;
       const double drho = (double)dAc + (double)dBc;
       const double c0 = rAj / rho0;
@@ -307,6 +322,18 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
 
     if constexpr (MODE != kSampleOnly) {
      if (wave_act) {
+      const DT* aU = ring[jU & 3][0];
+      const DT* bU = ring[jU & 3][1];
+      const DT* aC = ring[j & 3][0];
+      const DT* bC = ring[j & 3][1];
+      const DT* aD = ring[jD & 3][0];
+      const DT* bD = ring[jD & 3][1];
+      const DT dAc = aC[c], dBc = bC[c];
+      const DT aWc = aC[c - 1], aEc = aC[c + 1], bWc = bC[c - 1], bEc = bC[c + 1];
+      const DT dAp = aU[c], aWp = aU[c - 1], aEp = aU[c + 1];
+      const DT dBp = bU[c], bWp = bU[c - 1], bEp = bU[c + 1];
+      const DT dAm = aD[c], aWm = aD[c - 1], aEm = aD[c + 1];
+      const DT dBm = bD[c], bWm = bD[c - 1], bEm = bD[c + 1];
       Real dA[9], dB[9];
 #pragma unroll
       for (int l = 0; l < 9; ++l) {
