@@ -119,3 +119,18 @@ def test_checkpoint_resume_is_bit_identical(F, prec):
         F.Lattice(reps, precision=precision, sample_every=10).load(image)
     with pytest.raises(F.FnlbError):
         F.Lattice(reps, precision=precision, sample_every=5).load(image[:-8])
+
+
+@pytest.mark.parametrize("flags", [W.DEFAULT_FLAGS, W.DEFAULT_FLAGS | W.SAMPLE_VELOCITY])
+def test_sampling_leaves_fp32_trajectory_unchanged(F, flags):
+    """With FP32-deviation storage a step that samples runs the same collision
+    arithmetic as one that does not: the trajectories agree bit for bit."""
+    reps = [W.Replica(Lx=100, Lz=20, grad_c0=5e-3, kT=1e-4, G=0.5, tau_s=0.7, tau_d=0.8, seed=71),
+            W.Replica(Lx=600, Lz=9, grad_c0=1e-2, kT=1e-4, G=0.3, seed=72)]
+    say(f"case: sampled vs unsampled fp32, flags={flags}")
+    a = F.Lattice(reps, precision=F.FP32_DEV, sample_every=3, flags=flags)
+    b = F.Lattice(reps, precision=F.FP32_DEV, sample_every=0, flags=flags)
+    a.step(37)
+    b.step(37)
+    for i in range(len(reps)):
+        np.testing.assert_array_equal(a.read_populations(i), b.read_populations(i))
