@@ -92,3 +92,15 @@ def compare_observables(lat, acc, rep_index, rep, tol):
     for k, v in out.items():
         assert v <= tol, f"{k}: {v:.3e} > {tol:.1e}"
     return out
+
+
+def phi_entries(dphi, qs):
+    """Phi(k_z, k_x) = (Lx Lz)^{-1/2} sum_{x,j} dphi(x,j) e^{-2 pi i (k_x x / Lx +
+    k_z j / Lz)} at the listed (k_z, k_x), by a direct separable sum in numpy
+    (for lattices whose full transform the oracle cannot afford)."""
+    Lz, Lx = dphi.shape
+    out = []
+    for kz, kx in qs:
+        row = dphi @ np.exp(-2j * np.pi * kx * np.arange(Lx) / Lx)
+        out.append(row @ np.exp(-2j * np.pi * kz * np.arange(Lz) / Lz) / np.sqrt(Lx * Lz))
+    return np.array(out)
