@@ -40,6 +40,39 @@ def _events_time(lat, nsteps):
     return e0.elapsed_time(e1)
 
 
+def adjoint_leg(F, W, reps_done: int = 3) -> dict:
+    """Time of one gradient of the structure-factor misfit by the adjoint
+    (256 x 128 FP64, horizon 2000 sampled every 10, checkpoints every 100),
+    against the forward run of the same horizon.  The target spectrum comes
+    from a GPU twin run at (tau_s, tau_d, G) x (1.05, 0.95, 1.1)."""
+    import dataclasses
+    import numpy as np
+    import torch
+    rep, H, every, K = W.adjoint_256x128(), 2000, 10, 100
+    twin = dataclasses.replace(rep, tau_s=rep.tau_s * 1.05, tau_d=rep.tau_d * 0.95,
+                               G=rep.G * 1.1)
+    lt = F.Lattice([twin], precision=F.FP64, sample_every=every)
+    lt.step(H)
+    S_t = lt.structure_factor(0, F.FIELD_C)
+    del lt
+    w = np.ones_like(S_t)
+    w[:, 0] = 0.0
+    lat = F.Lattice([rep], precision=F.FP64, sample_every=every)
+    lat.sq_misfit_gradient(S_t, w, H, ckpt_every=K)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps_done):
+        J, g = lat.sq_misfit_gradient(S_t, w, H, ckpt_every=K)
+    t_grad = (time.perf_counter() - t0) / reps_done
+    fwd = F.Lattice([rep], precision=F.FP64, sample_every=every)
+    fwd.step(H)
+    ms_fwd = _events_time(fwd, H)
+    return {"workload": "adjoint 256x128 fp64, horizon 2000, sample every 10, checkpoint every 100",
+            "ms_per_gradient": round(t_grad * 1e3, 2), "forward_ms": round(ms_fwd, 2),
+            "gradient_over_forward": round(t_grad * 1e3 / ms_fwd, 2),
+            "grad": [float(x) for x in g], "J": float(J)}
+
+
 STEP_SOURCES = ("k_step.hip", "fnlb_device.hpp", "fnlb_internal.hpp", "fnlb_state.hpp")
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_k_step_batched96_fp32dev.json")
 
@@ -171,6 +204,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device copy of this size (3 times), the "
                          "reference for scaling HBM byte counters")
@@ -291,6 +325,9 @@ def main():
                                   "of both storage forms agrees with the FP64 oracle to 1e-5, "
                                   "far below the statistical error of any finite run, so equal "
                                   "S(q) error means equal step counts")
+
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(F, W)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(reps, args.cpu_budget)

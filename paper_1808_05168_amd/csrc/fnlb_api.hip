@@ -111,9 +111,10 @@ int auto_chunk(const fnlb_replica_params* reps, int n_rep) {
   int64_t seg_rows = 0;
   for (int r = 0; r < n_rep; ++r)
     seg_rows += (int64_t)((reps[r].Lx + kSeg - 1) / kSeg) * reps[r].Lz;
-  // aim for about 1024 blocks (four per compute unit) when the lattice allows
+  // aim for about 1024 blocks (four per compute unit) when the lattice allows;
+  // small lattices get single-row items so that they still spread over the chip
   const int64_t c = seg_rows / 1024;
-  int chunk = 4;
+  int chunk = 1;
   while (chunk * 2 <= c && chunk < 64) chunk *= 2;
   return chunk;
 }
@@ -499,7 +500,7 @@ int fnlb_autotune(fnlb_handle* h, int32_t steps_per_trial, int32_t* chunk_rows_o
   Plan& P = h->plan;
   int max_lz = 0;
   for (const RepInfo& R : P.info) max_lz = std::max(max_lz, R.Lz);
-  const int cands[] = {4, 8, 16, 32, 64, 128};
+  const int cands[] = {1, 2, 4, 8, 16, 32, 64, 128};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -814,7 +815,7 @@ int adj_plan(const fnlb_handle* h, int64_t horizon, int32_t K, AdjPlan& A) {
   take(A.mean, P * 16);
   take(A.rows, P * 16);
   take(A.Gq, P * 16);
-  take(A.tpart, ((N + 255) / 256) * 3 * 8);
+  take(A.tpart, ((N + 63) / 64) * 3 * 8);  // one partial per 64-thread block
   take(A.jpart, ((P + 255) / 256) * 8);
   take(A.small, 64);  // theta accumulator [3], J
   A.total = o;

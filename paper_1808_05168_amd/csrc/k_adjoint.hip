@@ -21,13 +21,15 @@
 //     whose force reads its densities (ghost rows fold onto the wall row) and
 //     pushes the adjoint of each pre-collision population back to the stored
 //     element it was pulled from.
-//  4. k_adj_theta: fixed-order sum of the per-block parameter partials.
+//  4. k_adj_theta: fixed-order (strided, then tree) sum of the per-block
+//     parameter partials.
 // The structure-factor term of a sample step is dJ/d dphi(r) =
 // (Lx Lz)^{-1/2} Re sum_{q in half spectrum} G(q) e^{+i q.r} with
 // G(q) = (2 w_q (S(q) - S*(q))) * 2 (Phi(q) - <Phi(q)>) / n, evaluated with
 // direct sums (k_adj_rows_fwd, k_adj_cols_fwd, k_adj_cols_inv, k_adj_rows_inv).
 #include "fnlb.h"
 #include "fnlb_device.hpp"
+#include "fnlb_fft.hpp"
 #include "fnlb_internal.hpp"
 #include "fnlb_state.hpp"
 
@@ -398,17 +400,33 @@ __global__ void k_adj_gather(const AdjArgs a) {
     }
 }
 
+// One block of 256 threads: strided partial sums in a fixed order, then a
+// fixed-shape tree; the same result on every run for a given block count.
 __global__ void k_adj_theta(const double* tpart, int nblocks, double* acc) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  __shared__ double sh[3][256];
+  const int t = threadIdx.x;
   double s0 = 0, s1 = 0, s2 = 0;
-  for (int b = 0; b < nblocks; ++b) {
+  for (int b = t; b < nblocks; b += 256) {
     s0 += tpart[3 * b];
     s1 += tpart[3 * b + 1];
     s2 += tpart[3 * b + 2];
   }
-  acc[0] += s0;
-  acc[1] += s1;
-  acc[2] += s2;
+  sh[0][t] = s0;
+  sh[1][t] = s1;
+  sh[2][t] = s2;
+  for (int h = 128; h >= 1; h >>= 1) {
+    __syncthreads();
+    if (t < h) {
+      sh[0][t] += sh[0][t + h];
+      sh[1][t] += sh[1][t + h];
+      sh[2][t] += sh[2][t + h];
+    }
+  }
+  if (t == 0) {
+    acc[0] += sh[0][0];
+    acc[1] += sh[1][0];
+    acc[2] += sh[2][0];
+  }
 }
 
 // ---- structure-factor misfit and its spectral adjoint (direct sums) ----
@@ -542,6 +560,91 @@ __global__ void k_adj_rows_inv(const SpecArgs a) {
   a.adjfield[n] = re * R.inv_norm;
 }
 
+// ---- the same four transforms by in-LDS FFTs (power-of-two lattices) ----
+
+// one block per row j: rows[j][kx], kx = 0..Lx/2
+__global__ void k_adj_rows_fwd_fft(const SpecArgs a) {
+  extern __shared__ double2 lds[];
+  const RepInfo& R = *a.rep;
+  const int Lx = R.Lx, nkx = Lx / 2 + 1, bits = __ffs(Lx) - 1, j = blockIdx.x;
+  double2* tws = lds + Lx;
+  for (int x = threadIdx.x; x < Lx; x += blockDim.x)
+    lds[bitrev(x, bits)] = make_double2(sample_field(a, R, j, x), 0.0);
+  for (int m = threadIdx.x; m < Lx / 2; m += blockDim.x) tws[m] = a.tw[m];
+  lds_fft(lds, bits, 1, tws);
+  for (int k = threadIdx.x; k < nkx; k += blockDim.x) a.rows[(size_t)j * nkx + k] = lds[k];
+}
+
+// one block per tile of 2^lt columns: Phi = norm FFT_z(rows), then G
+__global__ void k_adj_cols_fwd_fft(const SpecArgs a, int lt) {
+  extern __shared__ double2 lds[];
+  const RepInfo& R = *a.rep;
+  const int M = R.Lz, nkx = R.Lx / 2 + 1, bits = __ffs(M) - 1, T = 1 << lt;
+  const int kx0 = blockIdx.x << lt, nc = min(T, nkx - kx0), total = M << lt;
+  double2* tws = lds + total;
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    const int j = q >> lt, c = q & (T - 1);
+    if (c < nc) lds[c * M + bitrev(j, bits)] = a.rows[(size_t)j * nkx + kx0 + c];
+  }
+  for (int m = threadIdx.x; m < M / 2; m += blockDim.x) tws[m] = a.tw[R.Lx + m];
+  lds_fft(lds, bits, nc, tws);
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    const int c = q >> bits, kz = q & (M - 1);
+    if (c >= nc) continue;
+    const double2 P = lds[c * M + kz];
+    const size_t o = (size_t)kz * nkx + kx0 + c;
+    const double cw = a.Wq[o] * 2.0 / a.nsamp;
+    a.Gq[o] = make_double2(cw * (P.x * R.inv_norm - a.mean[o].x),
+                           cw * (P.y * R.inv_norm - a.mean[o].y));
+  }
+}
+
+// one block per tile of columns: rows[j][kx] = sum_kz G e^{+2 pi i kz j / Lz},
+// as the conjugate of the forward FFT of conj(G)
+__global__ void k_adj_cols_inv_fft(const SpecArgs a, int lt) {
+  extern __shared__ double2 lds[];
+  const RepInfo& R = *a.rep;
+  const int M = R.Lz, nkx = R.Lx / 2 + 1, bits = __ffs(M) - 1, T = 1 << lt;
+  const int kx0 = blockIdx.x << lt, nc = min(T, nkx - kx0), total = M << lt;
+  double2* tws = lds + total;
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    const int kz = q >> lt, c = q & (T - 1);
+    if (c < nc) {
+      const double2 g = a.Gq[(size_t)kz * nkx + kx0 + c];
+      lds[c * M + bitrev(kz, bits)] = make_double2(g.x, -g.y);
+    }
+  }
+  for (int m = threadIdx.x; m < M / 2; m += blockDim.x) tws[m] = a.tw[R.Lx + m];
+  lds_fft(lds, bits, nc, tws);
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    const int j = q >> lt, c = q & (T - 1);
+    if (c >= nc) continue;
+    const double2 v = lds[c * M + j];
+    a.rows[(size_t)j * nkx + kx0 + c] = make_double2(v.x, -v.y);
+  }
+}
+
+// one block per row j: adjfield(x, j) = norm Re sum_{kx <= Lx/2} rows[j][kx]
+// e^{+2 pi i kx x / Lx} = norm Re FFT(conj(rows[j][.]) padded with zeros)(x)
+__global__ void k_adj_rows_inv_fft(const SpecArgs a) {
+  extern __shared__ double2 lds[];
+  const RepInfo& R = *a.rep;
+  const int Lx = R.Lx, nkx = Lx / 2 + 1, bits = __ffs(Lx) - 1, j = blockIdx.x;
+  double2* tws = lds + Lx;
+  for (int k = threadIdx.x; k < Lx; k += blockDim.x) {
+    double2 v = make_double2(0.0, 0.0);
+    if (k < nkx) {
+      const double2 r = a.rows[(size_t)j * nkx + k];
+      v = make_double2(r.x, -r.y);
+    }
+    lds[bitrev(k, bits)] = v;
+  }
+  for (int m = threadIdx.x; m < Lx / 2; m += blockDim.x) tws[m] = a.tw[m];
+  lds_fft(lds, bits, 1, tws);
+  for (int x = threadIdx.x; x < Lx; x += blockDim.x)
+    a.adjfield[(size_t)j * Lx + x] = lds[x].x * R.inv_norm;
+}
+
 __global__ void k_sum(const double* parts, int n, double* out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double s = 0;
@@ -551,6 +654,11 @@ __global__ void k_sum(const double* parts, int n, double* out) {
 
 inline dim3 grid_for(int n) { return dim3((unsigned)((n + 255) / 256)); }
 
+// The per-node adjoint kernels run one wavefront per block, so that lattices
+// of a few tens of thousands of nodes still occupy every compute unit.
+constexpr int kNodeBlock = 64;
+inline dim3 node_grid(int n) { return dim3((unsigned)((n + kNodeBlock - 1) / kNodeBlock)); }
+
 }  // namespace
 
 hipError_t launch_adj_step(const RepInfo* d_rep, const RepInfo& h_rep, const double* state,
@@ -559,10 +667,10 @@ hipError_t launch_adj_step(const RepInfo* d_rep, const RepInfo& h_rep, const dou
                            double* tpart, double* theta_acc, hipStream_t s) {
   AdjArgs a{d_rep, state, mu_next, mu, dens, gf, gs, adjfield, field, t, tpart};
   const int N = h_rep.Lx * h_rep.Lz;
-  const dim3 g = grid_for(N);
-  hipLaunchKernelGGL(k_adj_local, g, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_gather, g, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_theta, dim3(1), dim3(64), 0, s, (const double*)tpart, (int)g.x,
+  const dim3 g = node_grid(N);
+  hipLaunchKernelGGL(k_adj_local, g, dim3(kNodeBlock), 0, s, a);
+  hipLaunchKernelGGL(k_adj_gather, g, dim3(kNodeBlock), 0, s, a);
+  hipLaunchKernelGGL(k_adj_theta, dim3(1), dim3(256), 0, s, (const double*)tpart, (int)g.x,
                      theta_acc);
   return hipGetLastError();
 }
@@ -578,7 +686,8 @@ hipError_t launch_adj_density(const RepInfo* d_rep, const RepInfo& h_rep, const 
   a.rep = d_rep;
   a.state = state;
   a.dens = dens;
-  hipLaunchKernelGGL(k_adj_density, grid_for(h_rep.Lx * h_rep.Lz), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_density, node_grid(h_rep.Lx * h_rep.Lz), dim3(kNodeBlock), 0, s,
+                     a);
   return hipGetLastError();
 }
 
@@ -618,6 +727,19 @@ hipError_t launch_adj_sample(const RepInfo* d_rep, const RepInfo& h_rep, const d
   a.Gq = Gq;
   a.adjfield = adjfield;
   const int P = h_rep.Lz * (h_rep.Lx / 2 + 1), N = h_rep.Lx * h_rep.Lz;
+  if (h_rep.pow2) {
+    const int Lx = h_rep.Lx, Lz = h_rep.Lz, nkx = Lx / 2 + 1;
+    int lt = 0;  // column tiles of 2^lt: at most 16 columns and 2048 values
+    while (lt < 4 && (2 << lt) * Lz <= 2048) ++lt;
+    const unsigned ntile = (unsigned)((nkx + (1 << lt) - 1) >> lt);
+    const size_t row_lds = (size_t)(Lx + Lx / 2) * sizeof(double2);
+    const size_t col_lds = (size_t)(((size_t)Lz << lt) + Lz / 2) * sizeof(double2);
+    hipLaunchKernelGGL(k_adj_rows_fwd_fft, dim3(Lz), dim3(256), row_lds, s, a);
+    hipLaunchKernelGGL(k_adj_cols_fwd_fft, dim3(ntile), dim3(256), col_lds, s, a, lt);
+    hipLaunchKernelGGL(k_adj_cols_inv_fft, dim3(ntile), dim3(256), col_lds, s, a, lt);
+    hipLaunchKernelGGL(k_adj_rows_inv_fft, dim3(Lz), dim3(256), row_lds, s, a);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_adj_rows_fwd, grid_for(P), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_adj_cols_fwd, grid_for(P), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_adj_cols_inv, grid_for(P), dim3(256), 0, s, a);
