@@ -3,6 +3,7 @@
 // synchronous read/write calls of the C ABI (include/fnlb.h).
 #include "fnlb.h"
 #include "fnlb_internal.hpp"
+#include "fnlb_state.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -391,15 +392,15 @@ const int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
 // Where f_l(x, j) of the current state is stored: link l of node
 // (x - c_lx, j - c_lz), or link opp(l) of (x, j) itself when that source lies
-// beyond a wall (mid-way bounce-back).  Returns the element index inside one
-// species block of the stored planes (plane stride `plane`, row pitch).
-size_t pull_source(const RepInfo& R, int l, int j, int x) {
+// beyond a wall (mid-way bounce-back).  Returns the element index of species
+// s in the replica's state block (tiled layout, state_index).
+size_t pull_source(const RepInfo& R, int s, int l, int j, int x) {
   const int js = j - kCZ[l];
-  if (js < 0 || js >= R.Lz) return (size_t)kOpp[l] * R.plane + (size_t)j * R.pitch + x;
+  if (js < 0 || js >= R.Lz) return state_index(9 * s + kOpp[l], j, x, R.pitch);
   int xs = x - kCX[l];
   if (xs < 0) xs += R.Lx;
   if (xs >= R.Lx) xs -= R.Lx;
-  return (size_t)l * R.plane + (size_t)js * R.pitch + xs;
+  return state_index(9 * s + l, js, xs, R.pitch);
 }
 
 }  // namespace
@@ -617,7 +618,7 @@ int fnlb_read_populations(fnlb_handle* h, int32_t rep, double* out) {
         const double rA = R.rA_mid + R.rA_step * j;
         const double ref = kW[l] * (s == 0 ? rA : R.rho0 - rA);
         for (int x = 0; x < R.Lx; ++x) {
-          const size_t k = (size_t)s * 9 * R.plane + pull_source(R, l, j, x);
+          const size_t k = pull_source(R, s, l, j, x);
           const double d = ss == 8 ? ((const double*)raw.data())[k]
                                    : (double)((const float*)raw.data())[k];
           out[(size_t)(s * 9 + l) * n + (size_t)j * R.Lx + x] = ref + d;
@@ -640,7 +641,7 @@ int fnlb_write_populations(fnlb_handle* h, int32_t rep, const double* in) {
         const double rA = R.rA_mid + R.rA_step * j;
         const double ref = kW[l] * (s == 0 ? rA : R.rho0 - rA);
         for (int x = 0; x < R.Lx; ++x) {
-          const size_t k = (size_t)s * 9 * R.plane + pull_source(R, l, j, x);
+          const size_t k = pull_source(R, s, l, j, x);
           const double d = in[(size_t)(s * 9 + l) * n + (size_t)j * R.Lx + x] - ref;
           if (ss == 8)
             ((double*)raw.data())[k] = d;
@@ -729,7 +730,7 @@ int fnlb_save(fnlb_handle* h, void* host_buf, size_t n) {
   if (n < need) return FNLB_ENOMEM;
   CkptHeader hd{};
   std::memcpy(hd.magic, kCkptMagic, 8);
-  hd.version = 1;
+  hd.version = 2;  // 2: tiled state layout
   hd.precision = h->opt.precision;
   hd.flags = h->opt.flags;
   hd.sample_every = h->opt.sample_every;
@@ -756,7 +757,7 @@ int fnlb_load(fnlb_handle* h, const void* host_buf, size_t n) {
   if (h->error) return h->error;
   CkptHeader hd;
   std::memcpy(&hd, host_buf, sizeof hd);
-  if (std::memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 1) return FNLB_EINVAL;
+  if (std::memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != 2) return FNLB_EINVAL;
   if (hd.state_bytes != h->plan.state_half || hd.accum_bytes != h->plan.accum_bytes ||
       hd.key != ckpt_key(h) || hd.t < 0 || hd.nsamples < 0)
     return FNLB_EINVAL;

@@ -29,7 +29,7 @@ inline int n_fields(int flags) { return (flags & FNLB_SAMPLE_VELOCITY) ? 4 : 2; 
 // the work buffer once at init, read by the kernels with scalar loads.
 struct alignas(256) RepInfo {
   int32_t Lx, Lz;         // lattice size
-  int32_t pitch;          // elements per row of a population plane (>= Lx)
+  int32_t pitch;          // row length rounded up to whole 64-column tiles (>= Lx)
   int32_t nstrips;        // ceil(Lx / 64): pressure partials per row
   int64_t plane;          // elements per (species, link) plane
   int64_t state_off;      // element offset of this replica in one state copy

@@ -73,11 +73,12 @@ __global__ void k_adj_density(const AdjArgs a) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= Lx * Lz) return;
   const int j = n / Lx, x = n - j * Lx;
-  const uint32_t plane_b = (uint32_t)(R.plane * 8), row_b = (uint32_t)R.pitch * 8;
-  const Rsrc in = make_rsrc(a.state, 18u * plane_b);
+  const uint32_t link_b = 64u * 8u, row_b = (uint32_t)R.pitch * 18u * 8u;
+  const Rsrc in = make_rsrc(a.state, (uint32_t)(18 * R.plane * 8));
   const int xm = x == 0 ? Lx - 1 : x - 1, xp = x == Lx - 1 ? 0 : x + 1;
   double o[18];
-  load_pulled(in, plane_b, row_b, j, Lz, (uint32_t)x * 8, (uint32_t)xm * 8, (uint32_t)xp * 8, o);
+  load_pulled(in, link_b, row_b, j, Lz, col_offset(x, 8), col_offset(xm, 8), col_offset(xp, 8),
+              o);
   double da = 0, db = 0;
   for (int l = 0; l < 9; ++l) {
     da += o[l];
@@ -108,14 +109,14 @@ __global__ __launch_bounds__(256) void k_adj_local(const AdjArgs a) {
   if (n < N) {
     const int j = n / Lx, x = n - j * Lx;
     const bool bot = j == 0, top = j == Lz - 1;
-    const uint32_t plane_b = (uint32_t)(R.plane * 8), row_b = (uint32_t)R.pitch * 8;
-    const Rsrc in = make_rsrc(a.state, 18u * plane_b);
+    const uint32_t link_b = 64u * 8u, row_b = (uint32_t)R.pitch * 18u * 8u;
+    const Rsrc in = make_rsrc(a.state, (uint32_t)(18 * R.plane * 8));
     const int xm = x == 0 ? Lx - 1 : x - 1, xp = x == Lx - 1 ? 0 : x + 1;
     double f[2][9];
     {
       double o[18];
-      load_pulled(in, plane_b, row_b, j, Lz, (uint32_t)x * 8, (uint32_t)xm * 8,
-                  (uint32_t)xp * 8, o);
+      load_pulled(in, link_b, row_b, j, Lz, col_offset(x, 8), col_offset(xm, 8),
+                  col_offset(xp, 8), o);
       for (int l = 0; l < 9; ++l) {
         f[0][l] = o[l];
         f[1][l] = o[9 + l];
@@ -203,11 +204,9 @@ __global__ __launch_bounds__(256) void k_adj_local(const AdjArgs a) {
 
     // ---- reverse pass ----
     double gft[2][9], gU[2] = {0, 0}, gF[2][2] = {{0, 0}, {0, 0}}, grS[2] = {0, 0};
-    const uint32_t off_b = (uint32_t)j * row_b + (uint32_t)x * 8;
     for (int sp = 0; sp < 2; ++sp) {
       double mus[9];
-      for (int l = 0; l < 9; ++l)
-        mus[l] = a.mu_next[(size_t)(9 * sp + l) * R.plane + off_b / 8];
+      for (int l = 0; l < 9; ++l) mus[l] = a.mu_next[state_index(9 * sp + l, j, x, R.pitch)];
       // forward moments of this species (post-fix)
       double m[9];
       for (int aa = 0; aa < 9; ++aa) {
@@ -380,7 +379,7 @@ __global__ void k_adj_gather(const AdjArgs a) {
                            cz * a.gs[(2 * sp + 1) * (size_t)N + k]);
     }
   }
-  const int64_t pitch = R.pitch, plane = R.plane;
+  const int pitch = R.pitch;
   const int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
   for (int sp = 0; sp < 2; ++sp)
     for (int l = 0; l < 9; ++l) {
@@ -390,11 +389,11 @@ __global__ void k_adj_gather(const AdjArgs a) {
       const int js = j - kCZa[l];
       size_t e;
       if (js < 0 || js >= Lz) {
-        e = (size_t)(9 * sp + opp[l]) * plane + (size_t)j * pitch + x;
+        e = state_index(9 * sp + opp[l], j, x, pitch);
       } else {
         int xs = x - kCXa[l];
         xs = xs < 0 ? xs + Lx : (xs >= Lx ? xs - Lx : xs);
-        e = (size_t)(9 * sp + l) * plane + (size_t)js * pitch + xs;
+        e = state_index(9 * sp + l, js, xs, pitch);
       }
       a.mu[e] = v;
     }

@@ -54,12 +54,12 @@ __device__ __forceinline__ void density(const Store (&o)[18], DT& da, DT& db) {
 
 // the 18 populations of one column pulled at row jr (segment-edge column)
 template <typename Store>
-__device__ __forceinline__ void edge_pull(Rsrc r, uint32_t plane_b, uint32_t row_b, int jr,
+__device__ __forceinline__ void edge_pull(Rsrc r, uint32_t link_b, uint32_t row_b, int jr,
                                           int Lz, int Lx, int col, Store (&o)[18]) {
   constexpr uint32_t SB = sizeof(Store);
   const int cm = col == 0 ? Lx - 1 : col - 1, cp = col == Lx - 1 ? 0 : col + 1;
-  load_pulled(r, plane_b, row_b, jr, Lz, (uint32_t)col * SB, (uint32_t)cm * SB,
-              (uint32_t)cp * SB, o);
+  load_pulled(r, link_b, row_b, jr, Lz, col_offset(col, SB), col_offset(cm, SB),
+              col_offset(cp, SB), o);
 }
 
 template <typename Real, typename Store, int MODE>
@@ -91,10 +91,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   const RepInfo& R = a.reps[it.rep];
   const int Lx = R.Lx, Lz = R.Lz;
   constexpr uint32_t SB = sizeof(Store);
-  const uint32_t plane_b = (uint32_t)(R.plane * SB);
-  const uint32_t row_b = (uint32_t)R.pitch * SB;
-  const Rsrc in = make_rsrc((const char*)a.state_in + R.state_off * SB, 18u * plane_b);
-  const Rsrc out = make_rsrc((char*)a.state_out + R.state_off * SB, 18u * plane_b);
+  const uint32_t link_b = 64u * SB;                 // tiled layout of the state block
+  const uint32_t row_b = (uint32_t)R.pitch * 18u * SB;
+  const uint32_t block_b = (uint32_t)(18 * R.plane * SB);
+  const Rsrc in = make_rsrc((const char*)a.state_in + R.state_off * SB, block_b);
+  const Rsrc out = make_rsrc((char*)a.state_out + R.state_off * SB, block_b);
   const int flags = R.flags;
 
   // columns of this segment
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   const bool act = tid < width;
   const int x = act ? X0 + tid : X0;
   const int xm = x == 0 ? Lx - 1 : x - 1, xp = x == Lx - 1 ? 0 : x + 1;
-  const uint32_t xb = (uint32_t)x * SB, xmb = (uint32_t)xm * SB, xpb = (uint32_t)xp * SB;
+  const uint32_t xb = col_offset(x, SB), xmb = col_offset(xm, SB), xpb = col_offset(xp, SB);
   const bool whole_row = (X0 == 0 && width == Lx);
   const int hl = X0 == 0 ? Lx - 1 : X0 - 1;          // left edge column
   const int hr = X0 + width == Lx ? 0 : X0 + width;  // right edge column
@@ -163,15 +164,22 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   const int ecol = lane < 18 ? hl : hr;
   int exs = ecol - ecx;
   exs = exs < 0 ? exs + Lx : (exs >= Lx ? exs - Lx : exs);
-  auto pull_edges = [&](int jr) {
+  // the load is issued here and its value written to LDS only just before the
+  // row barrier, so that the noise of the current row overlaps the latency of
+  // the next row's loads
+  auto pull_edges = [&](int jr) -> Store {
     if (edge_lane) {
       const int js = jr - ecz;
       const bool bounce = js < 0 || js >= Lz;
-      const uint32_t pl = (uint32_t)(9 * es + (bounce ? eopp : el)) * plane_b;
+      const uint32_t pl = (uint32_t)(9 * es + (bounce ? eopp : el)) * link_b;
       const uint32_t off = pl + (uint32_t)(bounce ? jr : js) * row_b +
-                           (uint32_t)(bounce ? ecol : exs) * SB;
-      edge[jr & 1][lane] = bload<Store>(in, off, 0);
+                           col_offset(bounce ? ecol : exs, SB);
+      return bload<Store>(in, off, 0);
     }
+    return (Store)0;
+  };
+  auto put_edges = [&](int jr, Store v) {
+    if (edge_lane) edge[jr & 1][lane] = v;
   };
   auto sum_edges = [&](int jr) {
     if (!whole_row && (tid == 0 || tid == width - 1)) {
@@ -200,42 +208,48 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
 
   const int j0 = it.j0, j1 = it.j1;
   Store cur[18], nxt[18];
-  load_pulled(in, plane_b, row_b, j0, Lz, xb, xmb, xpb, cur);
+  load_pulled(in, link_b, row_b, j0, Lz, xb, xmb, xpb, cur);
   put_row(j0, cur);
   if (j0 > 0) {
     Store tmp[18];
-    load_pulled(in, plane_b, row_b, j0 - 1, Lz, xb, xmb, xpb, tmp);
+    load_pulled(in, link_b, row_b, j0 - 1, Lz, xb, xmb, xpb, tmp);
     put_row(j0 - 1, tmp);
   }
   if (!whole_row && (tid == 0 || tid == width - 1)) {
     const int col = tid == 0 ? hl : hr, rc = tid == 0 ? 0 : width + 1;
     for (int jr = max(j0 - 1, 0); jr <= j0; ++jr) {
       Store o[18];
-      edge_pull<Store>(in, plane_b, row_b, jr, Lz, Lx, col, o);
+      edge_pull<Store>(in, link_b, row_b, jr, Lz, Lx, col, o);
       put_col(jr, rc, o);
     }
   }
 
   for (int j = j0; j < j1; ++j) {
     const bool top = (j == Lz - 1), bot = (j == 0);
+    Store ev = (Store)0;
     if (!top) {
-      load_pulled(in, plane_b, row_b, j + 1, Lz, xb, xmb, xpb, nxt);
-      pull_edges(j + 1);
+      load_pulled(in, link_b, row_b, j + 1, Lz, xb, xmb, xpb, nxt);
+      ev = pull_edges(j + 1);
     }
 
-    // thermal noise of this node: 14 standard normals (independent of loads)
-    // (species A uses g_0..g_7 from calls 0 and 1; species B uses g_8..g_13
-    // from calls 2 and 3, drawn after the collision of A)
+    // thermal noise of this node: 14 standard normals, drawn while the next
+    // row's loads are in flight (species A uses g_0..g_7 from calls 0 and 1,
+    // species B g_8..g_13 from calls 2 and 3)
     const uint32_t node = (uint32_t)(j * Lx + x);
-    Real gA0[4], gA1[4];
+    Real gA0[4], gA1[4], gB0[4], gB1[4];
     if constexpr (MODE != kSampleOnly) {
       if (wave_act) {
+        node_normals(node, (uint64_t)t, 2u, k0, k1, gB0);
+        node_normals(node, (uint64_t)t, 3u, k0, k1, gB1);
         node_normals(node, (uint64_t)t, 0u, k0, k1, gA0);
         node_normals(node, (uint64_t)t, 1u, k0, k1, gA1);
       }
     }
 
-    if (!top) put_row(j + 1, nxt);
+    if (!top) {
+      put_row(j + 1, nxt);
+      put_edges(j + 1, ev);
+    }
     __syncthreads();
     if (!top) sum_edges(j + 1);
 
@@ -466,9 +480,6 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
       };
       collide(dA, rhoA, jAx, jAz, FAx, FAz, xi1, xi2, sA3 * gA0[2], sA4 * gA0[3],
               sA5 * gA1[0], sA6 * gA1[1], sA6 * gA1[2], sA8 * gA1[3]);
-      Real gB0[4], gB1[4];
-      node_normals(node, (uint64_t)t, 2u, k0, k1, gB0);
-      node_normals(node, (uint64_t)t, 3u, k0, k1, gB1);
       collide(dB, rhoB, jBx, jBz, FBx, FBz, -xi1, -xi2, sB3 * gB0[0], sB4 * gB0[1],
               sB5 * gB0[2], sB6 * gB0[3], sB6 * gB1[0], sB8 * gB1[1]);
 
@@ -478,16 +489,16 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
         const uint32_t off = (uint32_t)j * row_b + xb;
         const Real up = top ? (Real)0 : (Real)1, dn = bot ? (Real)0 : (Real)1;
         auto emit = [&](int s, const Real(&d)[9], Real sh1, Real sh5) {
-          const uint32_t p = (uint32_t)(9 * s) * plane_b;
+          const uint32_t p = (uint32_t)(9 * s) * link_b;
           bstore<Store>(out, off, p, (Store)d[0]);
-          bstore<Store>(out, off, p + plane_b, (Store)d[1]);
-          bstore<Store>(out, off, p + 2 * plane_b, (Store)(d[2] + up * sh1));
-          bstore<Store>(out, off, p + 3 * plane_b, (Store)d[3]);
-          bstore<Store>(out, off, p + 4 * plane_b, (Store)(d[4] - dn * sh1));
-          bstore<Store>(out, off, p + 5 * plane_b, (Store)(d[5] + up * sh5));
-          bstore<Store>(out, off, p + 6 * plane_b, (Store)(d[6] + up * sh5));
-          bstore<Store>(out, off, p + 7 * plane_b, (Store)(d[7] - dn * sh5));
-          bstore<Store>(out, off, p + 8 * plane_b, (Store)(d[8] - dn * sh5));
+          bstore<Store>(out, off, p + link_b, (Store)d[1]);
+          bstore<Store>(out, off, p + 2 * link_b, (Store)(d[2] + up * sh1));
+          bstore<Store>(out, off, p + 3 * link_b, (Store)d[3]);
+          bstore<Store>(out, off, p + 4 * link_b, (Store)(d[4] - dn * sh1));
+          bstore<Store>(out, off, p + 5 * link_b, (Store)(d[5] + up * sh5));
+          bstore<Store>(out, off, p + 6 * link_b, (Store)(d[6] + up * sh5));
+          bstore<Store>(out, off, p + 7 * link_b, (Store)(d[7] - dn * sh5));
+          bstore<Store>(out, off, p + 8 * link_b, (Store)(d[8] - dn * sh5));
         };
         emit(0, dA, shA1, shA5);
         emit(1, dB, -shA1, -shA5);
