@@ -74,6 +74,14 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   __shared__ DT ring[4][2][kRow];
   __shared__ double oring[kTwo ? 4 : 1][2][kTwo ? kRow : 1];
   __shared__ Store edge[2][36];  // pulled populations of the two edge columns
+  // With FP32 storage a lane parks the pulled populations of the rows it has
+  // loaded but not yet collided in LDS (two slots, private to the lane).  That
+  // frees the registers to receive the loads of the row after next while the
+  // current row is collided, so a row's loads are in flight for a whole
+  // iteration.  FP64 keeps the row in registers (its LDS share would cost
+  // blocks per compute unit).
+  constexpr bool kStage = sizeof(Store) == 4;
+  __shared__ Store pbuf[kStage ? 2 : 1][18][kStage ? kBlock : 1];
 
   // XCD-aware block order: consecutive hardware blocks go to different XCDs,
   // so give each XCD a contiguous range of work items (neighbouring segments
@@ -207,9 +215,17 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   const Real shA1 = (Real)(-rAs / 9.0), shA5 = (Real)(-rAs / 36.0);
 
   const int j0 = it.j0, j1 = it.j1;
+  const int jlast = min(j1, Lz - 1);  // last row whose densities the item needs
+  auto stage = [&](int jr, const Store(&o)[18]) {
+    if constexpr (kStage) {
+#pragma unroll
+      for (int q = 0; q < 18; ++q) pbuf[jr & 1][q][tid] = o[q];
+    }
+  };
   Store cur[18], nxt[18];
   load_pulled(in, link_b, row_b, j0, Lz, xb, xmb, xpb, cur);
   put_row(j0, cur);
+  stage(j0, cur);
   if (j0 > 0) {
     Store tmp[18];
     load_pulled(in, link_b, row_b, j0 - 1, Lz, xb, xmb, xpb, tmp);
@@ -224,12 +240,22 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     }
   }
 
+  Store ev = (Store)0;
+  if constexpr (kStage) {
+    // the first row ahead is in flight before the loop
+    if (j0 + 1 <= jlast) {
+      load_pulled(in, link_b, row_b, j0 + 1, Lz, xb, xmb, xpb, nxt);
+      ev = pull_edges(j0 + 1);
+    }
+  }
+
   for (int j = j0; j < j1; ++j) {
     const bool top = (j == Lz - 1), bot = (j == 0);
-    Store ev = (Store)0;
-    if (!top) {
-      load_pulled(in, link_b, row_b, j + 1, Lz, xb, xmb, xpb, nxt);
-      ev = pull_edges(j + 1);
+    if constexpr (!kStage) {
+      if (!top) {
+        load_pulled(in, link_b, row_b, j + 1, Lz, xb, xmb, xpb, nxt);
+        ev = pull_edges(j + 1);
+      }
     }
 
     // thermal noise of this node: 14 standard normals, drawn while the next
@@ -249,9 +275,21 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     if (!top) {
       put_row(j + 1, nxt);
       put_edges(j + 1, ev);
+      stage(j + 1, nxt);
+    }
+    if constexpr (kStage) {
+      // the row after next: its loads run through the barrier and the collision
+      if (j + 2 <= jlast) {
+        load_pulled(in, link_b, row_b, j + 2, Lz, xb, xmb, xpb, nxt);
+        ev = pull_edges(j + 2);
+      }
     }
     __syncthreads();
     if (!top) sum_edges(j + 1);
+    if constexpr (kStage) {
+#pragma unroll
+      for (int q = 0; q < 18; ++q) cur[q] = pbuf[j & 1][q][tid];
+    }
 
     // the 3 x 3 density stencil; ghost rows beyond the walls repeat the wall row
     const int jU = top ? j : j + 1, jD = bot ? j : j - 1;
@@ -506,8 +544,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
      }
     }
 
+    if constexpr (!kStage) {
 #pragma unroll
-    for (int q = 0; q < 18; ++q) cur[q] = nxt[q];
+      for (int q = 0; q < 18; ++q) cur[q] = nxt[q];
+    }
   }
 }
 
