@@ -99,6 +99,20 @@ def _traffic_from_profiles():
         return None
 
 
+def summarize_trace(trace_dir, out_md, title, command, top=16):
+    """Kernel-trace statistics of a rocprofv3 run as a short Markdown summary."""
+    import csv
+    stats = list(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_stats.csv"))))
+    lines = [f"# {title}", "", "Command (run from the repository root; <out> is any output "
+             "directory):", "", "```", command.strip(), "```", "",
+             "| kernel | calls | average us | share % |", "|---|---|---|---|"]
+    for r in stats[:top]:
+        lines.append(f"| {r['Name'][:90]} | {r['Calls']} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def summarize_profile(trace_dir, fetch_dir, write_dir, out_md, command):
     """Turns rocprofv3 outputs of this benchmark into the committed summary:
     kernel-trace statistics, the average duration of the step kernel in the
@@ -205,6 +219,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint leg (for its kernel trace)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a plain device copy of this size (3 times), the "
                          "reference for scaling HBM byte counters")
@@ -215,7 +231,15 @@ def main():
     ap.add_argument("--summarize-profile", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
                     help="summarise rocprofv3 output directories into profiles/ (CPU only)")
     ap.add_argument("--profile-command", default="")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE", "NAME", "TITLE"),
+                    help="summarise a rocprofv3 kernel trace into profiles/NAME.md (CPU only)")
     args = ap.parse_args()
+
+    if args.summarize_trace:
+        d, name, title = args.summarize_trace
+        summarize_trace(d, os.path.join(ROOT, "profiles", name + ".md"), title,
+                        args.profile_command)
+        return
 
     if args.summarize_profile:
         out = os.path.join(ROOT, "profiles", "k_step_batched96_fp32dev.md")
@@ -235,6 +259,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_leg(F, W)}), flush=True)
+        return
 
     if args.copy_calibration_mb > 0:
         n = args.copy_calibration_mb * (1 << 20) // 4
