@@ -790,6 +790,56 @@ int ora_sq_misfit(const ora_params* p, int64_t horizon, int field, const double*
   return 0;
 }
 
+// Pressure-profile misfit over a horizon: from the rest state on the imposed
+// profile, run `horizon` steps sampling the pressure per reading R9, form the
+// time-averaged row means Pbar_j of P - P_ref (reading R11) and return
+// J = sum_j weight_j (Pbar_j - P_target_j)^2.
+}  // extern "C"
+
+namespace {
+template <typename T>
+T p_misfit(const ora_params& p, const Theta<T>& th, int64_t horizon, const double* P_target,
+           const double* weight) {
+  Sim<T> sim(p, th);
+  std::vector<T> f((size_t)2 * Q * sim.n), prof((size_t)p.Lz, T(0));
+  T ps = T(0), ps2 = T(0);
+  sim.init(f.data());
+  int64_t ns = 0;
+  sim.run(f.data(), 0, horizon, nullptr, &ps, &ps2, prof.data(), &ns);
+  const double n = ns > 0 ? (double)ns : 1.0;
+  T J = T(0);
+  for (int j = 0; j < p.Lz; ++j) {
+    const T d = prof[j] / n - P_target[j];
+    J += weight[j] * d * d;
+  }
+  return J;
+}
+}  // namespace
+
+extern "C" {
+
+int ora_p_misfit(const ora_params* p, int64_t horizon, const double* P_target,
+                 const double* weight, double* J) {
+  if (check_params(p) || horizon < 0) return -1;
+  Theta<double> th{p->tau_d, p->tau_s, p->G};
+  *J = p_misfit<double>(*p, th, horizon, P_target, weight);
+  return 0;
+}
+
+int ora_p_misfit_cs(const ora_params* p, int64_t horizon, const double* P_target,
+                    const double* weight, int which, double h, double* dJ) {
+  if (check_params(p) || horizon < 0 || which < 0 || which > 2 || !(h > 0)) return -1;
+  typedef std::complex<double> C;
+  Theta<C> th{C(p->tau_d), C(p->tau_s), C(p->G)};
+  const C ih(0.0, h);
+  if (which == 0) th.tau_s += ih;
+  if (which == 1) th.tau_d += ih;
+  if (which == 2) th.G += ih;
+  const C J = p_misfit<C>(*p, th, horizon, P_target, weight);
+  *dJ = J.imag() / h;
+  return 0;
+}
+
 // Complex-step derivative dJ/dtheta_which (0: tau_s, 1: tau_d, 2: G):
 // Im J(theta + i h e_which) / h, exact to rounding for small h.
 int ora_sq_misfit_cs(const ora_params* p, int64_t horizon, int field, const double* S_target,

@@ -245,3 +245,41 @@ def sq_misfit_complex_step(rep, horizon: int, every: int, field: int, S_target: 
                               ctypes.byref(d)):
         raise ValueError("oracle: invalid arguments")
     return d.value
+
+
+def _p_misfit_argtypes():
+    dp = ctypes.POINTER(ctypes.c_double)
+    pp = ctypes.POINTER(OraParams)
+    lib().ora_p_misfit.argtypes = [pp, ctypes.c_int64, dp, dp, dp]
+    lib().ora_p_misfit_cs.argtypes = [pp, ctypes.c_int64, dp, dp, ctypes.c_int, ctypes.c_double,
+                                      dp]
+
+
+def p_misfit(rep, horizon: int, every: int, P_target: np.ndarray, weight: np.ndarray,
+             flags: int = DEFAULT_FLAGS) -> float:
+    """J = sum_j weight_j (Pbar_j - P_target_j)^2, Pbar_j the time-averaged row
+    means of P - P_ref over a run of `horizon` steps sampled every `every`."""
+    _p_misfit_argtypes()
+    p = params(rep, flags, every)
+    Pt = np.ascontiguousarray(P_target, dtype=np.float64)
+    w = np.ascontiguousarray(weight, dtype=np.float64)
+    J = ctypes.c_double()
+    if lib().ora_p_misfit(ctypes.byref(p), horizon, _dp(Pt), _dp(w), ctypes.byref(J)):
+        raise ValueError("oracle: invalid arguments")
+    return J.value
+
+
+def p_misfit_complex_step(rep, horizon: int, every: int, P_target: np.ndarray,
+                          weight: np.ndarray, which: int, h: float = 1e-20,
+                          flags: int = DEFAULT_FLAGS) -> float:
+    """dJ/d(tau_s, tau_d, G)[which] of the pressure-profile misfit by
+    complex-step differentiation of the oracle."""
+    _p_misfit_argtypes()
+    p = params(rep, flags, every)
+    Pt = np.ascontiguousarray(P_target, dtype=np.float64)
+    w = np.ascontiguousarray(weight, dtype=np.float64)
+    d = ctypes.c_double()
+    if lib().ora_p_misfit_cs(ctypes.byref(p), horizon, _dp(Pt), _dp(w), which, h,
+                             ctypes.byref(d)):
+        raise ValueError("oracle: invalid arguments")
+    return d.value
