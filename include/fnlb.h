@@ -207,7 +207,8 @@ int fnlb_checkpoint_bytes(const fnlb_handle* h, size_t* bytes);
 int fnlb_save(fnlb_handle* h, void* host_buf, size_t n);
 int fnlb_load(fnlb_handle* h, const void* host_buf, size_t n);
 
-/* Bytes of the device workspace fnlb_sq_misfit_gradient needs for a horizon
+/* Bytes of the device workspace fnlb_sq_misfit_gradient and
+ * fnlb_pressure_misfit_gradient need for a horizon
  * of `horizon` steps with populations checkpointed every `ckpt_every` steps:
  * ceil(horizon/ckpt_every) + ckpt_every + 2 state copies plus O(Lx Lz)
  * adjoint fields.  FNLB_EINVAL when the handle does not meet the
@@ -235,6 +236,18 @@ int fnlb_adjoint_bytes_required(const fnlb_handle* h, int64_t horizon, int32_t c
 int fnlb_sq_misfit_gradient(fnlb_handle* h, int32_t field, const double* S_target,
                             const double* weight, int64_t horizon, int32_t ckpt_every,
                             void* d_adj, size_t adj_bytes, double* J, double* grad);
+
+/* Pressure-profile misfit and its gradient, by the same adjoint: with
+ * Pbar_j the time-averaged row mean of P - P_ref over the samples of the
+ * horizon (the pressure of fnlb_read_pressure, Eq. (24) / Sec. IV.C),
+ *   J = sum_j weight_j (Pbar_j - P_target_j)^2,
+ * and grad = dJ/d(tau_s, tau_d, G), G entering both P (its non-local part
+ * and P_ref) and the dynamics.  P_target and weight: host arrays of Lz
+ * doubles.  Requirements, workspace and effects as for
+ * fnlb_sq_misfit_gradient. */
+int fnlb_pressure_misfit_gradient(fnlb_handle* h, const double* P_target, const double* weight,
+                                  int64_t horizon, int32_t ckpt_every, void* d_adj,
+                                  size_t adj_bytes, double* J, double* grad);
 
 /* Frees the handle's host metadata.  Caller buffers are untouched. */
 int fnlb_destroy(fnlb_handle* h);

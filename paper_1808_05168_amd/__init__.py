@@ -6,8 +6,9 @@ of ``include/fnlb.h``; this package is its thin Python binding.
 """
 from .fnlb import (ASTAR, DEFAULT_FLAGS, FIELD_C, FIELD_RHO, FIELD_UX, FIELD_UZ, FORCE_LITERAL,
                    FP32_DEV, FP64, NO_GRAPH, NOISE_LOC, SAMPLE_VELOCITY, WALL_UZ_FIX, FnlbError,
-                   Lattice, bytes_required, load, sq_misfit)
+                   Lattice, bytes_required, load, p_misfit, sq_misfit)
 
 __all__ = ["ASTAR", "DEFAULT_FLAGS", "FIELD_C", "FIELD_RHO", "FIELD_UX", "FIELD_UZ",
            "FORCE_LITERAL", "FP32_DEV", "FP64", "NO_GRAPH", "NOISE_LOC", "SAMPLE_VELOCITY",
-           "WALL_UZ_FIX", "FnlbError", "Lattice", "bytes_required", "load", "sq_misfit"]
+           "WALL_UZ_FIX", "FnlbError", "Lattice", "bytes_required", "load", "p_misfit",
+           "sq_misfit"]

@@ -808,7 +808,7 @@ int adj_plan(const fnlb_handle* h, int64_t horizon, int32_t K, AdjPlan& A) {
   take(A.gf, 18 * N * 8);
   take(A.gs, 4 * N * 8);
   take(A.dens, 2 * N * 8);
-  take(A.adjf, N * 8);
+  take(A.adjf, 2 * N * 8);  // sample term: one field, or the two pressure adjoints
   take(A.acc, h->plan.accum_bytes);
   take(A.target, P * 8);
   take(A.weight, P * 8);
@@ -837,11 +837,16 @@ int fnlb_adjoint_bytes_required(const fnlb_handle* h, int64_t horizon, int32_t c
   return FNLB_OK;
 }
 
-int fnlb_sq_misfit_gradient(fnlb_handle* h, int32_t field, const double* S_target,
-                            const double* weight, int64_t horizon, int32_t ckpt_every,
-                            void* d_adj, size_t adj_bytes, double* J, double* grad) {
-  if (!h || !S_target || !weight || !d_adj || !J || !grad || (field != 0 && field != 1))
-    return FNLB_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// The checkpointed adjoint of a misfit over a horizon: the structure factor of
+// `field` (pressure false) or the pressure row profile (pressure true).
+int adjoint_gradient(fnlb_handle* h, bool pressure, int32_t field, const double* S_target,
+                     const double* weight, int64_t horizon, int32_t ckpt_every, void* d_adj,
+                     size_t adj_bytes, double* J, double* grad) {
+  if (!h || !S_target || !weight || !d_adj || !J || !grad) return FNLB_EINVAL;
   if (h->error) return h->error;
   AdjPlan A;
   int rc = adj_plan(h, horizon, ckpt_every, A);
@@ -877,8 +882,9 @@ int fnlb_sq_misfit_gradient(fnlb_handle* h, int32_t field, const double* S_targe
     return e;
   };
 
-  hipError_t e = hipMemcpyAsync(W + A.target, S_target, P * 8, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(W + A.weight, weight, P * 8, hipMemcpyHostToDevice, s);
+  const size_t nt = pressure ? (size_t)R.Lz : P;  // target and weight entries
+  hipError_t e = hipMemcpyAsync(W + A.target, S_target, nt * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(W + A.weight, weight, nt * 8, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_fill_zero(acc, h->plan.accum_bytes, s);
   if (e == hipSuccess) e = launch_fill_zero(W + A.small, 64, s);
   // forward sweep: checkpoints every K steps, samples into private sums
@@ -894,11 +900,19 @@ int fnlb_sq_misfit_gradient(fnlb_handle* h, int32_t field, const double* S_targe
   }
   if (nsamp == 0) return e == hipSuccess ? FNLB_EINVAL : dev_err(h, e);
   const double ns = (double)nsamp;
-  if (e == hipSuccess)
-    e = launch_adj_misfit(dR, R, h->d_tw(), acc, (const double*)(W + A.target),
-                          (const double*)(W + A.weight), (double*)(W + A.Wq),
-                          (double2*)(W + A.mean), (double*)(W + A.jpart), field, ns, s);
-  if (e == hipSuccess) e = launch_sum((const double*)(W + A.jpart), (int)((P + 255) / 256), dJ, s);
+  if (pressure) {
+    // Wq holds lam_j = dJ/d(P - P_ref) of a node of row j in one sample
+    if (e == hipSuccess)
+      e = launch_adj_pmisfit(dR, R, acc, (const double*)(W + A.target),
+                             (const double*)(W + A.weight), ns, (double*)(W + A.Wq), dJ, s);
+  } else {
+    if (e == hipSuccess)
+      e = launch_adj_misfit(dR, R, h->d_tw(), acc, (const double*)(W + A.target),
+                            (const double*)(W + A.weight), (double*)(W + A.Wq),
+                            (double2*)(W + A.mean), (double*)(W + A.jpart), field, ns, s);
+    if (e == hipSuccess)
+      e = launch_sum((const double*)(W + A.jpart), (int)((P + 255) / 256), dJ, s);
+  }
   // reverse sweep over the checkpointed segments
   if (e == hipSuccess) e = launch_fill_zero(mu[0], 2 * SH, s);
   int nx = 0;  // mu[nx] holds dJ/dS_{t+1}
@@ -912,16 +926,21 @@ int fnlb_sq_misfit_gradient(fnlb_handle* h, int32_t field, const double* S_targe
       e = launch_adj_density(dR, R, S, (double*)(W + A.dens), s);
       const double* adjf = nullptr;
       if (e == hipSuccess && sampled(t0 + k)) {
-        e = launch_adj_sample(dR, R, h->d_tw(), (const double*)(W + A.Wq),
-                              (const double2*)(W + A.mean), field, ns,
-                              (const double*)(W + A.dens), (double2*)(W + A.rows),
-                              (double2*)(W + A.Gq), (double*)(W + A.adjf), s);
+        if (pressure)
+          e = launch_adj_psample(dR, R, (const double*)(W + A.dens), (const double*)(W + A.Wq),
+                                 (double*)(W + A.adjf), (double*)(W + A.tpart), theta, s);
+        else
+          e = launch_adj_sample(dR, R, h->d_tw(), (const double*)(W + A.Wq),
+                                (const double2*)(W + A.mean), field, ns,
+                                (const double*)(W + A.dens), (double2*)(W + A.rows),
+                                (double2*)(W + A.Gq), (double*)(W + A.adjf), s);
         adjf = (const double*)(W + A.adjf);
       }
       if (e == hipSuccess)
         e = launch_adj_step(dR, R, S, (const double*)mu[nx], (double*)mu[nx ^ 1],
                             (double*)(W + A.dens), (double*)(W + A.gf), (double*)(W + A.gs),
-                            adjf, field, t0 + k, (double*)(W + A.tpart), theta, s);
+                            adjf, pressure ? kAdjPressure : field, t0 + k,
+                            (double*)(W + A.tpart), theta, s);
       nx ^= 1;
     }
   }
@@ -936,6 +955,25 @@ int fnlb_sq_misfit_gradient(fnlb_handle* h, int32_t field, const double* S_targe
   grad[1] = -ld * ld * out[1];
   grad[2] = out[2];
   return FNLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fnlb_sq_misfit_gradient(fnlb_handle* h, int32_t field, const double* S_target,
+                            const double* weight, int64_t horizon, int32_t ckpt_every,
+                            void* d_adj, size_t adj_bytes, double* J, double* grad) {
+  if (field != 0 && field != 1) return FNLB_EINVAL;
+  return adjoint_gradient(h, false, field, S_target, weight, horizon, ckpt_every, d_adj,
+                          adj_bytes, J, grad);
+}
+
+int fnlb_pressure_misfit_gradient(fnlb_handle* h, const double* P_target, const double* weight,
+                                  int64_t horizon, int32_t ckpt_every, void* d_adj,
+                                  size_t adj_bytes, double* J, double* grad) {
+  return adjoint_gradient(h, true, 0, P_target, weight, horizon, ckpt_every, d_adj, adj_bytes,
+                          J, grad);
 }
 
 int fnlb_destroy(fnlb_handle* h) {

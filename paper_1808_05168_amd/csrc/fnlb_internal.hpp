@@ -119,5 +119,13 @@ hipError_t launch_adj_sample(const RepInfo* d_rep, const RepInfo& h_rep, const d
                              const double* dens, double2* rows, double2* Gq, double* adjfield,
                              hipStream_t s);
 hipError_t launch_sum(const double* parts, int n, double* out, hipStream_t s);
+// the adjoint's sample term is a pressure term instead of a structure factor
+constexpr int kAdjPressure = 2;
+hipError_t launch_adj_pmisfit(const RepInfo* d_rep, const RepInfo& h_rep, const double* acc,
+                              const double* target, const double* weight, double nsamp,
+                              double* lam, double* J, hipStream_t s);
+hipError_t launch_adj_psample(const RepInfo* d_rep, const RepInfo& h_rep, const double* dens,
+                              const double* lam, double* adjfield, double* tpart,
+                              double* theta_acc, hipStream_t s);
 
 }  // namespace fnlb

@@ -321,8 +321,11 @@ __global__ __launch_bounds__(256) void k_adj_local(const AdjArgs a) {
     }
     grS[0] += grho;
     grS[1] += grho;
-    // structure-factor term of a sample step
-    if (a.adjfield) {
+    // sample term: the pressure's density adjoints, or a structure factor's
+    if (a.adjfield && a.field == kAdjPressure) {
+      grS[0] += a.adjfield[n];
+      grS[1] += a.adjfield[(size_t)N + n];
+    } else if (a.adjfield) {
       const double v = a.adjfield[n];
       if (a.field == 0) {  // delta c = rho^A / rho - c_0
         grS[0] += v * rS[1] / (rho * rho);
@@ -644,6 +647,89 @@ __global__ void k_adj_rows_inv_fft(const SpecArgs a) {
     a.adjfield[(size_t)j * Lx + x] = lds[x].x * R.inv_norm;
 }
 
+// ---- pressure-profile misfit J = sum_j w_j (Pbar_j - P*_j)^2 ----
+
+// One block: lam_j = dJ/d(P - P_ref)(x, j) of every node of row j in one
+// sample, 2 w_j (Pbar_j - P*_j) / (n Lx), and J by a fixed-order sum.
+__global__ void k_adj_pmisfit(const RepInfo* rep, const double* acc, const double* target,
+                              const double* weight, double nsamp, double* lam, double* J) {
+  __shared__ double sh[256];
+  const RepInfo& R = *rep;
+  const double* prof = acc + R.pacc_off + 2;  // sums of the row means of P - P_ref
+  double part = 0;
+  for (int j = threadIdx.x; j < R.Lz; j += blockDim.x) {
+    const double d = prof[j] / nsamp - target[j];
+    lam[j] = 2.0 * weight[j] * d / (nsamp * R.Lx);
+    part += weight[j] * d * d;
+  }
+  sh[threadIdx.x] = part;
+  for (int h = 128; h >= 1; h >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+  }
+  if (threadIdx.x == 0) *J = sh[0];
+}
+
+// Pressure term of a sample step (reading R11): with lam(r) = lam_j of the
+// node's row, the density adjoints adjA(r') = sum_r lam(r) dP(r)/drho^A(r')
+// and adjB likewise, where P(r) = rho/3 + (G/4) sum_l w_l |c_l|^2 [rho^A(r)
+// rho^B(r + c_l) + rho^B(r) rho^A(r + c_l)] and the neighbour r + c_l of a
+// wall row beyond the wall is the wall row at x + c_lx.  A node r' is that
+// neighbour of r = r' - c_l when that row lies in the fluid, and of
+// r = (x' - c_lx, j') when r' is on a wall row and c_l points out of it.
+// Also the explicit G-derivative sum_r lam(r) d(P - P_ref)(r)/dG, as one
+// partial per block (components tau_s and tau_d zero).
+__global__ void k_adj_psample(const RepInfo* rep, const double* dens, const double* lam,
+                              double* adjfield, double* tpart) {
+  __shared__ double sh[4];
+  const RepInfo& R = *rep;
+  const int Lx = R.Lx, Lz = R.Lz, N = Lx * Lz;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double gpart = 0;
+  if (n < N) {
+    const int j = n / Lx, x = n - j * Lx;
+    auto rho = [&](int s, int xx, int jj) {
+      xx = xx < 0 ? xx + Lx : (xx >= Lx ? xx - Lx : xx);
+      jj = jj < 0 ? 0 : (jj > Lz - 1 ? Lz - 1 : jj);
+      return dens[(size_t)s * N + (size_t)jj * Lx + xx];
+    };
+    const double G = R.G, q = 0.25 * G;
+    double sA = 0, sB = 0;
+    for (int l = 1; l < 9; ++l) {
+      const double c2w = kWa[l] * (double)(kCXa[l] * kCXa[l] + kCZa[l] * kCZa[l]);
+      sA += c2w * rho(0, x + kCXa[l], j + kCZa[l]);
+      sB += c2w * rho(1, x + kCXa[l], j + kCZa[l]);
+    }
+    const double lam0 = lam[j];
+    double gA = lam0 * (1.0 / 3.0 + q * sB);
+    double gB = lam0 * (1.0 / 3.0 + q * sA);
+    for (int l = 1; l < 9; ++l) {
+      const double c2w = kWa[l] * (double)(kCXa[l] * kCXa[l] + kCZa[l] * kCZa[l]);
+      const int js = j - kCZa[l];
+      if (js >= 0 && js < Lz) {
+        const double v = q * c2w * lam[js];
+        gA += v * rho(1, x - kCXa[l], js);
+        gB += v * rho(0, x - kCXa[l], js);
+      }
+      if (j + kCZa[l] < 0 || j + kCZa[l] >= Lz) {
+        const double v = q * c2w * lam0;
+        gA += v * rho(1, x - kCXa[l], j);
+        gB += v * rho(0, x - kCXa[l], j);
+      }
+    }
+    adjfield[n] = gA;
+    adjfield[(size_t)N + n] = gB;
+    const double rA = rho(0, x, j), rB = rho(1, x, j);
+    gpart = lam0 * (0.25 * (rA * sB + rB * sA) - R.rho0 * R.rho0 / 12.0);
+  }
+  const double b = block_sum(gpart, sh);
+  if (threadIdx.x == 0) {
+    tpart[3 * blockIdx.x + 0] = 0.0;
+    tpart[3 * blockIdx.x + 1] = 0.0;
+    tpart[3 * blockIdx.x + 2] = b;
+  }
+}
+
 __global__ void k_sum(const double* parts, int n, double* out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double s = 0;
@@ -669,6 +755,26 @@ hipError_t launch_adj_step(const RepInfo* d_rep, const RepInfo& h_rep, const dou
   const dim3 g = node_grid(N);
   hipLaunchKernelGGL(k_adj_local, g, dim3(kNodeBlock), 0, s, a);
   hipLaunchKernelGGL(k_adj_gather, g, dim3(kNodeBlock), 0, s, a);
+  hipLaunchKernelGGL(k_adj_theta, dim3(1), dim3(256), 0, s, (const double*)tpart, (int)g.x,
+                     theta_acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_pmisfit(const RepInfo* d_rep, const RepInfo& h_rep, const double* acc,
+                              const double* target, const double* weight, double nsamp,
+                              double* lam, double* J, hipStream_t s) {
+  (void)h_rep;
+  hipLaunchKernelGGL(k_adj_pmisfit, dim3(1), dim3(256), 0, s, d_rep, acc, target, weight, nsamp,
+                     lam, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_psample(const RepInfo* d_rep, const RepInfo& h_rep, const double* dens,
+                              const double* lam, double* adjfield, double* tpart,
+                              double* theta_acc, hipStream_t s) {
+  const int N = h_rep.Lx * h_rep.Lz;
+  const dim3 g = node_grid(N);
+  hipLaunchKernelGGL(k_adj_psample, g, dim3(kNodeBlock), 0, s, d_rep, dens, lam, adjfield, tpart);
   hipLaunchKernelGGL(k_adj_theta, dim3(1), dim3(256), 0, s, (const double*)tpart, (int)g.x,
                      theta_acc);
   return hipGetLastError();

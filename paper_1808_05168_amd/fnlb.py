@@ -47,7 +47,7 @@ EXPORTS = ["fnlb_bytes_required", "fnlb_init", "fnlb_step", "fnlb_autotune",
            "fnlb_read_pressure", "fnlb_read_populations", "fnlb_write_populations",
            "fnlb_reset_accumulators", "fnlb_get_time", "fnlb_set_time", "fnlb_destroy",
            "fnlb_strerror", "fnlb_adjoint_bytes_required", "fnlb_sq_misfit_gradient",
-           "fnlb_checkpoint_bytes", "fnlb_save", "fnlb_load"]
+           "fnlb_checkpoint_bytes", "fnlb_save", "fnlb_load", "fnlb_pressure_misfit_gradient"]
 
 
 def load(path: str = LIB_PATH):
@@ -80,6 +80,8 @@ def load(path: str = LIB_PATH):
     lib.fnlb_adjoint_bytes_required.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, szp]
     lib.fnlb_sq_misfit_gradient.argtypes = [vp, ctypes.c_int32, dp, dp, ctypes.c_int64,
                                             ctypes.c_int32, vp, ctypes.c_size_t, dp, dp]
+    lib.fnlb_pressure_misfit_gradient.argtypes = [vp, dp, dp, ctypes.c_int64, ctypes.c_int32,
+                                                  vp, ctypes.c_size_t, dp, dp]
     lib.fnlb_checkpoint_bytes.argtypes = [vp, szp]
     lib.fnlb_save.argtypes = [vp, vp, ctypes.c_size_t]
     lib.fnlb_load.argtypes = [vp, vp, ctypes.c_size_t]
@@ -201,6 +203,30 @@ class Lattice:
         del ws
         return J.value, g
 
+    def pressure_misfit_gradient(self, P_target: np.ndarray, weight: np.ndarray, horizon: int,
+                                 ckpt_every: int = 100):
+        """(J, dJ/d(tau_s, tau_d, G)) of J = sum_j w_j (Pbar_j - P*_j)^2 over
+        `horizon` steps from the current state (Pbar_j: time-averaged row means
+        of P - P_ref), by the adjoint of the step."""
+        import torch
+        r = self.reps[0]
+        Pt = np.ascontiguousarray(P_target, dtype=np.float64).reshape(r.Lz)
+        w = np.ascontiguousarray(weight, dtype=np.float64).reshape(r.Lz)
+        nb = ctypes.c_size_t()
+        _check(self._lib.fnlb_adjoint_bytes_required(self._h, int(horizon), int(ckpt_every),
+                                                     ctypes.byref(nb)),
+               "fnlb_adjoint_bytes_required")
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        J = ctypes.c_double()
+        g = np.zeros(3)
+        _check(self._lib.fnlb_pressure_misfit_gradient(self._h, _dp(Pt), _dp(w), int(horizon),
+                                                       int(ckpt_every),
+                                                       ctypes.c_void_p(ws.data_ptr()), nb.value,
+                                                       ctypes.byref(J), _dp(g)),
+               "fnlb_pressure_misfit_gradient")
+        del ws
+        return J.value, g
+
     def accumulate_structure_factor(self) -> None:
         _check(self._lib.fnlb_accumulate_structure_factor(self._h),
                "fnlb_accumulate_structure_factor")
@@ -278,7 +304,16 @@ def sq_misfit(theta, rep, S_target, weight, horizon: int, sample_every: int,
     Forward runs the step from the rest state on the imposed profile; backward
     returns the adjoint gradient (noise held fixed)."""
     return _SqMisfit.apply(theta, rep, S_target, weight, horizon, sample_every, ckpt_every,
-                           field, device)
+                           field, device, "sq")
+
+
+def p_misfit(theta, rep, P_target, weight, horizon: int, sample_every: int,
+             ckpt_every: int = 100, device: str = "cuda:0"):
+    """Differentiable pressure-profile misfit: theta = tensor([tau_s, tau_d, G]).
+    Forward runs the step from the rest state on the imposed profile; backward
+    returns the adjoint gradient (noise held fixed)."""
+    return _SqMisfit.apply(theta, rep, P_target, weight, horizon, sample_every, ckpt_every,
+                           FIELD_C, device, "p")
 
 
 def _make_fn():
@@ -288,12 +323,15 @@ def _make_fn():
 
     class SqMisfit(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, theta, rep, S_target, weight, horizon, sample_every, ckpt_every,
-                    field, device):
+        def forward(ctx, theta, rep, target, weight, horizon, sample_every, ckpt_every,
+                    field, device, kind):
             t = [float(v) for v in theta.detach().cpu().tolist()]
             r = dataclasses.replace(rep, tau_s=t[0], tau_d=t[1], G=t[2])
             lat = Lattice([r], precision=FP64, sample_every=sample_every, device=device)
-            J, g = lat.sq_misfit_gradient(S_target, weight, horizon, ckpt_every, field)
+            if kind == "p":
+                J, g = lat.pressure_misfit_gradient(target, weight, horizon, ckpt_every)
+            else:
+                J, g = lat.sq_misfit_gradient(target, weight, horizon, ckpt_every, field)
             lat.close()
             ctx.save_for_backward(torch.as_tensor(g, dtype=theta.dtype))
             return theta.new_tensor(J)
@@ -301,7 +339,8 @@ def _make_fn():
         @staticmethod
         def backward(ctx, gJ):
             (g,) = ctx.saved_tensors
-            return (gJ.cpu() * g).to(gJ.device), None, None, None, None, None, None, None, None
+            return ((gJ.cpu() * g).to(gJ.device), None, None, None, None, None, None, None, None,
+                    None)
 
     return SqMisfit
 

@@ -116,3 +116,68 @@ def test_adjoint_256x128_horizon_2000(F):
     cs = np.array([O.sq_misfit_complex_step(rep, H, every, 0, S_t, w, k) for k in range(3)])
     say(f"  complex-step {cs}")
     np.testing.assert_allclose(g, cs, rtol=1e-7)
+
+
+# ------------------------------------------------- pressure-profile misfit
+
+def p_target(rep, horizon, every):
+    """Target row profile of P - P_ref from a twin run at (tau_s, tau_d, G) x
+    (1.05, 0.95, 1.1); row weights 0.5 .. 1.5."""
+    twin = dataclasses.replace(rep, tau_s=rep.tau_s * 1.05, tau_d=rep.tau_d * 0.95, G=rep.G * 1.1)
+    f = O.init_state(twin)
+    acc = O.Accum(twin.Lx, twin.Lz)
+    O.run(twin, f, 0, horizon, acc, sample_every=every)
+    return acc.prof / acc.n_samples, np.linspace(0.5, 1.5, rep.Lz)
+
+
+def test_pressure_adjoint_matches_complex_step_small(F):
+    rep, H, every = SMALL, 120, 10
+    say(f"case: pressure adjoint 32x16 horizon {H}")
+    P_t, w = p_target(rep, H, every)
+    lat = F.Lattice([rep], precision=F.FP64, sample_every=every)
+    J, g = lat.pressure_misfit_gradient(P_t, w, H, ckpt_every=25)
+    J_o = O.p_misfit(rep, H, every, P_t, w)
+    assert abs(J - J_o) <= 1e-10 * abs(J_o)
+    cs = np.array([O.p_misfit_complex_step(rep, H, every, P_t, w, k) for k in range(3)])
+    say(f"  adjoint {g}  complex-step {cs}")
+    np.testing.assert_allclose(g, cs, rtol=1e-7, atol=1e-9 * np.abs(cs).max())
+
+
+def test_pressure_adjoint_256x128_horizon_2000(F):
+    """256 x 128 over 2000 steps sampled every 10, checkpoints every 100:
+    the pressure-profile gradient against central differences of the GPU
+    forward (h = 1e-6 relative) and the oracle's complex-step derivative."""
+    rep, H, every = W.adjoint_256x128(), 2000, 10
+    say("case: pressure adjoint 256x128 horizon 2000")
+    P_t, w = p_target(rep, H, every)
+    lat = F.Lattice([rep], precision=F.FP64, sample_every=every)
+    J, g = lat.pressure_misfit_gradient(P_t, w, H, ckpt_every=100)
+    fd = []
+    for name in ("tau_s", "tau_d", "G"):
+        v = getattr(rep, name)
+        h = 1e-6 * v
+        Js = []
+        for sgn in (1, -1):
+            r = dataclasses.replace(rep, **{name: v + sgn * h})
+            lt = F.Lattice([r], precision=F.FP64, sample_every=every)
+            Js.append(lt.pressure_misfit_gradient(P_t, w, H, ckpt_every=100)[0])
+        fd.append((Js[0] - Js[1]) / (2 * h))
+    fd = np.array(fd)
+    say(f"  adjoint {g}  central differences {fd}")
+    np.testing.assert_allclose(g, fd, rtol=1e-5)
+    cs = np.array([O.p_misfit_complex_step(rep, H, every, P_t, w, k) for k in range(3)])
+    say(f"  complex-step {cs}")
+    np.testing.assert_allclose(g, cs, rtol=1e-7)
+
+
+def test_pressure_autograd_function(F):
+    import torch
+    rep, H, every = SMALL, 60, 10
+    P_t, w = p_target(rep, H, every)
+    theta = torch.tensor([rep.tau_s, rep.tau_d, rep.G], dtype=torch.float64, requires_grad=True)
+    J = F.p_misfit(theta, rep, P_t, w, H, every, ckpt_every=20)
+    J.backward()
+    lat = F.Lattice([rep], precision=F.FP64, sample_every=every)
+    J2, g = lat.pressure_misfit_gradient(P_t, w, H, ckpt_every=20)
+    assert float(J.detach()) == J2
+    np.testing.assert_array_equal(theta.grad.numpy(), g)
