@@ -83,7 +83,11 @@ void make_items(Plan& P, int chunk) {
     const int nseg = (R.Lx + kSeg - 1) / kSeg;
     for (int j0 = 0; j0 < R.Lz; j0 += chunk)
       for (int s = 0; s < nseg; ++s)
-        P.items.push_back(Item{(int32_t)r, s, j0, std::min(R.Lz, j0 + chunk)});
+        // every other row range marches downwards, so that neighbouring ranges
+        // read their shared boundary rows at the same time (one of the two
+        // reads then hits L2)
+        P.items.push_back(Item{(int32_t)r, s, j0, std::min(R.Lz, j0 + chunk),
+                               ((j0 / chunk) & 1) ? -1 : 1});
   }
 }
 

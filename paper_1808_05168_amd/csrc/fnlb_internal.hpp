@@ -58,7 +58,8 @@ struct alignas(256) RepInfo {
 
 // One block's work: replica, 256-column segment and a range of rows.
 struct Item {
-  int32_t rep, strip, j0, j1;  // strip = segment index
+  int32_t rep, strip, j0, j1;  // strip = segment index; rows j0 .. j1 - 1
+  int32_t dir;                 // marching direction along z: +1 up, -1 down
 };
 
 // A row of one replica (row transform of the structure factor).

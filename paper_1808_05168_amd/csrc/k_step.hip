@@ -215,7 +215,14 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   const Real shA1 = (Real)(-rAs / 9.0), shA5 = (Real)(-rAs / 36.0);
 
   const int j0 = it.j0, j1 = it.j1;
-  const int jlast = min(j1, Lz - 1);  // last row whose densities the item needs
+  // Rows whose densities the item needs: its own and one more on each side
+  // inside the walls.  The item marches from jfirst in direction dir (items
+  // alternate, so that two sharing a boundary read its rows at the same time);
+  // "ahead" is the next row in that direction.
+  const int dir = it.dir;
+  const int lo = max(j0 - 1, 0), hi = min(j1, Lz - 1);
+  const int jfirst = dir > 0 ? j0 : j1 - 1;
+  auto needed = [&](int jr) { return jr >= lo && jr <= hi; };
   auto stage = [&](int jr, const Store(&o)[18]) {
     if constexpr (kStage) {
 #pragma unroll
@@ -223,17 +230,19 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     }
   };
   Store cur[18], nxt[18];
-  load_pulled(in, link_b, row_b, j0, Lz, xb, xmb, xpb, cur);
-  put_row(j0, cur);
-  stage(j0, cur);
-  if (j0 > 0) {
+  load_pulled(in, link_b, row_b, jfirst, Lz, xb, xmb, xpb, cur);
+  put_row(jfirst, cur);
+  stage(jfirst, cur);
+  if (needed(jfirst - dir)) {  // the row behind the first one
     Store tmp[18];
-    load_pulled(in, link_b, row_b, j0 - 1, Lz, xb, xmb, xpb, tmp);
-    put_row(j0 - 1, tmp);
+    load_pulled(in, link_b, row_b, jfirst - dir, Lz, xb, xmb, xpb, tmp);
+    put_row(jfirst - dir, tmp);
   }
   if (!whole_row && (tid == 0 || tid == width - 1)) {
     const int col = tid == 0 ? hl : hr, rc = tid == 0 ? 0 : width + 1;
-    for (int jr = max(j0 - 1, 0); jr <= j0; ++jr) {
+    for (int k = 0; k < 2; ++k) {
+      const int jr = k == 0 ? jfirst - dir : jfirst;
+      if (!needed(jr)) continue;
       Store o[18];
       edge_pull<Store>(in, link_b, row_b, jr, Lz, Lx, col, o);
       put_col(jr, rc, o);
@@ -243,18 +252,21 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   Store ev = (Store)0;
   if constexpr (kStage) {
     // the first row ahead is in flight before the loop
-    if (j0 + 1 <= jlast) {
-      load_pulled(in, link_b, row_b, j0 + 1, Lz, xb, xmb, xpb, nxt);
-      ev = pull_edges(j0 + 1);
+    if (needed(jfirst + dir)) {
+      load_pulled(in, link_b, row_b, jfirst + dir, Lz, xb, xmb, xpb, nxt);
+      ev = pull_edges(jfirst + dir);
     }
   }
 
-  for (int j = j0; j < j1; ++j) {
+  for (int i = 0; i < j1 - j0; ++i) {
+    const int j = jfirst + dir * i;
     const bool top = (j == Lz - 1), bot = (j == 0);
+    const int ja = j + dir;  // the row ahead
+    const bool ahead = needed(ja);
     if constexpr (!kStage) {
-      if (!top) {
-        load_pulled(in, link_b, row_b, j + 1, Lz, xb, xmb, xpb, nxt);
-        ev = pull_edges(j + 1);
+      if (ahead) {
+        load_pulled(in, link_b, row_b, ja, Lz, xb, xmb, xpb, nxt);
+        ev = pull_edges(ja);
       }
     }
 
@@ -272,20 +284,20 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
       }
     }
 
-    if (!top) {
-      put_row(j + 1, nxt);
-      put_edges(j + 1, ev);
-      stage(j + 1, nxt);
+    if (ahead) {
+      put_row(ja, nxt);
+      put_edges(ja, ev);
+      stage(ja, nxt);
     }
     if constexpr (kStage) {
       // the row after next: its loads run through the barrier and the collision
-      if (j + 2 <= jlast) {
-        load_pulled(in, link_b, row_b, j + 2, Lz, xb, xmb, xpb, nxt);
-        ev = pull_edges(j + 2);
+      if (needed(ja + dir)) {
+        load_pulled(in, link_b, row_b, ja + dir, Lz, xb, xmb, xpb, nxt);
+        ev = pull_edges(ja + dir);
       }
     }
     __syncthreads();
-    if (!top) sum_edges(j + 1);
+    if (ahead) sum_edges(ja);
     if constexpr (kStage) {
 #pragma unroll
       for (int q = 0; q < 18; ++q) cur[q] = pbuf[j & 1][q][tid];
