@@ -23,13 +23,15 @@
 // is all zeros.
 //
 // Mapping.  A block of four wavefronts owns a 256-column segment of one row
-// range and marches up the rows.  Every lane pulls its node's 18 populations
-// of the next row, sums its densities into a four-row ring in LDS (plus the
+// range and marches through its rows, upwards or downwards (neighbouring row
+// ranges alternate, so that the halo rows they share are read at the same
+// time and served once from HBM).  Every lane pulls its node's 18 populations
+// of the row ahead, sums its densities into a four-row ring in LDS (plus the
 // two segment-edge columns, pulled by 36 lanes of the first wavefront with one
 // load, or wrapped when the segment is a whole periodic row), and after one
 // barrier per row reads the eight neighbour densities of the non-local force
-// from LDS.  Stores are the node's own 18 post-collision values: full,
-// aligned cache lines.
+// from LDS.  Stores are the node's own 18 post-collision values; in the tiled
+// layout each link of a wavefront's row is one contiguous 256-byte run.
 #include "fnlb.h"
 #include "fnlb_device.hpp"
 #include "fnlb_internal.hpp"

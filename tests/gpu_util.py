@@ -36,11 +36,6 @@ def dev_norm(f_gpu, f_ora, rep):
     return np.abs(d_g - d_o).max() / scale if scale > 0 else np.abs(d_g - d_o).max()
 
 
-def sq_norm(S_gpu, S_ora):
-    """max_q |S_gpu - S_ora| / mean_q S_ora."""
-    return np.abs(S_gpu - S_ora).max() / np.abs(S_ora).mean()
-
-
 def sq_from_sums(a2, re, im, n):
     n = max(n, 1)
     return a2 / n - ((re / n) ** 2 + (im / n) ** 2)
