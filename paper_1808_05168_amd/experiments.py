@@ -87,13 +87,14 @@ class SpectrumRun:
     phi_measured: float        # Eq. (37) with the measured bulk gradient
     grad_measured: float       # slope of the mean concentration profile (bulk rows)
     S_c_wall_normal: np.ndarray  # S_c(0, q) / S_eq for k_z = 1..Lz/2
+    C_x: np.ndarray            # real-space correlation <dc(x) dc(x + dx)> - S_eq delta, dx = 0..Lx/2
 
 
 def ne_spectrum(L: int = 32, Lx: int = 128, kT: float = 1e-5, grad_c0: float = 0.01,
                 D: float = 0.0043, nu: float = 0.0667, replicas: int = 64,
                 warmup: int = 300000, steps: int = 400000, sample_every: int = 50,
                 precision: int = _f.FP32_DEV, seed0: int = 100, edge_rows: int = 4,
-                device: str = "cuda:0") -> SpectrumRun:
+                noise_loc: bool = False, device: str = "cuda:0") -> SpectrumRun:
     """Non-equilibrium concentration spectrum of Sec. IV.B.
 
     `replicas` independent lattices (seeds seed0, seed0 + 1, ...) with
@@ -101,10 +102,16 @@ def ne_spectrum(L: int = 32, Lx: int = 128, kT: float = 1e-5, grad_c0: float = 0
     steps, then `steps` sampled steps.  The measured gradient is the slope of
     the time-averaged concentration profile over the rows away from the walls
     (`edge_rows` dropped at each side); in two dimensions fluctuations renormalise
-    the diffusivity, so at larger kT it falls below grad c0."""
+    the diffusivity, so at larger kT it falls below grad c0.
+    noise_loc: noise amplitudes from the local densities ("loc") instead of the
+    reference ones ("hom"), the comparison of Sec. IV.B.  C_x: the equal-row
+    correlation of delta c along x minus its equilibrium value (S_eq at dx = 0),
+    the real-space picture of the long-range correlations of Sec. IV.B."""
     reps = [_Run(Lx=Lx, Lz=L, grad_c0=grad_c0, kT=kT, G=0.0, seed=seed0 + i,
                  tau_d=3.0 * D + 0.5, tau_s=3.0 * nu + 0.5) for i in range(replicas)]
-    lat = _f.Lattice(reps, precision=precision, sample_every=sample_every, device=device)
+    flags = _f.DEFAULT_FLAGS | (_f.NOISE_LOC if noise_loc else 0)
+    lat = _f.Lattice(reps, precision=precision, sample_every=sample_every, flags=flags,
+                     device=device)
     lat.step(warmup)
     lat.reset_accumulators()
     lat.step(steps)
@@ -131,7 +138,16 @@ def ne_spectrum(L: int = 32, Lx: int = 128, kT: float = 1e-5, grad_c0: float = 0
                        if replicas > 1 else np.zeros(len(k)),
                        S_eq=S_eq, phi_imposed=phi(grad_c0), phi_measured=phi(g_meas),
                        grad_measured=g_meas,
-                       S_c_wall_normal=S[:, 1:L // 2 + 1, 0].mean(axis=0) / S_eq)
+                       S_c_wall_normal=S[:, 1:L // 2 + 1, 0].mean(axis=0) / S_eq,
+                       C_x=_equal_row_correlation(S.mean(axis=0), Lx, S_eq))
+
+
+def _equal_row_correlation(S_half: np.ndarray, Lx: int, S_eq: float) -> np.ndarray:
+    """<dphi(x, z) dphi(x + dx, z)> averaged over x and z, minus S_eq at dx = 0,
+    for dx = 0..Lx/2 (needs no periodicity in z)."""
+    C = correlation(S_half, Lx)[0, : Lx // 2 + 1].copy()
+    C[0] -= S_eq
+    return C
 
 
 @dataclasses.dataclass
@@ -247,6 +263,8 @@ def _main(argv=None) -> None:
     a.add_argument("--replicas", type=int, default=64)
     a.add_argument("--warmup", type=int, default=300000)
     a.add_argument("--steps", type=int, default=400000)
+    a.add_argument("--noise-loc", action="store_true",
+                   help="noise amplitudes from local densities (\"loc\")")
     b = sub.add_parser("pressure", help="non-equilibrium pressure scans (Sec. IV.C)")
     b.add_argument("--L", type=int, nargs="+", default=[32])
     b.add_argument("--grad", type=float, nargs="+", default=[0.01])
@@ -258,13 +276,16 @@ def _main(argv=None) -> None:
     args = ap.parse_args(argv)
     if args.what == "spectrum":
         r = ne_spectrum(L=args.L, Lx=args.Lx, kT=args.kT, grad_c0=args.grad,
-                        replicas=args.replicas, warmup=args.warmup, steps=args.steps)
+                        replicas=args.replicas, warmup=args.warmup, steps=args.steps,
+                        noise_loc=args.noise_loc)
         print(f"measured bulk gradient {r.grad_measured:.5g} (imposed {args.grad})")
         for i, qt in enumerate(r.q_tilde):
             ne = r.S_c[i] / r.S_eq - 1.0
             print(f"q~ {qt:8.3f}  phi S_NE {ne:11.4e} +- {r.S_c_err[i] / r.S_eq:9.2e}  "
                   f"phi q~^-4 {r.phi_imposed * qt ** -4:11.4e} (imposed) "
                   f"{r.phi_measured * qt ** -4:11.4e} (measured)")
+        print("non-equilibrium correlation <dc(x) dc(x+dx)> - S_eq delta, dx = 0..8:",
+              " ".join(f"{v:.3e}" for v in r.C_x[:9]))
     else:
         r = ne_pressure(args.L, args.grad, kT=args.kT, G=args.G, seeds=args.seeds,
                         warmup=args.warmup, steps=args.steps)

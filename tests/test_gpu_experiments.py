@@ -108,4 +108,7 @@ def test_ne_spectrum_matches_oracle(F):
     c = np.mean(prof, axis=0)
     g_o = np.polyfit(z[2:-2], c[2:-2], 1)[0]
     assert abs(r.grad_measured - g_o) < 1e-12
+    C = X.correlation(S.mean(axis=0), Lx)[0, : Lx // 2 + 1]
+    C[0] -= r.S_eq
+    np.testing.assert_allclose(r.C_x, C, rtol=0, atol=1e-10 * np.abs(C).max())
     assert np.allclose(r.q_tilde, 2 * np.pi * np.arange(1, Lx // 2 + 1) / Lx * L)
