@@ -141,7 +141,6 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
     R.Lx = p.Lx;
     R.Lz = p.Lz;
     R.pitch = (p.Lx + kRowAlign - 1) / kRowAlign * kRowAlign;
-    R.nstrips = (p.Lx + kWave - 1) / kWave;
     R.plane = ((int64_t)p.Lz * R.pitch + elem_align - 1) / elem_align * elem_align;
     R.state_off = state_elems;
     state_elems += 18 * R.plane;
@@ -155,7 +154,7 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
     R.pacc_off = acc_d;
     acc_d += 2 + p.Lz;
     R.ppart_off = ppart_d;
-    ppart_d += (int64_t)R.nstrips * p.Lz;
+    ppart_d += p.Lz;
     R.tw_off = tw_c;
     tw_c += p.Lx + p.Lz;
     R.flags = opt->flags;
@@ -265,8 +264,11 @@ struct fnlb_handle {
   int64_t t_dev = 0;     // value held by the device time base
   int64_t nsamples = 0;
   int error = FNLB_OK;   // sticky error
-  // one sampling period captured as a graph, per parity of the starting copy
-  hipStream_t cap_stream = nullptr;
+  // one sampling period captured as a graph, per parity of the starting copy;
+  // in it the transforms of the sample run on a branch of their own (captured
+  // from obs_stream) beside the plain steps that follow
+  hipStream_t cap_stream = nullptr, obs_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int64_t period = 0;
 
@@ -303,8 +305,6 @@ StepArgs step_args(fnlb_handle* h, int64_t t_off) {
   a.t_base = h->d_time();
   a.t_off = t_off;
   a.fields = h->d_fields();
-  a.ppart = h->d_ppart();
-  a.watchdog = h->d_watchdog();
   return a;
 }
 
@@ -313,7 +313,8 @@ hipError_t observe(fnlb_handle* h, hipStream_t s, double* acc = nullptr) {
   const Plan& P = h->plan;
   if (!acc) acc = (double*)h->accum;
   hipError_t e = launch_row_transform(h->d_reps(), h->d_rows(), (int)P.rows.size(), P.n_pairs,
-                                      P.max_row_lds, h->d_fields(), h->d_spec(), h->d_tw(), s);
+                                      P.max_row_lds, h->d_fields(), h->d_spec(), h->d_tw(),
+                                      h->d_ppart(), h->d_watchdog(), s);
   if (e != hipSuccess) return e;
   e = launch_col_transform(h->d_reps(), h->d_cols(), (int)P.cols.size(), P.max_col_lds,
                            h->d_spec(), acc, h->d_tw(), s);
@@ -333,10 +334,18 @@ void drop_graphs(fnlb_handle* h) {
 // Captures one period of `period` steps starting at a period start, from
 // state copy `parity`: the first step samples when sampling is on, and the
 // last node advances the device time counter by the period.  Kernels read
-// their time as counter + offset, so one graph serves every period.
+// their time as counter + offset, so one graph serves every period.  The
+// transforms of the sample form a branch that forks after the sampling step
+// and joins before the last node: they read only the sample buffer and write
+// only the spectra, pressure sums and accumulators, which no step touches, and
+// the next sample is taken by the next period.
 hipError_t capture_period(fnlb_handle* h, int parity) {
   hipError_t e = hipSuccess;
   if (!h->cap_stream) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess && !h->obs_stream)
+    e = hipStreamCreateWithFlags(&h->obs_stream, hipStreamNonBlocking);
+  if (e == hipSuccess && !h->ev_fork) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess && !h->ev_join) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
   if (e != hipSuccess) return e;
   hipStream_t s = h->cap_stream;
   e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
@@ -345,12 +354,24 @@ hipError_t capture_period(fnlb_handle* h, int parity) {
   const int saved = h->cur;
   h->cur = parity;
   hipError_t le = hipSuccess;
+  bool forked = false;
   for (int64_t k = 0; k < h->period && le == hipSuccess; ++k) {
     const bool smp = sampling && k == 0;
     StepArgs a = step_args(h, k);
     le = launch_step(h->opt.precision, smp ? kStepSample : kStep, a, s);
-    if (le == hipSuccess && smp) le = observe(h, s);
+    if (le == hipSuccess && smp) {
+      le = hipEventRecord(h->ev_fork, s);
+      if (le == hipSuccess) le = hipStreamWaitEvent(h->obs_stream, h->ev_fork, 0);
+      if (le == hipSuccess) forked = true;
+      if (le == hipSuccess) le = observe(h, h->obs_stream);
+      if (le == hipSuccess) le = hipEventRecord(h->ev_join, h->obs_stream);
+    }
     h->cur ^= 1;
+  }
+  // the branch always joins, so that the capture can end
+  if (forked) {
+    const hipError_t je = hipStreamWaitEvent(s, h->ev_join, 0);
+    if (le == hipSuccess) le = je;
   }
   if (le == hipSuccess) le = launch_advance_time(h->d_time(), h->period, s);
   h->cur = saved;
@@ -984,6 +1005,9 @@ int fnlb_destroy(fnlb_handle* h) {
   if (!h) return FNLB_OK;
   drop_graphs(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->obs_stream) (void)hipStreamDestroy(h->obs_stream);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   delete h;
   return FNLB_OK;
 }

@@ -13,8 +13,7 @@
 namespace fnlb {
 
 // A block of four wavefronts updates a segment of 256 consecutive columns of
-// one row range; pressure partials are kept per 64-column strip (one per
-// wavefront).  Rows are padded to 64 elements so every segment starts on a
+// one row range.  Rows are padded to 64 elements so every segment starts on a
 // cache-line boundary.
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
@@ -22,7 +21,9 @@ constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kSeg = kBlock;
 constexpr int kRowAlign = 64;
 
-// sampled real fields: delta c, delta rho, and U_x, U_z on request
+// sampled real fields: delta c, delta rho, and U_x, U_z on request (the step
+// leaves as many per-node inputs: the two density deviations, and the two
+// momenta)
 inline int n_fields(int flags) { return (flags & FNLB_SAMPLE_VELOCITY) ? 4 : 2; }
 
 // Everything a kernel needs about one replica.  Filled on the host, copied to
@@ -30,14 +31,13 @@ inline int n_fields(int flags) { return (flags & FNLB_SAMPLE_VELOCITY) ? 4 : 2; 
 struct alignas(256) RepInfo {
   int32_t Lx, Lz;         // lattice size
   int32_t pitch;          // row length rounded up to whole 64-column tiles (>= Lx)
-  int32_t nstrips;        // ceil(Lx / 64): pressure partials per row
   int64_t plane;          // elements per (species, link) plane
   int64_t state_off;      // element offset of this replica in one state copy
-  int64_t field_off;      // double offset of the sample fields [2][Lz][Lx]
+  int64_t field_off;      // double offset of the sample inputs [2 or 4][Lz][Lx]
   int64_t spec_off;       // double2 offset of the row spectra [2][Lz][Lx/2+1]
   int64_t acc_off;        // double offset of [2][3][Lz][Lx/2+1] sums
   int64_t pacc_off;       // double offset of {sum, sum2, profile[Lz]}
-  int64_t ppart_off;      // double offset of pressure partials [nstrips][Lz]
+  int64_t ppart_off;      // double offset of the pressure row sums [Lz]
   int64_t tw_off;         // double2 offset of twiddles: Lx entries then Lz
   int32_t flags;          // FNLB_* option bits
   int32_t pow2;           // both Lx and Lz are powers of two (FFT path)
@@ -84,9 +84,7 @@ struct StepArgs {
   void* state_out;        // next state copy
   const int64_t* t_base;  // device time counter (graph replays advance it)
   int64_t t_off;          // time = *t_base + t_off
-  double* fields;         // sample fields base (double)
-  double* ppart;          // pressure partials base
-  int32_t* watchdog;      // set non-zero when a sample sees a bad state
+  double* fields;         // sample inputs base (double)
 };
 
 // Launchers (asynchronous on `stream`).
@@ -94,9 +92,11 @@ hipError_t launch_step(int precision, int mode, const StepArgs& a, hipStream_t s
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t stream);
 hipError_t launch_twiddles(const RepInfo* d_reps, const RepInfo* h_reps, int n_rep,
                            double2* tw_base, hipStream_t stream);
+// watchdog: set non-zero when a sample sees a bad state
 hipError_t launch_row_transform(const RepInfo* reps, const RowRef* rows, int n_rows,
                                 int n_pairs, int max_row_lds, const double* fields, double2* spec,
-                                const double2* tw, hipStream_t stream);
+                                const double2* tw, double* ppart, int32_t* watchdog,
+                                hipStream_t stream);
 hipError_t launch_col_transform(const RepInfo* reps, const ColRef* cols, int n_cols,
                                 int max_lds_cols, const double2* spec, double* acc,
                                 const double2* tw, hipStream_t stream);

@@ -48,41 +48,122 @@ __global__ void k_twiddles(const RepInfo* reps, double2* tw_base) {
 // that their latencies overlap.
 constexpr int kBatch = 8;
 
-// Row pass: one block per group of consecutive rows of one replica (several
-// short rows share a block) and field pair (blockIdx.y).  LDS: the rows, then
-// (power-of-two rows) the N/2 twiddles the FFT uses.
-__global__ void k_row_transform(const RepInfo* reps, const RowRef* rows, const double* fields,
-                                double2* spec, const double2* tw_base) {
+// Row pass of a sample: one block per group of consecutive rows of one
+// replica (several short rows share a block) and field pair (blockIdx.y).
+// The step kernel leaves, per node, the FP64 deviations of the two species
+// densities from the row references (and, with velocity sampling, the FP64
+// total momenta).  This pass forms the sampled fields from them: pair 0 is
+// delta c + i delta rho, together with the pressure of every node (reading
+// R11: P = rho/3 + (G/4) sum_l w_l |c_l|^2 [rho^A rho^B(r + c_l) + rho^B
+// rho^A(r + c_l)], ghost rows repeating the wall row) summed per row in a
+// fixed order, and the check of the state; pair 1 is U_x + i U_z, the
+// barycentric velocity of Eq. (10) after the wall fix.  Neighbour densities
+// are read from global memory (L2) with 32-bit offsets shared by both species.
+// Each row is then transformed and split into the two half spectra.  LDS: the
+// rows, then (power-of-two rows) the N/2 twiddles the FFT uses.
+__global__ __launch_bounds__(256) void k_row_transform(const RepInfo* reps, const RowRef* rows,
+                                                       const double* fields, double2* spec,
+                                                       const double2* tw_base, double* ppart,
+                                                       int32_t* watchdog) {
   extern __shared__ double2 lds[];
+  __shared__ double red[256];
   const RowRef rr = rows[blockIdx.x];
   const RepInfo& R = reps[rr.rep];
   const int N = R.Lx, Lz = R.Lz, nkx = N / 2 + 1, nr = rr.nrows;
-  const size_t row0 = (size_t)(2 * blockIdx.y) * Lz + rr.j0;  // first field of the pair
-  const double* fc = fields + R.field_off + row0 * N;
-  const double* fr = fc + (size_t)Lz * N;
+  const int pair = blockIdx.y;
+  const size_t plane = (size_t)Lz * N;
+  const double* dA = fields + R.field_off;  // density deviations [Lz][Lx]
+  const double* dB = dA + plane;
+  const double* mX = dB + plane;  // total momenta (velocity sampling)
+  const double* mZ = mX + plane;
   const double2* tw = tw_base + R.tw_off;
-  double2* out_c = spec + R.spec_off + row0 * nkx;
+  const size_t orow = (size_t)(2 * pair) * Lz + rr.j0;  // first field of the pair
+  double2* out_c = spec + R.spec_off + orow * nkx;
   double2* out_r = out_c + (size_t)Lz * nkx;
   const int total = nr * N;
   const int bits = R.pow2 ? __ffs(N) - 1 : 0;
-  for (int base = threadIdx.x; base < total; base += kBatch * blockDim.x) {
-    double vc[kBatch], vr[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int q = base + u * blockDim.x;
-      if (q < total) {
-        vc[u] = fc[q];
-        vr[u] = fr[q];
+  // the block's threads split into one group per row
+  const int gsz = blockDim.x / nr;
+  const int r = threadIdx.x / gsz, t2 = threadIdx.x - r * gsz;
+  const bool live = r < nr;
+  const int j = rr.j0 + (live ? r : 0);
+  const int jU = min(j + 1, Lz - 1), jD = max(j - 1, 0);
+  const double rho0 = R.rho0, G = R.G;
+  const double rAj = R.rA_mid + R.rA_step * j, rBj = rho0 - rAj;
+  const double rAu = R.rA_mid + R.rA_step * jU, rAd = R.rA_mid + R.rA_step * jD;
+  const double rBu = rho0 - rAu, rBd = rho0 - rAd;
+  const double szref = R.rA_step * (double)(jU - jD) * (1.0 / 6.0);  // species A
+  // reference parts of the weighted neighbour sums s^S of the pressure
+  const double sAref = (1.0 / 9.0) * (2.0 * rAj + rAu + rAd) + (1.0 / 9.0) * (rAu + rAd);
+  const double sBref = (1.0 / 9.0) * (2.0 * rBj + rBu + rBd) + (1.0 / 9.0) * (rBu + rBd);
+  const double c0 = rAj / rho0, dPref = R.p_ref - rho0 / 3.0;
+  const bool wall = (R.flags & FNLB_WALL_UZ_FIX) && (j == 0 || j == Lz - 1);
+  // byte offsets of the three rows (Lx, Lz <= 4096, so 8 Lx Lz < 2^32: the
+  // planes are read through 32-bit offsets from a uniform base)
+  const uint32_t oC = (uint32_t)j * N * 8u, oU = (uint32_t)jU * N * 8u, oD = (uint32_t)jD * N * 8u;
+  auto ld = [](const double* base, uint32_t off) {
+    return *(const double*)((const char*)base + off);
+  };
+  double psum = 0.0;
+  bool bad = false;
+  if (live) {
+    for (int x = t2; x < N; x += gsz) {
+      const uint32_t x8 = 8u * x, xm8 = x == 0 ? 8u * (N - 1) : x8 - 8u,
+                     xp8 = x == N - 1 ? 0u : x8 + 8u;
+      const uint32_t c = oC + x8, cW = oC + xm8, cE = oC + xp8;
+      const uint32_t u = oU + x8, uW = oU + xm8, uE = oU + xp8;
+      const uint32_t d = oD + x8, dW = oD + xm8, dE = oD + xp8;
+      const double aC = ld(dA, c), aW = ld(dA, cW), aE = ld(dA, cE), aU = ld(dA, u),
+                   aUW = ld(dA, uW), aUE = ld(dA, uE), aD = ld(dA, d), aDW = ld(dA, dW),
+                   aDE = ld(dA, dE);
+      const double bC = ld(dB, c), bW = ld(dB, cW), bE = ld(dB, cE), bU = ld(dB, u),
+                   bUW = ld(dB, uW), bUE = ld(dB, uE), bD = ld(dB, d), bDW = ld(dB, dW),
+                   bDE = ld(dB, dE);
+      const double rhoA = rAj + aC, rhoB = rBj + bC;
+      const double rho = rhoA + rhoB;
+      double2 v;
+      if (pair == 0) {
+        const double drho = aC + bC;
+        const double dc = (aC - c0 * drho) / rho;
+        const double sA = sAref + (1.0 / 9.0) * ((aE + aW) + (aU + aD)) +
+                          (1.0 / 18.0) * ((aUE + aUW) + (aDE + aDW));
+        const double sB = sBref + (1.0 / 9.0) * ((bE + bW) + (bU + bD)) +
+                          (1.0 / 18.0) * ((bUE + bUW) + (bDE + bDW));
+        const double dP = drho * (1.0 / 3.0) + G * 0.25 * (rhoA * sB + rhoB * sA) - dPref;
+        psum += dP;
+        bad = bad || !(rhoA > 0.0) || !(rhoB > 0.0) || !(dc + c0 > 0.0) || !(dc + c0 < 1.0) ||
+              !isfinite(dP);
+        v = make_double2(dc, drho);
+      } else {
+        // total force -G (rho^A s^B + rho^B s^A) with s^S = sum_l w_l c_l rho^S(r + c_l)
+        // (the a_* and non-equilibrium parts cancel between the species)
+        const double vAx = (1.0 / 9.0) * (aE - aW) + (1.0 / 36.0) * ((aUE - aUW) + (aDE - aDW));
+        const double vBx = (1.0 / 9.0) * (bE - bW) + (1.0 / 36.0) * ((bUE - bUW) + (bDE - bDW));
+        const double vAz =
+            (1.0 / 9.0) * (aU - aD) + (1.0 / 36.0) * ((aUE + aUW) - (aDE + aDW)) + szref;
+        const double vBz =
+            (1.0 / 9.0) * (bU - bD) + (1.0 / 36.0) * ((bUE + bUW) - (bDE + bDW)) - szref;
+        const double Fx = -G * (rhoA * vBx + rhoB * vAx);
+        const double Fz = -G * (rhoA * vBz + rhoB * vAz);
+        v = make_double2((ld(mX, c) + 0.5 * Fx) / rho, wall ? 0.0 : (ld(mZ, c) + 0.5 * Fz) / rho);
       }
+      lds[(size_t)r * N + (R.pow2 ? bitrev(x, bits) : x)] = v;
     }
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int q = base + u * blockDim.x;
-      if (q < total) {
-        const int d = R.pow2 ? ((q >> bits) << bits) + bitrev(q & (N - 1), bits) : q;
-        lds[d] = make_double2(vc[u], vr[u]);
-      }
+  }
+  if (pair == 0) {
+    // row sums of P - P_ref: strided partials, then a fixed-shape tree per row
+    red[threadIdx.x] = psum;
+    int P2 = 1;
+    while (P2 * 2 <= gsz) P2 *= 2;
+    __syncthreads();
+    if (live && t2 + P2 < gsz) red[threadIdx.x] += red[threadIdx.x + P2];
+    for (int h = P2 >> 1; h >= 1; h >>= 1) {
+      __syncthreads();
+      if (live && t2 < h) red[threadIdx.x] += red[threadIdx.x + h];
     }
+    __syncthreads();
+    if (live && t2 == 0) ppart[R.ppart_off + j] = red[threadIdx.x];
+    if (bad) atomicOr(watchdog, 1);
   }
   if (R.pow2) {
     double2* tws = lds + total;
@@ -91,12 +172,9 @@ __global__ void k_row_transform(const RepInfo* reps, const RowRef* rows, const d
   } else {
     __syncthreads();
   }
-  // the block's threads split into one group per row
-  const int gsz = blockDim.x / nr;
-  const int r = threadIdx.x / gsz;
-  if (r >= nr) return;
+  if (!live) return;
   const double2* row = lds + (size_t)r * N;
-  for (int k = threadIdx.x - r * gsz; k < nkx; k += gsz) {
+  for (int k = t2; k < nkx; k += gsz) {
     double2 Z, Zm;
     if (R.pow2) {
       Z = row[k];
@@ -130,7 +208,7 @@ __global__ void k_row_transform(const RepInfo* reps, const RowRef* rows, const d
 
 // Column pass: one block per (replica, field, tile of 2^ltile k_x columns).
 // LDS: the tile's columns, then (power-of-two columns) the M/2 twiddles.
-__global__ void k_col_transform(const RepInfo* reps, const ColRef* cols, const double2* spec,
+__global__ __launch_bounds__(256) void k_col_transform(const RepInfo* reps, const ColRef* cols, const double2* spec,
                                 double* acc, const double2* tw_base) {
   extern __shared__ double2 lds[];
   const ColRef cr = cols[blockIdx.x];
@@ -150,17 +228,24 @@ __global__ void k_col_transform(const RepInfo* reps, const ColRef* cols, const d
   const int total = M << lt;
   // load: row-major reads of the tile's consecutive k_x of each row
   for (int base = threadIdx.x; base < total; base += kBatch * blockDim.x) {
-    double2 v[kBatch];
+    // (two plain arrays: an array of double2 assigned under a condition is
+    // kept in scratch memory)
+    double vr[kBatch], vi[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const int q = base + u * blockDim.x;
-      if (q < total && (q & tmask) < nc) v[u] = in[(size_t)(q >> lt) * nkx + (q & tmask)];
+      if (q < total && (q & tmask) < nc) {
+        const double2 t = in[(size_t)(q >> lt) * nkx + (q & tmask)];
+        vr[u] = t.x;
+        vi[u] = t.y;
+      }
     }
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const int q = base + u * blockDim.x;
       const int j = q >> lt, c = q & tmask;
-      if (q < total && c < nc) lds[(size_t)c * M + (R.pow2 ? bitrev(j, bits) : j)] = v[u];
+      if (q < total && c < nc)
+        lds[(size_t)c * M + (R.pow2 ? bitrev(j, bits) : j)] = make_double2(vr[u], vi[u]);
     }
   }
   if (R.pow2) {
@@ -169,31 +254,29 @@ __global__ void k_col_transform(const RepInfo* reps, const ColRef* cols, const d
     lds_fft(lds, bits, nc, tws);
     // accumulate: the three sums of a batch of entries are read before any is
     // written back
-    for (int base = threadIdx.x; base < total; base += kBatch * blockDim.x) {
-      double re[kBatch], im[kBatch], s2[kBatch], sr[kBatch], si[kBatch];
-      size_t o[kBatch];
-      bool ok[kBatch];
+    // (entry q of the tile is column q >> bits, k_z = q & (M - 1), at offset q
+    // of each accumulator run; the transform is read from LDS after the loads)
+    const int valid = min(total, nc * M);
+    for (int base = threadIdx.x; base < valid; base += kBatch * blockDim.x) {
+      double s2[kBatch], sr[kBatch], si[kBatch];
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
         const int q = base + u * blockDim.x;
-        const int c = q >> bits, kz = q & (M - 1);
-        ok[u] = q < total && c < nc;
-        o[u] = (size_t)c * M + kz;
-        if (ok[u]) {
-          const double2 P = lds[(size_t)c * M + kz];
-          re[u] = P.x * norm;
-          im[u] = P.y * norm;
-          s2[u] = a2[o[u]];
-          sr[u] = are[o[u]];
-          si[u] = aim[o[u]];
+        if (q < valid) {
+          s2[u] = a2[q];
+          sr[u] = are[q];
+          si[u] = aim[q];
         }
       }
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
-        if (ok[u]) {
-          a2[o[u]] = s2[u] + (re[u] * re[u] + im[u] * im[u]);
-          are[o[u]] = sr[u] + re[u];
-          aim[o[u]] = si[u] + im[u];
+        const int q = base + u * blockDim.x;
+        if (q < valid) {
+          const double2 P = lds[q];
+          const double re = P.x * norm, im = P.y * norm;
+          a2[q] = s2[u] + (re * re + im * im);
+          are[q] = sr[u] + re;
+          aim[q] = si[u] + im;
         }
       }
     }
@@ -222,21 +305,20 @@ __global__ void k_col_transform(const RepInfo* reps, const ColRef* cols, const d
   }
 }
 
-// Pressure: one block per replica.  Row sums over strips in strip order, row
-// means into the profile, then a fixed-shape tree over rows for the spatial
-// mean.  Layout of the replica's block: {sum, sum2, profile[Lz]}.
+// Pressure: one block per replica.  Row means into the profile, then a
+// fixed-shape tree over rows for the spatial mean.  Layout of the replica's block: {sum, sum2, profile[Lz]}.
 __global__ void k_pressure_reduce(const RepInfo* reps, const double* ppart, double* acc) {
   extern __shared__ double rows[];
   const RepInfo& R = reps[blockIdx.x];
-  const int Lz = R.Lz, ns = R.nstrips;
-  const double* pp = ppart + R.ppart_off;
+  const int Lz = R.Lz;
+  const double* pp = ppart + R.ppart_off;  // row sums of P - P_ref
   double* pa = acc + R.pacc_off;
   int P2 = 1;
   while (P2 < Lz) P2 <<= 1;
   for (int j = threadIdx.x; j < P2; j += blockDim.x) {
     double s = 0.0;
     if (j < Lz) {
-      for (int k = 0; k < ns; ++k) s += pp[(size_t)k * Lz + j];
+      s = pp[j];
       pa[2 + j] += s / (double)R.Lx;
     }
     rows[j] = s;
@@ -280,11 +362,12 @@ hipError_t launch_twiddles(const RepInfo* d_reps, const RepInfo* h_reps, int n_r
 
 hipError_t launch_row_transform(const RepInfo* reps, const RowRef* rows, int n_rows, int n_pairs,
                                 int max_row_lds, const double* fields, double2* spec,
-                                const double2* tw, hipStream_t stream) {
+                                const double2* tw, double* ppart, int32_t* watchdog,
+                                hipStream_t stream) {
   if (n_rows <= 0) return hipSuccess;
   const size_t lds = (size_t)max_row_lds * sizeof(double2);
   hipLaunchKernelGGL(k_row_transform, dim3(n_rows, n_pairs), dim3(256), lds, stream, reps, rows,
-                     fields, spec, tw);
+                     fields, spec, tw, ppart, watchdog);
   return hipGetLastError();
 }
 

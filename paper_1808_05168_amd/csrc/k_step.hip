@@ -31,7 +31,10 @@
 // load, or wrapped when the segment is a whole periodic row), and after one
 // barrier per row reads the eight neighbour densities of the non-local force
 // from LDS.  Stores are the node's own 18 post-collision values; in the tiled
-// layout each link of a wavefront's row is one contiguous 256-byte run.
+// layout each link of a wavefront's row is one contiguous 256-byte run.  A
+// step that samples also writes, per node, the FP64 density deviations of the
+// state it pulled (and the FP64 momenta for velocity sampling); the transform
+// pass forms the observables from them.
 #include "fnlb.h"
 #include "fnlb_device.hpp"
 #include "fnlb_internal.hpp"
@@ -66,15 +69,12 @@ __device__ __forceinline__ void edge_pull(Rsrc r, uint32_t link_b, uint32_t row_
 
 template <typename Real, typename Store, int MODE>
 __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
-  // Density rings in LDS (row slot, species, column + 1).  The collision reads
-  // sums in the compute type, exactly as in a step that does not sample, so
-  // sampling leaves the trajectory bit-identical; the observables read FP64
-  // sums, from a second ring when the compute type is FP32.
-  using DT = typename std::conditional<MODE == kSampleOnly, double, Real>::type;
-  constexpr bool kTwo = MODE == kStepSample && !std::is_same<Real, double>::value;
+  // Density ring in LDS (row slot, species, column + 1) in the compute type:
+  // the collision reads the same sums whether or not the step samples, so
+  // sampling leaves the trajectory bit-identical.
+  using DT = Real;
   constexpr int kRow = kSeg + 2;
   __shared__ DT ring[4][2][kRow];
-  __shared__ double oring[kTwo ? 4 : 1][2][kTwo ? kRow : 1];
   __shared__ Store edge[2][36];  // pulled populations of the two edge columns
   // With FP32 storage a lane parks the pulled populations of the rows it has
   // loaded but not yet collided in LDS (two slots, private to the lane).  That
@@ -124,28 +124,12 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   const bool wave_act = X0 + kWave * wv < Lx;
 
   // writes the density deviations of 18 pulled populations into ring column
-  // col of row jr (both rings when there are two)
+  // col of row jr
   auto put_col = [&](int jr, int col, const Store(&o)[18]) {
     DT da, db;
     density<DT>(o, da, db);
     ring[jr & 3][0][col] = da;
     ring[jr & 3][1][col] = db;
-    if constexpr (kTwo) {
-      double oa, ob;
-      density<double>(o, oa, ob);
-      oring[jr & 3][0][col] = oa;
-      oring[jr & 3][1][col] = ob;
-    }
-  };
-  // FP64 density rows for the observables
-  auto orow = [&](int jr, int sp) -> const double* {
-    if constexpr (kTwo) {
-      return oring[jr & 3][sp];
-    } else if constexpr (std::is_same<DT, double>::value) {
-      return ring[jr & 3][sp];
-    } else {
-      return nullptr;
-    }
   };
   // writes the density deviations of row jr of this lane into the ring (and,
   // for a whole periodic row, the wrapped edge columns)
@@ -313,77 +297,24 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     const double szref = rAs * (double)(jU - jD) * (1.0 / 6.0);  // species A
 
     if constexpr (MODE != kStep) {
-      // observables of f(t): delta c, delta rho and the pressure, from the FP64
-      // density sums
-      const double* oaU = orow(jU, 0);
-      const double* obU = orow(jU, 1);
-      const double* oaC = orow(j, 0);
-      const double* obC = orow(j, 1);
-      const double* oaD = orow(jD, 0);
-      const double* obD = orow(jD, 1);
-      const double dAc = oaC[c], dBc = obC[c];
-      const double aWc = oaC[c - 1], aEc = oaC[c + 1], bWc = obC[c - 1], bEc = obC[c + 1];
-      const double dAp = oaU[c], aWp = oaU[c - 1], aEp = oaU[c + 1];
-      const double dBp = obU[c], bWp = obU[c - 1], bEp = obU[c + 1];
-      const double dAm = oaD[c], aWm = oaD[c - 1], aEm = oaD[c + 1];
-      const double dBm = obD[c], bWm = obD[c - 1], bEm = obD[c + 1];
-      const double rhoA = rAj + dAc, rhoB = (rho0 - rAj) + dBc;
-      const double rho = rhoA + rhoB;
-      const double drho = (double)dAc + (double)dBc;
-      const double c0 = rAj / rho0;
-      const double dc = ((double)dAc - c0 * drho) / rho;
-      // pressure (half trace): rho/3 + (G/4) sum w|c|^2 [rhoA rhoB' + rhoB rhoA']
-      const double rAu = rA0 + rAs * jU, rAd = rA0 + rAs * jD;
-      const double rBu = rho0 - rAu, rBd = rho0 - rAd, rBj = rho0 - rAj;
-      const double sA = (1.0 / 9.0) * ((rAj + (double)aEc) + (rAj + (double)aWc) +
-                                       (rAu + (double)dAp) + (rAd + (double)dAm)) +
-                        (1.0 / 18.0) * ((rAu + (double)aEp) + (rAu + (double)aWp) +
-                                        (rAd + (double)aEm) + (rAd + (double)aWm));
-      const double sB = (1.0 / 9.0) * ((rBj + (double)bEc) + (rBj + (double)bWc) +
-                                       (rBu + (double)dBp) + (rBd + (double)dBm)) +
-                        (1.0 / 18.0) * ((rBu + (double)bEp) + (rBu + (double)bWp) +
-                                        (rBd + (double)bEm) + (rBd + (double)bWm));
-      const double dP =
-          drho * (1.0 / 3.0) + R.G * 0.25 * (rhoA * sB + rhoB * sA) - (R.p_ref - rho0 / 3.0);
-      // barycentric velocity of Eq. (10) as the collision sees it (after the
-      // wall fix, which zeroes U_z on the wall rows and leaves j_x alone); the
-      // total force is the non-ideal one, -G (rho^A s^B + rho^B s^A), since
-      // the a_* and non-equilibrium parts cancel between the species
-      double ux = 0.0, uz = 0.0;
-      if (flags & FNLB_SAMPLE_VELOCITY) {
-        double d[9];
-#pragma unroll
-        for (int l = 0; l < 9; ++l) d[l] = (double)cur[l] + (double)cur[9 + l];
-        const double jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
-        const double jz = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
-        const double vAx = (1.0 / 9.0) * (double)(aEc - aWc) +
-                           (1.0 / 36.0) * (double)((aEp - aWp) + (aEm - aWm));
-        const double vBx = (1.0 / 9.0) * (double)(bEc - bWc) +
-                           (1.0 / 36.0) * (double)((bEp - bWp) + (bEm - bWm));
-        const double vAz = (1.0 / 9.0) * (double)(dAp - dAm) +
-                           (1.0 / 36.0) * (double)((aEp + aWp) - (aEm + aWm)) + szref;
-        const double vBz = (1.0 / 9.0) * (double)(dBp - dBm) +
-                           (1.0 / 36.0) * (double)((bEp + bWp) - (bEm + bWm)) - szref;
-        const double Fx = -R.G * (rhoA * vBx + rhoB * vAx);
-        const double Fz = -R.G * (rhoA * vBz + rhoB * vAz);
-        ux = (jx + 0.5 * Fx) / rho;
-        uz = ((flags & FNLB_WALL_UZ_FIX) && (bot || top)) ? 0.0 : (jz + 0.5 * Fz) / rho;
-      }
+      // sample of f(t): the FP64 density deviations of this node and, for
+      // velocity sampling, its FP64 total momentum; the transform pass forms
+      // the observables from them
       if (act) {
+        double da, db;
+        density<double>(cur, da, db);
         double* fld = a.fields + R.field_off;
-        fld[(int64_t)j * Lx + x] = dc;
-        fld[(int64_t)(Lz + j) * Lx + x] = drho;
+        const int64_t plane = (int64_t)Lz * Lx, n = (int64_t)j * Lx + x;
+        fld[n] = da;
+        fld[plane + n] = db;
         if (flags & FNLB_SAMPLE_VELOCITY) {
-          fld[(int64_t)(2 * Lz + j) * Lx + x] = ux;
-          fld[(int64_t)(3 * Lz + j) * Lx + x] = uz;
+          double d[9];
+#pragma unroll
+          for (int l = 0; l < 9; ++l) d[l] = (double)cur[l] + (double)cur[9 + l];
+          fld[2 * plane + n] = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+          fld[3 * plane + n] = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
         }
-        const bool bad = !(rhoA > 0.0) || !(rhoB > 0.0) || !(dc + c0 > 0.0) ||
-                         !(dc + c0 < 1.0) || !isfinite(dP);
-        if (bad) atomicOr(a.watchdog, 1);
       }
-      const double tot = wave_sum(act ? dP : 0.0);
-      const int strip = X0 / kWave + wv;
-      if (lane == 0 && strip * kWave < Lx) a.ppart[R.ppart_off + (int64_t)strip * Lz + j] = tot;
     }
 
     if constexpr (MODE != kSampleOnly) {
