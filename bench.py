@@ -154,19 +154,24 @@ def summarize_trace(trace_dir, out_md, title, command, top=16):
 def summarize_profile(trace_dir, fetch_dir, write_dir, out_md, command):
     """Turns rocprofv3 outputs of this benchmark into the committed summary:
     kernel-trace statistics, the average duration of the step kernel in the
-    timed configuration (its most frequent grid size; autotuning trials use
-    other grids), and HBM bytes per step launch from FETCH_SIZE and WRITE_SIZE
-    scaled by what the same counters read for the plain 1 GiB copies that
-    --copy-calibration-mb 1024 runs first."""
+    roofline leg (the plain steps after the last sampling step, at the timed
+    grid size; in the sampled run the transforms of a sample overlap the plain
+    steps that follow it, and autotuning trials use other grids), and HBM bytes
+    per step launch from FETCH_SIZE and WRITE_SIZE scaled by what the same
+    counters read for the plain 1 GiB copies that --copy-calibration-mb 1024
+    runs first."""
     import csv
     from collections import Counter, defaultdict
     step_name = "k_step<float, float, 0>"
     stats = list(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_stats.csv"))))
-    trace = [r for r in csv.DictReader(open(os.path.join(trace_dir, "run_kernel_trace.csv")))
-             if step_name in r["Kernel_Name"]]
+    rows = sorted(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_trace.csv"))),
+                  key=lambda r: int(r["Start_Timestamp"]))
+    trace = [r for r in rows if step_name in r["Kernel_Name"]]
     grid = Counter(r["Grid_Size_X"] for r in trace).most_common(1)[0][0]
+    last_sample = max((int(r["Start_Timestamp"]) for r in rows
+                       if "k_step<float, float, 1>" in r["Kernel_Name"]), default=-1)
     durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace
-            if r["Grid_Size_X"] == grid]
+            if r["Grid_Size_X"] == grid and int(r["Start_Timestamp"]) > last_sample]
     avg_us = sum(durs) / len(durs) / 1e3
 
     def counters(d, name):
@@ -198,7 +203,9 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, out_md, command):
     for r in stats:
         lines.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs'])/1e3:.1f} | "
                      f"{float(r['Percentage']):.2f} |")
-    lines += ["", f"Step kernel in the timed configuration (grid {grid} threads, "
+    lines += ["", "In the sampled run the transforms of each sample run beside the plain steps "
+              "that follow it, so the averages above include that overlap.", "",
+              f"Step kernel in the roofline leg (plain steps, grid {grid} threads, "
               f"{len(durs)} dispatches): average {avg_us:.1f} us.", "",
               "## HBM traffic per step launch", "",
               f"FETCH_SIZE and WRITE_SIZE (KiB per dispatch, {nf} and {nw} step dispatches) "

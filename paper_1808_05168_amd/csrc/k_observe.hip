@@ -208,8 +208,9 @@ __global__ __launch_bounds__(256) void k_row_transform(const RepInfo* reps, cons
 
 // Column pass: one block per (replica, field, tile of 2^ltile k_x columns).
 // LDS: the tile's columns, then (power-of-two columns) the M/2 twiddles.
-__global__ __launch_bounds__(256) void k_col_transform(const RepInfo* reps, const ColRef* cols, const double2* spec,
-                                double* acc, const double2* tw_base) {
+__global__ __launch_bounds__(256) void k_col_transform(const RepInfo* reps, const ColRef* cols,
+                                                       const double2* spec, double* acc,
+                                                       const double2* tw_base) {
   extern __shared__ double2 lds[];
   const ColRef cr = cols[blockIdx.x];
   const RepInfo& R = reps[cr.rep];
@@ -249,23 +250,33 @@ __global__ __launch_bounds__(256) void k_col_transform(const RepInfo* reps, cons
     }
   }
   if (R.pow2) {
+    // The sums of the first batch of entries are loaded before the transform,
+    // so that their latency overlaps it (entry q of the tile is column
+    // q >> bits, k_z = q & (M - 1), at offset q of each accumulator run).
+    const int valid = min(total, nc * M);
+    double s2[kBatch], sr[kBatch], si[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int q = threadIdx.x + u * blockDim.x;
+      if (q < valid) {
+        s2[u] = a2[q];
+        sr[u] = are[q];
+        si[u] = aim[q];
+      }
+    }
     double2* tws = lds + ((size_t)M << lt);
     for (int m = threadIdx.x; m < M / 2; m += blockDim.x) tws[m] = tw[m];
     lds_fft(lds, bits, nc, tws);
-    // accumulate: the three sums of a batch of entries are read before any is
-    // written back
-    // (entry q of the tile is column q >> bits, k_z = q & (M - 1), at offset q
-    // of each accumulator run; the transform is read from LDS after the loads)
-    const int valid = min(total, nc * M);
     for (int base = threadIdx.x; base < valid; base += kBatch * blockDim.x) {
-      double s2[kBatch], sr[kBatch], si[kBatch];
+      if (base != (int)threadIdx.x) {
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int q = base + u * blockDim.x;
-        if (q < valid) {
-          s2[u] = a2[q];
-          sr[u] = are[q];
-          si[u] = aim[q];
+        for (int u = 0; u < kBatch; ++u) {
+          const int q = base + u * blockDim.x;
+          if (q < valid) {
+            s2[u] = a2[q];
+            sr[u] = are[q];
+            si[u] = aim[q];
+          }
         }
       }
 #pragma unroll
