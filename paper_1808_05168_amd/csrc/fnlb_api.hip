@@ -29,7 +29,8 @@ constexpr int kMaxDim = 4096;
 constexpr int kMaxDirect = 2048;
 // Complex entries of the column-pass LDS tile.
 constexpr int kColTile = 2048;  // complex values per column-transform tile (32 KiB)
-constexpr int kRowGroup = 512;  // complex values per row-transform block (short rows share)
+constexpr int kRowGroup = 1024;  // complex values per row-transform block (short rows share)
+constexpr int kTransformThreads = 256;  // threads of a transform block (at least one per row)
 
 int validate(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options* opt) {
   if (!reps || !opt || n_rep <= 0) return FNLB_EINVAL;
@@ -205,7 +206,7 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
   for (int r = 0; r < n_rep; ++r) {
     const RepInfo& R = P.info[r];
     // short power-of-two rows are transformed several to a block
-    const int per = R.pow2 ? std::max(1, kRowGroup / R.Lx) : 1;
+    const int per = R.pow2 ? std::min(kTransformThreads, std::max(1, kRowGroup / R.Lx)) : 1;
     for (int j = 0; j < R.Lz; j += per) {
       const int nr = std::min(per, R.Lz - j);
       P.rows.push_back(RowRef{r, j, nr, 0});

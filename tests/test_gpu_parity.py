@@ -80,6 +80,9 @@ VARIANTS = {
     "noiseless": (W.Replica(Lx=32, Lz=16, grad_c0=0.01, kT=0.0, G=0.5, seed=20), None, 500, 50),
     "large_seed_and_time": (W.Replica(Lx=32, Lz=8, grad_c0=0.0, kT=1e-4, seed=(1 << 63) + 5),
                             None, 50, 5),
+    # two-column power-of-two rows: a row-transform block holds one row per thread
+    "two_columns_tall_pow2": (W.Replica(Lx=2, Lz=512, grad_c0=1e-3, kT=1e-4, G=0.5, seed=28),
+                              None, 60, 5),
     # velocity structure factors: direct-sum (non-power-of-two) and FFT paths,
     # with and without the wall fix and the a_* correction
     "velocity_ragged": (W.Replica(Lx=100, Lz=20, grad_c0=5e-3, kT=1e-4, G=0.5, tau_s=0.7,
