@@ -40,6 +40,27 @@ def _events_time(lat, nsteps):
     return e0.elapsed_time(e1)
 
 
+def copy_ceiling_gbs(mib: int = 1024, reps: int = 20) -> float:
+    """Read + write bandwidth of a plain device-to-device copy of `mib` MiB
+    (torch's copy kernel), timed with HIP events: the practical streaming
+    ceiling of the box, beside the published peak."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    del src, dst
+    return 2 * n * 4 * reps / sec / 1e9
+
+
 def storage_agreement(F, reps, every: int, steps: int = 200) -> dict:
     """The same replicas (same seeds) advanced `steps` steps with FP32-deviation
     and with FP64 storage: largest relative differences over all replicas of
@@ -355,6 +376,7 @@ def main():
     achieved = bytes_per_node * nodes / t_launch / 1e9
     del lat_r
     traffic = _traffic_from_profiles()
+    copy_gbs = copy_ceiling_gbs()
 
     out = {
         "metric": "MLUPS (both species)",
@@ -376,7 +398,9 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_step (fused collide-stream)",
                      "launch_ms": round(t_launch * 1e3, 5),
-                     "algorithmic_bytes_per_launch": bytes_per_node * nodes},
+                     "algorithmic_bytes_per_launch": bytes_per_node * nodes,
+                     "copy_ceiling_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(achieved / copy_gbs, 4)},
         "wall_s": round(wall, 3),
     }
 

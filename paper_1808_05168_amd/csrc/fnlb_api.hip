@@ -25,6 +25,8 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 // Largest lattice dimension the observable kernels hold in LDS (64 KiB of
 // complex doubles per row or column).
 constexpr int kMaxDim = 4096;
+// the row transform reads a sample plane through 32-bit byte offsets
+static_assert((int64_t)kMaxDim * kMaxDim * 8 < ((int64_t)1 << 32), "sample plane offsets");
 // Largest non-power-of-two dimension (direct transform, quadratic cost).
 constexpr int kMaxDirect = 2048;
 // Complex entries of the column-pass LDS tile.
