@@ -3,15 +3,15 @@
 // sum_{x,j} dphi e^{-i q.r}, S(q) = <|Phi(q)|^2> on the lattice; Sec. IV.A for
 // S_U) and the mean pressure (Sec. IV.C).
 //
-// The step kernel writes the real fields of a sample.  A row pass transforms
-// two fields of a row at once as one complex sequence (z = delta c + i delta
-// rho, and z = U_x + i U_z) and splits the result by Hermitian symmetry into
-// the half spectra k_x = 0..Lx/2; a column pass transforms each k_x column
-// over the Lz rows and adds |Phi|^2, Re Phi and Im Phi to the FP64
-// accumulators.  Power-of-two lengths use an in-LDS radix-2 FFT; other
-// lengths a direct sum with exactly reduced twiddle indices.  Pressure
-// partials (one per strip and row) are reduced in a fixed order, so every
-// accumulator is deterministic.
+// The step kernel writes the FP64 density deviations (and momenta) of a
+// sample.  A row pass forms the real fields and the pressure from them,
+// transforms two fields of a row at once as one complex sequence (z = delta c
+// + i delta rho, and z = U_x + i U_z) and splits the result by Hermitian
+// symmetry into the half spectra k_x = 0..Lx/2; a column pass transforms each
+// k_x column over the Lz rows and adds |Phi|^2, Re Phi and Im Phi to the FP64
+// accumulators.  Power-of-two lengths use the in-LDS FFT; other lengths a
+// direct sum with exactly reduced twiddle indices.  Pressure row sums are
+// formed and reduced in a fixed order, so every accumulator is deterministic.
 #include "fnlb.h"
 #include "fnlb_fft.hpp"
 #include "fnlb_internal.hpp"
