@@ -267,11 +267,25 @@ def cpu_baseline(reps, budget_s: float):
         O.run(r, fr, 5, steps)
     dt = time.perf_counter() - t
     nodes = sum(r.Lx * r.Lz for r in sample)
+    # the same sample on one thread, for a third of the budget
+    O.set_threads(1)
+    t = time.perf_counter()
+    for r, fr in zip(sample, f):
+        O.run(r, fr, 5 + steps, 2)
+    cal1 = (time.perf_counter() - t) / 2
+    steps1 = max(3, int(budget_s / 3 / max(cal1, 1e-9)))
+    t = time.perf_counter()
+    for r, fr in zip(sample, f):
+        O.run(r, fr, 7 + steps, steps1)
+    dt1 = time.perf_counter() - t
+    O.set_threads(threads)
     return {"value": round(nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
+            "value_1thread": round(nodes * steps1 / dt1 / 1e6, 3),
             "sample": f"{len(sample)} replicas (one per size: "
                       + ", ".join(f"{r.Lx}x{r.Lz}" for r in sample)
-                      + f"), {steps} steps each, FP64, no sampling, {dt:.1f} s"}
+                      + f"), {steps} steps each, FP64, no sampling, {dt:.1f} s; one thread: "
+                      f"{steps1} steps each, {dt1:.1f} s"}
 
 
 def main():
@@ -402,6 +416,8 @@ def main():
                      "copy_ceiling_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
         "wall_s": round(wall, 3),
+        # the same batch with sampling off (the roofline leg)
+        "value_without_sampling": round(nodes / t_launch / 1e6, 1),
     }
 
     if not args.no_compare and prec == F.FP32_DEV:

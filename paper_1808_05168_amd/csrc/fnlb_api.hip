@@ -365,9 +365,13 @@ hipError_t capture_period(fnlb_handle* h, int parity) {
     if (le == hipSuccess && smp) {
       le = hipEventRecord(h->ev_fork, s);
       if (le == hipSuccess) le = hipStreamWaitEvent(h->obs_stream, h->ev_fork, 0);
-      if (le == hipSuccess) forked = true;
-      if (le == hipSuccess) le = observe(h, h->obs_stream);
-      if (le == hipSuccess) le = hipEventRecord(h->ev_join, h->obs_stream);
+      if (le == hipSuccess) {
+        forked = true;
+        le = observe(h, h->obs_stream);
+        // recorded even after a failed launch, so that the branch can join
+        const hipError_t re = hipEventRecord(h->ev_join, h->obs_stream);
+        if (le == hipSuccess) le = re;
+      }
     }
     h->cur ^= 1;
   }
