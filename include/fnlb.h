@@ -21,7 +21,8 @@
  *  - Device buffers (state, accumulators, workspace) are allocated and owned
  *    by the caller, sized by fnlb_bytes_required(), 256-byte aligned, and must
  *    outlive the handle.  The library allocates no device memory.  It owns
- *    only small host metadata, freed by fnlb_destroy().
+ *    only small host metadata and the streams, events and graphs of its
+ *    captured sampling periods, freed by fnlb_destroy().
  *  - Work is enqueued asynchronously on the caller's HIP stream; read_* calls
  *    synchronise that stream and copy into caller-allocated host arrays.
  *  - One handle is used from one host thread at a time.
@@ -128,12 +129,14 @@ int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep,
  * Samples according to options->sample_every.  All replicas advance in one
  * kernel launch per step.  Whole sampling periods (sample_every steps, or 16
  * steps without sampling) that start on a period boundary are replayed from a
- * HIP graph captured on first use (unless FNLB_NO_GRAPH); results are
- * identical either way.  Asynchronous. */
+ * HIP graph captured on first use (unless FNLB_NO_GRAPH).  In the graph the
+ * transforms of a sample run on a branch of their own beside the steps that
+ * follow it, joined before the period ends; results are identical either
+ * way.  Asynchronous: all of it is ordered on the caller's stream. */
 int fnlb_step(fnlb_handle* h, int64_t n);
 
 /* Chooses the number of rows each work item of the step kernel covers by
- * timing steps_per_trial >= 1 launches of each candidate (4 to 128 rows) and
+ * timing steps_per_trial >= 1 launches of each candidate (1 to 128 rows) and
  * keeps the fastest for this handle and, for the rest of the process, for
  * any handle with the same precision and set of lattice shapes created with
  * options->chunk_rows = 0.  Trial steps read the current state and write the
