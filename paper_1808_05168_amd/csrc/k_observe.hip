@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void k_row_transform(const RepInfo* reps, cons
                                                        const double2* tw_base, double* ppart,
                                                        int32_t* watchdog) {
   extern __shared__ double2 lds[];
-  __shared__ double red[256];
+  __shared__ double red[256 / kWave];
   const RowRef rr = rows[blockIdx.x];
   const RepInfo& R = reps[rr.rep];
   const int N = R.Lx, Lz = R.Lz, nkx = N / 2 + 1, nr = rr.nrows;
@@ -151,18 +151,24 @@ __global__ __launch_bounds__(256) void k_row_transform(const RepInfo* reps, cons
     }
   }
   if (pair == 0) {
-    // row sums of P - P_ref: strided partials, then a fixed-shape tree per row
-    red[threadIdx.x] = psum;
-    int P2 = 1;
-    while (P2 * 2 <= gsz) P2 *= 2;
-    __syncthreads();
-    if (live && t2 + P2 < gsz) red[threadIdx.x] += red[threadIdx.x + P2];
-    for (int h = P2 >> 1; h >= 1; h >>= 1) {
+    // row sums of P - P_ref: a butterfly over the row's lanes within each
+    // wavefront (fixed order, every lane receives the sum), then the row's
+    // wavefronts in order.  gsz is a power of two: rows are grouped only on
+    // power-of-two lattices, where every group holds the same power of two.
+    const int w = gsz < kWave ? gsz : kWave;
+    double v = psum;
+    for (int m = w >> 1; m >= 1; m >>= 1) v += __shfl_xor(v, m, w);
+    if (gsz > kWave) {
+      if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
       __syncthreads();
-      if (live && t2 < h) red[threadIdx.x] += red[threadIdx.x + h];
+      if (live && t2 == 0) {
+        double sum = 0.0;
+        for (int k = 0; k < gsz / kWave; ++k) sum += red[threadIdx.x / kWave + k];
+        ppart[R.ppart_off + j] = sum;
+      }
+    } else if (live && t2 == 0) {
+      ppart[R.ppart_off + j] = v;
     }
-    __syncthreads();
-    if (live && t2 == 0) ppart[R.ppart_off + j] = red[threadIdx.x];
     if (bad) atomicOr(watchdog, 1);
   }
   if (R.pow2) {
