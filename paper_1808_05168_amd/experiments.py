@@ -11,6 +11,10 @@
   ensemble of independent replicas, reduced as in Eqs. (36)-(37):
   phi S_NE(q~) = S_c(q, 0) / (3 kT c(1-c) / rho_bar) - 1 against phi q~^-4, with
   phi from the imposed gradient and from the measured bulk gradient.
+* ``gradient_scan``: structure factors and mean pressure of one lattice at
+  several imposed gradients (one replica per gradient, one batch), in either
+  storage form, for the dependence of S_c, S_rho and the mean pressure shift
+  on grad c0.
 * ``mean_row_profile``: time-averaged row means of a sampled field, read out of
   the k_x = 0 column of the accumulated Fourier sums (no extra accumulator).
 * ``correlation``: the translation-averaged two-point correlation of a sampled
@@ -250,6 +254,62 @@ def ne_pressure(Ls: Iterable[int], grads: Iterable[float], kT: float = 1e-4, G: 
                         profiles=profiles, steps=steps, warmup=warmup, seeds=seeds)
 
 
+@dataclasses.dataclass
+class GradientScan:
+    """Outcome of ``gradient_scan``; dictionary keys are the gradients."""
+    precision: int
+    warmup: int
+    steps: int
+    sample_every: int
+    kT: float
+    G: float
+    S_eq_c: float                      # 3 kT c(1-c) / rho_bar at c = 1/2
+    S_c_qx: Dict[float, np.ndarray]    # S_c(q_x, 0), k_x = 1..Lx/2
+    S_c_band: Dict[float, float]       # mean of S_c over all q with k_x >= 1
+    S_rho_band: Dict[float, float]     # mean of S_rho over all q with k_x >= 1
+    P_mean: Dict[float, Tuple[float, float]]  # time mean of mean(P - P_ref), naive std. error
+    P_shift: Dict[float, Tuple[float, float]]  # P_mean(grad) - P_mean(0)
+
+
+def gradient_scan(Lx: int = 512, Lz: int = 256, grads: Iterable[float] = (0.0, 5e-4, 1e-3),
+                  kT: float = 1e-5, G: float = 0.5, warmup: int = 20000, steps: int = 180000,
+                  sample_every: int = 10, precision: int = _f.FP64, seed: int = 1,
+                  device: str = "cuda:0") -> GradientScan:
+    """One Lx x Lz lattice at each imposed gradient (the same Philox seed for
+    all, so the gradients see the same noise), all tau = 1, run as one batch:
+    `warmup` steps, then `steps` steps sampled every `sample_every`.  The naive
+    standard error of the mean pressure treats the samples as independent."""
+    grads = [float(g) for g in grads]
+    reps = [_Run(Lx=Lx, Lz=Lz, grad_c0=g, kT=kT, G=G, seed=seed) for g in grads]
+    lat = _f.Lattice(reps, precision=precision, sample_every=sample_every, device=device)
+    lat.step(warmup)
+    lat.reset_accumulators()
+    lat.step(steps)
+    S_c_qx, S_c_band, S_rho_band, P_mean = {}, {}, {}, {}
+    for i, g in enumerate(grads):
+        spectra = []
+        for field in (_f.FIELD_C, _f.FIELD_RHO):
+            a2, re, im, n = lat.read_structure_factor(i, field)
+            n = max(n, 1)
+            spectra.append(a2 / n - ((re / n) ** 2 + (im / n) ** 2))
+        S_c, S_rho = spectra
+        S_c_qx[g] = S_c[0, 1:].copy()
+        S_c_band[g] = float(S_c[:, 1:].mean())
+        S_rho_band[g] = float(S_rho[:, 1:].mean())
+        s, s2, _, n = lat.read_pressure(i)
+        m = s / n
+        var = max(s2 / n - m * m, 0.0)
+        P_mean[g] = (float(m), float(np.sqrt(var / max(n - 1, 1))))
+    lat.close()
+    g0 = grads[0]
+    P_shift = {g: (P_mean[g][0] - P_mean[g0][0], float(np.hypot(P_mean[g][1], P_mean[g0][1])))
+               for g in grads}
+    return GradientScan(precision=precision, warmup=warmup, steps=steps,
+                        sample_every=sample_every, kT=kT, G=G, S_eq_c=0.75 * kT,
+                        S_c_qx=S_c_qx, S_c_band=S_c_band, S_rho_band=S_rho_band,
+                        P_mean=P_mean, P_shift=P_shift)
+
+
 def _main(argv=None) -> None:
     import argparse
     ap = argparse.ArgumentParser(prog="python -m paper_1808_05168_amd.experiments",
@@ -273,7 +333,30 @@ def _main(argv=None) -> None:
     b.add_argument("--seeds", type=int, default=16)
     b.add_argument("--warmup", type=int, default=150000)
     b.add_argument("--steps", type=int, default=400000)
+    c = sub.add_parser("gradscan", help="S_c, S_rho and mean pressure against grad c0")
+    c.add_argument("--Lx", type=int, default=512)
+    c.add_argument("--Lz", type=int, default=256)
+    c.add_argument("--grad", type=float, nargs="+", default=[0.0, 5e-4, 1e-3])
+    c.add_argument("--kT", type=float, default=1e-5)
+    c.add_argument("--G", type=float, default=0.5)
+    c.add_argument("--warmup", type=int, default=20000)
+    c.add_argument("--steps", type=int, default=180000)
+    c.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     args = ap.parse_args(argv)
+    if args.what == "gradscan":
+        r = gradient_scan(args.Lx, args.Lz, args.grad, kT=args.kT, G=args.G,
+                          warmup=args.warmup, steps=args.steps,
+                          precision=_f.FP64 if args.precision == "fp64" else _f.FP32_DEV)
+        print(f"{args.precision}: {r.warmup} + {r.steps} steps, sampled every {r.sample_every}")
+        for g in sorted(r.S_c_band):
+            sq = r.S_c_qx[g]
+            print(f"grad c0 {g:.4g}  S_c band / S_eq {r.S_c_band[g] / r.S_eq_c:.4f}  "
+                  f"S_rho band / kT {r.S_rho_band[g] / r.kT:.4f}  "
+                  f"S_c(q_x, 0) / S_eq at k_x = 1, 2, 4, 8, 16: "
+                  + " ".join(f"{sq[k - 1] / r.S_eq_c:.3f}" for k in (1, 2, 4, 8, 16))
+                  + f"  mean(P - P_ref) {r.P_mean[g][0]:.5e} +- {r.P_mean[g][1]:.1e}"
+                  f"  shift {r.P_shift[g][0]:.4e} +- {r.P_shift[g][1]:.1e}")
+        return
     if args.what == "spectrum":
         r = ne_spectrum(L=args.L, Lx=args.Lx, kT=args.kT, grad_c0=args.grad,
                         replicas=args.replicas, warmup=args.warmup, steps=args.steps,

@@ -112,3 +112,32 @@ def test_ne_spectrum_matches_oracle(F):
     C[0] -= r.S_eq
     np.testing.assert_allclose(r.C_x, C, rtol=0, atol=1e-10 * np.abs(C).max())
     assert np.allclose(r.q_tilde, 2 * np.pi * np.arange(1, Lx // 2 + 1) / Lx * L)
+
+
+def test_gradient_scan_matches_oracle(F):
+    """The grad c0 scan (S_c, S_rho band means, S_c(q_x, 0), mean pressure and
+    its shift) against the same replicas run on the oracle."""
+    from paper_1808_05168_amd import experiments as X
+    Lx, Lz, grads, kT, G, warm, steps, every = 32, 16, [0.0, 5e-3, 1e-2], 1e-4, 0.5, 40, 120, 6
+    say("case: gradient scan 32x16 fp64")
+    res = X.gradient_scan(Lx, Lz, grads, kT=kT, G=G, warmup=warm, steps=steps,
+                          sample_every=every, precision=F.FP64, seed=7)
+    P = {}
+    for g in grads:
+        r = X._Run(Lx=Lx, Lz=Lz, grad_c0=g, kT=kT, G=G, seed=7)
+        f = O.init_state(r)
+        O.run(r, f, 0, warm)
+        acc = O.Accum(Lx, Lz)
+        O.run(r, f, warm, steps, acc, sample_every=every)
+        n = acc.n_samples
+        S = acc.sq[:, 0] / n - ((acc.sq[:, 1] / n) ** 2 + (acc.sq[:, 2] / n) ** 2)
+        S_c, S_rho = S[0], S[1]
+        scale = S_c[:, 1:].mean()
+        assert abs(res.S_c_band[g] - S_c[:, 1:].mean()) <= 1e-12 * scale
+        assert abs(res.S_rho_band[g] - S_rho[:, 1:].mean()) <= 1e-12 * S_rho[:, 1:].mean()
+        np.testing.assert_allclose(res.S_c_qx[g], S_c[0, 1:], rtol=0, atol=1e-12 * scale)
+        P[g] = acc.pr[0] / n
+    scale = max(abs(v) for v in P.values()) + 1e-14
+    for g in grads:
+        assert abs(res.P_mean[g][0] - P[g]) <= 1e-12 * scale
+        assert abs(res.P_shift[g][0] - (P[g] - P[grads[0]])) <= 2e-12 * scale
