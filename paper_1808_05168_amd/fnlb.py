@@ -100,7 +100,8 @@ def _check(rc: int, what: str) -> None:
 def _dp(a: Optional[np.ndarray]):
     if a is None:
         return None
-    assert a.dtype == np.float64 and a.flags.c_contiguous
+    if a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise TypeError("expected a C-contiguous float64 array")
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
@@ -265,7 +266,8 @@ class Lattice:
     def write_populations(self, rep: int, f: np.ndarray) -> None:
         f = np.ascontiguousarray(f, dtype=np.float64)
         r = self.reps[rep]
-        assert f.shape == (2, 9, r.Lz, r.Lx)
+        if f.shape != (2, 9, r.Lz, r.Lx):
+            raise ValueError(f"populations of shape {f.shape}, expected {(2, 9, r.Lz, r.Lx)}")
         _check(self._lib.fnlb_write_populations(self._h, rep, _dp(f)), "fnlb_write_populations")
 
     def save(self) -> np.ndarray:
