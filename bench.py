@@ -327,8 +327,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(replicas and z-slabs would shard across GPUs, see the design notes)",
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(replicas, and z-slabs of a single lattice, would shard across GPUs)",
               file=sys.stderr)
         sys.exit(2)
 
