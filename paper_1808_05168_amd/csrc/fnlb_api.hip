@@ -2,6 +2,7 @@
 // replica and work-item tables, the per-step launch sequence and the
 // synchronous read/write calls of the C ABI (include/fnlb.h).
 #include "fnlb.h"
+#include "fnlb_device.hpp"
 #include "fnlb_internal.hpp"
 #include "fnlb_state.hpp"
 
@@ -69,6 +70,7 @@ struct Plan {
   size_t state_half = 0;  // bytes of one state copy
   size_t state_bytes = 0, accum_bytes = 0, work_bytes = 0;
   // work-buffer offsets (bytes)
+  size_t o_bm = 0;  // FP64 Box-Muller tables
   size_t o_reps = 0, o_items = 0, o_rows = 0, o_cols = 0, o_misc = 0, o_tw = 0, o_fields = 0,
          o_spec = 0, o_ppart = 0;
   size_t item_capacity = 0;  // items the work buffer holds (row ranges of one row)
@@ -125,6 +127,31 @@ int auto_chunk(const fnlb_replica_params* reps, int n_rep) {
   int chunk = 1;
   while (chunk * 2 <= c && chunk < 64) chunk *= 2;
   return chunk;
+}
+
+// The FP64 Box-Muller tables (see BmTables), computed in extended precision.
+void fill_bm_tables(BmTables& T) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int j = 0; j < 256; ++j) {
+    const long double ang = 2.0L * pi * (long double)j / 256.0L;
+    T.sc[j] = make_double2((double)sinl(ang), (double)cosl(ang));
+  }
+  for (int j = 0; j < 96; ++j) {
+    if (j == 31 || j == 32) {
+      T.lg[j] = make_double2(1.0, 0.0);
+      continue;
+    }
+    const long double b = 0.75L + ((long double)j + 0.5L) / 128.0L;
+    int ex;
+    const double m = std::frexp((double)(1.0L / b), &ex);  // 20 significant bits
+    const double c = std::ldexp(std::nearbyint(std::ldexp(m, 20)), ex - 20);
+    T.lg[j] = make_double2(c, (double)logl((long double)c));
+  }
+  const long double ln2 = 0.693147180559945309417232121458176568L;
+  int ex;
+  const double m = std::frexp((double)ln2, &ex);  // 42 significant bits
+  const double hi = std::ldexp(std::nearbyint(std::ldexp(m, 42)), ex - 42);
+  T.ln2 = make_double2(hi, (double)(ln2 - (long double)hi));
 }
 
 void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* opt, Plan& P) {
@@ -241,6 +268,8 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
   o = align_up(o + P.cols.size() * sizeof(ColRef));
   P.o_misc = o;  // int64 time base + int32 watchdog
   o = align_up(o + 16);
+  P.o_bm = o;
+  o = align_up(o + sizeof(BmTables));
   P.o_tw = o;
   o = align_up(o + (size_t)tw_c * 16);
   P.o_fields = o;
@@ -481,6 +510,11 @@ int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options
   auto up = [&](size_t off, const void* src, size_t n) {
     if (e == hipSuccess && n) e = hipMemcpyAsync(h->work + off, src, n, hipMemcpyHostToDevice, s);
   };
+  static_assert(sizeof(BmTables) % 16 == 0, "table layout");
+  BmTables bm;
+  fill_bm_tables(bm);
+  up(P.o_bm, &bm, sizeof(BmTables));
+  for (RepInfo& R : h->plan.info) R.bm = (const BmTables*)(h->work + P.o_bm);
   up(P.o_reps, P.info.data(), P.info.size() * sizeof(RepInfo));
   up(P.o_items, P.items.data(), P.items.size() * sizeof(Item));
   up(P.o_rows, P.rows.data(), P.rows.size() * sizeof(RowRef));

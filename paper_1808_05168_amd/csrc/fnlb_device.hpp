@@ -1,5 +1,5 @@
 // Device helpers of the fnlb kernels: the counter-based noise generator,
-// Box-Muller in FP64 and FP32, and wavefront lane shifts.
+// Box-Muller in FP64 and FP32, and a wavefront sum.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -40,14 +40,67 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
   return Philox4{{c0, c1, c2, c3}};
 }
 
+// Tables of the FP64 Box-Muller, filled on the host at init (in extended
+// precision) and read through the vector caches.
+//  sc[j] = (sin, cos)(2 pi j / 256), j = 0..255.
+//  lg[j] = (c_j, ln c_j) for the log reduction over f in [3/4, 3/2) in buckets
+//          of width 1/128: c_j is 1 / (3/4 + (j + 1/2) / 128) rounded to 20
+//          significant bits (so that f c_j is exact), and exactly 1 for the two
+//          buckets next to f = 1 (j = 31, 32), which keeps ln u accurate to a
+//          few ulps relative as u -> 1.
+//  ln2 = (ln 2 rounded to 42 bits, the rest), so that e ln 2 is exact for the
+//        small integers e that occur.
+struct BmTables {
+  double2 sc[256];
+  double2 lg[96];
+  double2 ln2;
+};
+
+// ln u for u = (w + 1/2) 2^-32: u = 2^e f with f in [3/4, 3/2), then
+// ln u = e ln 2 - ln c_j + ln(1 + r) with r = f c_j - 1 (exact, |r| < 1/128)
+// and the Taylor series of ln(1 + r) to r^8 (remainder below 1e-20).
+__device__ __forceinline__ double bm_log(uint32_t w, const BmTables* __restrict__ tab) {
+  const double u = ((double)w + 0.5) * 0x1.0p-32;
+  int k;
+  const double m = frexp(u, &k);  // u = m 2^k, m in [1/2, 1)
+  const bool lo = m < 0.75;
+  const double f = lo ? 2.0 * m : m;
+  const int e = lo ? k - 1 : k;
+  const int j = min((int)((f - 0.75) * 128.0), 95);
+  const double2 cl = tab->lg[j];
+  const double r = f * cl.x - 1.0;
+  const double p =
+      r * (1.0 + r * (-1.0 / 2 + r * (1.0 / 3 + r * (-1.0 / 4 + r * (1.0 / 5 + r * (-1.0 / 6 +
+                                      r * (1.0 / 7 - r * (1.0 / 8))))))));
+  const double2 ln2 = tab->ln2;
+  const double ef = (double)e;
+  return (ef * ln2.x - cl.y) + (p + ef * ln2.y);
+}
+
+// (sin, cos)(2 pi u) for u = (w + 1/2) 2^-32: with the angle in turns an
+// exact 33-bit fraction, u = j / 256 + (d + 1/2) 2^-32 with |d + 1/2| <= 2^23,
+// and the small angle a = 2 pi (d + 1/2) 2^-32 (|a| <= pi / 256) goes through
+// its Taylor series (sin to a^7, 1 - cos to a^6; remainders below 1e-20).
+__device__ __forceinline__ void bm_sincos(uint32_t w, const BmTables* __restrict__ tab, double& s,
+                                          double& c) {
+  const uint32_t jj = (w >> 24) + ((w >> 23) & 1u);  // nearest multiple of 2^24, in 2^24 units
+  const int32_t d = (int32_t)(w - (jj << 24));
+  const double2 t = tab->sc[jj & 255u];
+  const double a = ((double)d + 0.5) * 0x1.921fb54442d18p-30;  // 2 pi 2^-32
+  const double a2 = a * a;
+  const double sa = a + a * a2 * (-1.0 / 6 + a2 * (1.0 / 120 - a2 * (1.0 / 5040)));
+  const double q = a2 * (0.5 + a2 * (-1.0 / 24 + a2 * (1.0 / 720)));  // 1 - cos a
+  s = t.x + (t.y * sa - t.x * q);
+  c = t.y - (t.x * sa + t.y * q);
+}
+
 // Box-Muller (Box and Muller 1958) on u = (w + 1/2) 2^-32:
 // g0 = sqrt(-2 ln u_a) cos(2 pi u_b), g1 = sqrt(-2 ln u_a) sin(2 pi u_b).
-__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& g0, double& g1) {
-  const double ua = ((double)wa + 0.5) * 0x1.0p-32;
-  const double ub = ((double)wb + 0.5) * 0x1.0p-32;
-  const double r = sqrt(-2.0 * log(ua));
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& g0, double& g1,
+                                           const BmTables* __restrict__ tab) {
+  const double r = sqrt(-2.0 * bm_log(wa, tab));
   double s, c;
-  sincospi(2.0 * ub, &s, &c);
+  bm_sincos(wb, tab, s, c);
   g0 = r * c;
   g1 = r * s;
 }
@@ -60,7 +113,8 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& g0,
 // v <= 1/16) in v = 1 - u_a = (~w + 1/2) 2^-32, which FP32 holds to full
 // relative precision.  The angle 2 pi u_b is written as pi + 2 pi x with
 // x = u_b - 1/2 in (-1/2, 1/2).
-__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& g0, float& g1) {
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& g0, float& g1,
+                                           const BmTables*) {
   constexpr float kMinus2Ln2 = -1.3862943611198906f;
   const float u = fmaf((float)wa, 0x1.0p-32f, 0x1.0p-33f);
   const float nl_log = kMinus2Ln2 * __builtin_amdgcn_logf(u);
@@ -85,34 +139,15 @@ __device__ __forceinline__ Philox4 node_call(uint32_t node, uint64_t t, uint32_t
 }
 
 // The standard normals g_{4c}, ..., g_{4c+3} (Box-Muller on the word pairs of
-// call c); g_14 and g_15 of call 3 are not used by the step.
+// call c); g_14 and g_15 of call 3 are not used by the step.  tab: the FP64
+// Box-Muller tables (unused by the FP32 form).
 template <typename Real>
 __device__ __forceinline__ void node_normals(uint32_t node, uint64_t t, uint32_t call,
-                                             uint32_t k0, uint32_t k1, Real (&g)[4]) {
+                                             uint32_t k0, uint32_t k1, Real (&g)[4],
+                                             const BmTables* tab) {
   const Philox4 r = node_call(node, t, call, k0, k1);
-  box_muller(r.v[0], r.v[1], g[0], g[1]);
-  box_muller(r.v[2], r.v[3], g[2], g[3]);
-}
-
-// Wavefront lane shifts through DPP: lane i receives lane i-1 (from_left) or
-// lane i+1 (from_right); the edge lane that has no source keeps its own value.
-__device__ __forceinline__ float from_left(float v) {
-  return __int_as_float(
-      __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xf, 0xf, false));
-}
-__device__ __forceinline__ float from_right(float v) {
-  return __int_as_float(
-      __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xf, 0xf, false));
-}
-__device__ __forceinline__ double from_left(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),
-                          __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
-}
-__device__ __forceinline__ double from_right(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),
-                          __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
+  box_muller(r.v[0], r.v[1], g[0], g[1], tab);
+  box_muller(r.v[2], r.v[3], g[2], g[3], tab);
 }
 
 // Deterministic sum over the 64 lanes of a wavefront (fixed butterfly order);

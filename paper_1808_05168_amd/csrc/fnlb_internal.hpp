@@ -12,6 +12,8 @@
 
 namespace fnlb {
 
+struct BmTables;  // tables of the FP64 Box-Muller (fnlb_device.hpp)
+
 // A block of four wavefronts updates a segment of 256 consecutive columns of
 // one row range.  Rows are padded to 64 elements so every segment starts on a
 // cache-line boundary.
@@ -54,6 +56,7 @@ struct alignas(256) RepInfo {
   double sig_base[9];     // same without the density factor (local-noise option)
   double p_ref;           // rho_bar/3 + G rho_bar^2 / 12
   double inv_norm;        // 1 / sqrt(Lx Lz)
+  const BmTables* bm;     // FP64 Box-Muller tables in the work buffer (shared)
 };
 
 // One block's work: replica, 256-column segment and a range of rows.

@@ -190,10 +190,17 @@ __global__ __launch_bounds__(256) void k_adj_local(const AdjArgs a) {
     // noise: the same 14 normals as the forward step
     const uint32_t node = (uint32_t)(j * Lx + x);
     double g[16];
+    // one call at a time (not unrolled): the table-driven FP64 Box-Muller of
+    // four calls interleaved would raise the register pressure of this kernel
+#pragma unroll 1
     for (uint32_t call = 0; call < 4; ++call) {
       double q4[4];
-      node_normals(node, (uint64_t)a.t, call, R.seed_lo, R.seed_hi, q4);
-      for (int i = 0; i < 4; ++i) g[4 * call + i] = q4[i];
+      node_normals(node, (uint64_t)a.t, call, R.seed_lo, R.seed_hi, q4, R.bm);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (c == (int)call) g[4 * c + i] = q4[i];
     }
     // gaussian index of moment a for species A / B (a = 3..8); a = 1,2 use g0, g1
     const int gA[9] = {0, 0, 1, 2, 3, 4, 5, 6, 7};

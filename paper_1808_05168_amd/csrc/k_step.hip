@@ -263,10 +263,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     Real gA0[4], gA1[4], gB0[4], gB1[4];
     if constexpr (MODE != kSampleOnly) {
       if (wave_act) {
-        node_normals(node, (uint64_t)t, 2u, k0, k1, gB0);
-        node_normals(node, (uint64_t)t, 3u, k0, k1, gB1);
-        node_normals(node, (uint64_t)t, 0u, k0, k1, gA0);
-        node_normals(node, (uint64_t)t, 1u, k0, k1, gA1);
+        node_normals(node, (uint64_t)t, 2u, k0, k1, gB0, R.bm);
+        node_normals(node, (uint64_t)t, 3u, k0, k1, gB1, R.bm);
+        node_normals(node, (uint64_t)t, 0u, k0, k1, gA0, R.bm);
+        node_normals(node, (uint64_t)t, 1u, k0, k1, gA1, R.bm);
       }
     }
 
