@@ -133,6 +133,9 @@ def adjoint_leg(F, W, reps_done: int = 3) -> dict:
 
 
 STEP_SOURCES = ("k_step.hip", "fnlb_device.hpp", "fnlb_internal.hpp", "fnlb_state.hpp")
+# SQ counters of the one --pmc pass behind profiles/counters_batched96_fp32dev.md
+PMC_SET = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU",
+           "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_BUSY_CYCLES")
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_k_step_batched96_fp32dev.json")
 
 
@@ -244,6 +247,47 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, out_md, command):
     print("\n".join(lines))
 
 
+def summarize_counters(pmc_dir, out_md, command):
+    """Per-kernel averages of the SQ counters of one rocprofv3 --pmc pass over
+    this benchmark, with the derived figures quoted in the design notes:
+    VALU instructions per node (wavefront instructions x 64 / nodes), the share
+    of wave-resident cycles spent issuing VALU work and waiting, and LDS bank
+    conflict cycles per LDS instruction."""
+    import csv
+    from collections import defaultdict
+    import workloads as W
+    nodes = sum(r.Lx * r.Lz for r in W.batched_ensemble(96))
+    agg = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(os.path.join(pmc_dir, "run_counter_collection.csv"))):
+        name = r["Kernel_Name"].replace("fnlb::(anonymous namespace)::", "")
+        name = name.split("(")[0] if "k_step" not in name else name.split("(fnlb")[0]
+        agg[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = ["# SQ counters, batched 96-replica FP32-deviation workload", "",
+             "Command (run from the repository root; <out> is any output directory):", "",
+             "```", command.strip(), "```", "",
+             "Averages per dispatch of the library's kernels. VALU/node = SQ_INSTS_VALU x 64 "
+             "/ 4,177,920 nodes. The next two columns are raw ratios of counters to "
+             "SQ_WAVE_CYCLES (SQ_ACTIVE_INST_VALU, SQ_WAIT_ANY), summed over the wavefronts "
+             "of a dispatch; their cycle units need not match. The last column is "
+             "SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS.", "",
+             "| kernel | waves | VALU/node | ACTIVE_INST_VALU / WAVE_CYCLES | "
+             "WAIT_ANY / WAVE_CYCLES | LDS instr | bank-conflict cycles per LDS instr |",
+             "|---|---|---|---|---|---|---|"]
+    for name, c in sorted(agg.items()):
+        m = {k: sum(v) / len(v) for k, v in c.items()}
+        if not any(k in name for k in ("k_step", "transform", "pressure")):
+            continue
+        wc = max(m.get("SQ_WAVE_CYCLES", 1.0), 1.0)
+        lines.append(
+            f"| {name} | {m['SQ_WAVES']:.0f} | {m['SQ_INSTS_VALU'] * 64 / nodes:.0f} | "
+            f"{m['SQ_ACTIVE_INST_VALU'] / wc:.2f} | {m['SQ_WAIT_ANY'] / wc:.2f} | "
+            f"{m['SQ_INSTS_LDS']:.3g} | "
+            f"{m['SQ_LDS_BANK_CONFLICT'] / max(m['SQ_INSTS_LDS'], 1.0):.2f} |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def cpu_baseline(reps, budget_s: float):
     """The oracle as it stands, on one replica of each lattice size, for as many
     steps as fit the budget (at least 20)."""
@@ -311,10 +355,21 @@ def main():
     ap.add_argument("--summarize-profile", nargs=3, metavar=("TRACE", "FETCH", "WRITE"),
                     help="summarise rocprofv3 output directories into profiles/ (CPU only)")
     ap.add_argument("--profile-command", default="")
+    ap.add_argument("--summarize-counters", metavar="PMC_DIR",
+                    help="write profiles/counters_batched96_fp32dev.md from a --pmc pass "
+                         "with the counters of PMC_SET")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE", "NAME", "TITLE"),
                     help="summarise a rocprofv3 kernel trace into profiles/NAME.md (CPU only)")
     args = ap.parse_args()
 
+    if args.summarize_counters:
+        d = args.summarize_counters
+        summarize_counters(d, os.path.join(ROOT, "profiles", "counters_batched96_fp32dev.md"),
+                           f"rocprofv3 --pmc {' '.join(PMC_SET)} --output-format csv -d <out>/pc "
+                           f"-o run -- python3 bench.py --steps 20 --warmup 2 --no-cpu-baseline "
+                           f"--no-compare --no-adjoint --chunk-rows 8\n"
+                           f"python3 bench.py --summarize-counters <out>/pc")
+        return
     if args.summarize_trace:
         d, name, title = args.summarize_trace
         summarize_trace(d, os.path.join(ROOT, "profiles", name + ".md"), title,
