@@ -979,8 +979,10 @@ int adjoint_gradient(fnlb_handle* h, bool pressure, int32_t field, const double*
     if (e == hipSuccess)
       e = launch_sum((const double*)(W + A.jpart), (int)((P + 255) / 256), dJ, s);
   }
-  // reverse sweep over the checkpointed segments
+  // reverse sweep over the checkpointed segments; the parameter partials of
+  // each block run over the whole sweep and are summed once at its end
   if (e == hipSuccess) e = launch_fill_zero(mu[0], 2 * SH, s);
+  if (e == hipSuccess) e = launch_fill_zero(W + A.tpart, ((N + 63) / 64) * 3 * 8, s);
   int nx = 0;  // mu[nx] holds dJ/dS_{t+1}
   for (int64_t sgi = A.nck - 1; sgi >= 0 && e == hipSuccess; --sgi) {
     const int64_t ts = sgi * K, te = std::min<int64_t>(horizon, ts + K);
@@ -994,7 +996,7 @@ int adjoint_gradient(fnlb_handle* h, bool pressure, int32_t field, const double*
       if (e == hipSuccess && sampled(t0 + k)) {
         if (pressure)
           e = launch_adj_psample(dR, R, (const double*)(W + A.dens), (const double*)(W + A.Wq),
-                                 (double*)(W + A.adjf), (double*)(W + A.tpart), theta, s);
+                                 (double*)(W + A.adjf), (double*)(W + A.tpart), s);
         else
           e = launch_adj_sample(dR, R, h->d_tw(), (const double*)(W + A.Wq),
                                 (const double2*)(W + A.mean), field, ns,
@@ -1006,10 +1008,11 @@ int adjoint_gradient(fnlb_handle* h, bool pressure, int32_t field, const double*
         e = launch_adj_step(dR, R, S, (const double*)mu[nx], (double*)mu[nx ^ 1],
                             (double*)(W + A.dens), (double*)(W + A.gf), (double*)(W + A.gs),
                             adjf, pressure ? kAdjPressure : field, t0 + k,
-                            (double*)(W + A.tpart), theta, s);
+                            (double*)(W + A.tpart), s);
       nx ^= 1;
     }
   }
+  if (e == hipSuccess) e = launch_adj_theta(R, (const double*)(W + A.tpart), theta, s);
   double out[5] = {0, 0, 0, 0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(out, theta, 5 * 8, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -113,7 +113,10 @@ hipError_t launch_adj_density(const RepInfo* d_rep, const RepInfo& h_rep, const 
 hipError_t launch_adj_step(const RepInfo* d_rep, const RepInfo& h_rep, const double* state,
                            const double* mu_next, double* mu, double* dens, double* gf,
                            double* gs, const double* adjfield, int field, int64_t t,
-                           double* tpart, double* theta_acc, hipStream_t s);
+                           double* tpart, hipStream_t s);
+// sum of the per-block parameter partials of a reverse sweep into theta_acc
+hipError_t launch_adj_theta(const RepInfo& h_rep, const double* tpart, double* theta_acc,
+                            hipStream_t s);
 hipError_t launch_adj_misfit(const RepInfo* d_rep, const RepInfo& h_rep, const double2* tw,
                              const double* acc, const double* target, const double* weight,
                              double* Wq, double2* mean, double* Jpart, int field, double nsamp,
@@ -130,6 +133,6 @@ hipError_t launch_adj_pmisfit(const RepInfo* d_rep, const RepInfo& h_rep, const 
                               double* lam, double* J, hipStream_t s);
 hipError_t launch_adj_psample(const RepInfo* d_rep, const RepInfo& h_rep, const double* dens,
                               const double* lam, double* adjfield, double* tpart,
-                              double* theta_acc, hipStream_t s);
+                              hipStream_t s);
 
 }  // namespace fnlb

@@ -21,8 +21,9 @@
 //     whose force reads its densities (ghost rows fold onto the wall row) and
 //     pushes the adjoint of each pre-collision population back to the stored
 //     element it was pulled from.
-//  4. k_adj_theta: fixed-order (strided, then tree) sum of the per-block
-//     parameter partials.
+//  4. k_adj_theta, once after the reverse sweep: fixed-order (strided, then
+//     tree) sum of the per-block parameter partials, which each block of
+//     k_adj_local (and of k_adj_psample) adds to over the steps in order.
 // The structure-factor term of a sample step is dJ/d dphi(r) =
 // (Lx Lz)^{-1/2} Re sum_{q in half spectrum} G(q) e^{+i q.r} with
 // G(q) = (2 w_q (S(q) - S*(q))) * 2 (Phi(q) - <Phi(q)>) / n, evaluated with
@@ -352,10 +353,10 @@ __global__ __launch_bounds__(256) void k_adj_local(const AdjArgs a) {
   const double bs = block_sum(th_s, sh);
   const double bd = block_sum(th_d, sh);
   const double bg = block_sum(th_g, sh);
-  if (threadIdx.x == 0) {
-    a.tpart[3 * blockIdx.x + 0] = bs;
-    a.tpart[3 * blockIdx.x + 1] = bd;
-    a.tpart[3 * blockIdx.x + 2] = bg;
+  if (threadIdx.x == 0) {  // running partials of this block over the reverse sweep
+    a.tpart[3 * blockIdx.x + 0] += bs;
+    a.tpart[3 * blockIdx.x + 1] += bd;
+    a.tpart[3 * blockIdx.x + 2] += bg;
   }
 }
 
@@ -730,11 +731,7 @@ __global__ void k_adj_psample(const RepInfo* rep, const double* dens, const doub
     gpart = lam0 * (0.25 * (rA * sB + rB * sA) - R.rho0 * R.rho0 / 12.0);
   }
   const double b = block_sum(gpart, sh);
-  if (threadIdx.x == 0) {
-    tpart[3 * blockIdx.x + 0] = 0.0;
-    tpart[3 * blockIdx.x + 1] = 0.0;
-    tpart[3 * blockIdx.x + 2] = b;
-  }
+  if (threadIdx.x == 0) tpart[3 * blockIdx.x + 2] += b;  // running G partial
 }
 
 __global__ void k_sum(const double* parts, int n, double* out) {
@@ -756,14 +753,19 @@ inline dim3 node_grid(int n) { return dim3((unsigned)((n + kNodeBlock - 1) / kNo
 hipError_t launch_adj_step(const RepInfo* d_rep, const RepInfo& h_rep, const double* state,
                            const double* mu_next, double* mu, double* dens, double* gf,
                            double* gs, const double* adjfield, int field, int64_t t,
-                           double* tpart, double* theta_acc, hipStream_t s) {
+                           double* tpart, hipStream_t s) {
   AdjArgs a{d_rep, state, mu_next, mu, dens, gf, gs, adjfield, field, t, tpart};
   const int N = h_rep.Lx * h_rep.Lz;
   const dim3 g = node_grid(N);
   hipLaunchKernelGGL(k_adj_local, g, dim3(kNodeBlock), 0, s, a);
   hipLaunchKernelGGL(k_adj_gather, g, dim3(kNodeBlock), 0, s, a);
-  hipLaunchKernelGGL(k_adj_theta, dim3(1), dim3(256), 0, s, (const double*)tpart, (int)g.x,
-                     theta_acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_theta(const RepInfo& h_rep, const double* tpart, double* theta_acc,
+                            hipStream_t s) {
+  const int nblk = (int)node_grid(h_rep.Lx * h_rep.Lz).x;
+  hipLaunchKernelGGL(k_adj_theta, dim3(1), dim3(256), 0, s, tpart, nblk, theta_acc);
   return hipGetLastError();
 }
 
@@ -778,12 +780,10 @@ hipError_t launch_adj_pmisfit(const RepInfo* d_rep, const RepInfo& h_rep, const 
 
 hipError_t launch_adj_psample(const RepInfo* d_rep, const RepInfo& h_rep, const double* dens,
                               const double* lam, double* adjfield, double* tpart,
-                              double* theta_acc, hipStream_t s) {
+                              hipStream_t s) {
   const int N = h_rep.Lx * h_rep.Lz;
   const dim3 g = node_grid(N);
   hipLaunchKernelGGL(k_adj_psample, g, dim3(kNodeBlock), 0, s, d_rep, dens, lam, adjfield, tpart);
-  hipLaunchKernelGGL(k_adj_theta, dim3(1), dim3(256), 0, s, (const double*)tpart, (int)g.x,
-                     theta_acc);
   return hipGetLastError();
 }
 
