@@ -42,3 +42,42 @@ def test_nonequilibrium_spectrum_follows_q_minus_4(F):
     assert 0.97 < level < 1.08, level
     # statistical error of the band well below the effect tested
     assert np.median(r.S_c_err[band] / r.S_c[band]) < 0.05
+
+
+def test_equilibrium_spectrum_flat(F):
+    """Sec. IV.A, Eq. (32): at grad c0 = 0 the concentration structure factor is
+    flat at the FDT level 3 kT c(1-c) / rho = 3kT/4, here with the non-ideal
+    coupling on (the a_* correction keeps S_c ideal) and FP32-deviation
+    storage."""
+    import workloads as W
+    reps = [W.Replica(Lx=128, Lz=32, grad_c0=0.0, kT=1e-5, G=0.5, seed=300 + i)
+            for i in range(16)]
+    say("case: equilibrium spectra 16 x (128x32), G = 0.5, fp32-dev")
+    lat = F.Lattice(reps, precision=F.FP32_DEV, sample_every=20)
+    lat.step(20000)
+    lat.reset_accumulators()
+    lat.step(60000)
+    S = np.mean([lat.structure_factor(i, F.FIELD_C) for i in range(len(reps))], axis=0)
+    S = S / (0.75 * 1e-5)
+    band = S[:, 1:]
+    say(f"S_c / S_eq: band {band.mean():.4f}, k_x means {band.mean(axis=0).min():.3f}.."
+        f"{band.mean(axis=0).max():.3f}")
+    assert abs(band.mean() - 1.0) < 0.02
+    assert np.all(np.abs(band.mean(axis=0) - 1.0) < 0.1)
+    lat.close()
+
+
+def test_mass_conserved_per_species(F):
+    """Each species' total mass is invariant (Eq. (6): the collision conserves
+    rho^S, streaming and bounce-back move populations), here over 2000 FP64
+    steps of a non-ideal, forced, fluctuating 256 x 128 lattice."""
+    import workloads as W
+    rep = W.Replica(Lx=256, Lz=128, grad_c0=1e-3, kT=1e-5, G=0.5, tau_s=0.7, tau_d=0.8, seed=9)
+    say("case: mass conservation 256x128 fp64, 2000 steps")
+    lat = F.Lattice([rep], precision=F.FP64, sample_every=10)
+    m0 = lat.read_populations(0).sum(axis=(1, 2, 3))
+    lat.step(2000)
+    m1 = lat.read_populations(0).sum(axis=(1, 2, 3))
+    say(f"relative mass change per species: {np.abs(m1 - m0) / m0}")
+    assert np.all(np.abs(m1 - m0) <= 1e-11 * m0)
+    lat.close()
