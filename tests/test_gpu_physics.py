@@ -81,3 +81,43 @@ def test_mass_conserved_per_species(F):
     say(f"relative mass change per species: {np.abs(m1 - m0) / m0}")
     assert np.all(np.abs(m1 - m0) <= 1e-11 * m0)
     lat.close()
+
+
+def _row_concentration(f):
+    rA = f[0].sum(axis=0).mean(axis=1)
+    rB = f[1].sum(axis=0).mean(axis=1)
+    return rA / (rA + rB)
+
+
+def test_noise_free_relaxation_to_the_imposed_profile(F):
+    """Noise-free relaxation (Sec. III.A with the forcing of reading R1): from
+    a uniform c = 1/2 at rest, the profile relaxes to c_0(z) = 1/2 + z grad_c0,
+    its slowest mode (a half cosine between the walls, Neumann) decaying at
+    D (pi/L)^2 with D = (tau_d - 1/2)/3; the imposed profile is an exact fixed
+    point, so after many relaxation times it is reached to rounding."""
+    import workloads as W
+    L, grad, tau_d = 32, 5e-3, 1.0
+    rep = W.Replica(Lx=16, Lz=L, grad_c0=grad, kT=0.0, G=0.0, tau_d=tau_d, seed=1)
+    say("case: noise-free relaxation 16x32 fp64")
+    lat = F.Lattice([rep], precision=F.FP64, sample_every=0)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    f = np.zeros((2, 9, L, 16))
+    f[:, :, :, :] = 0.5 * w[None, :, None, None]
+    lat.write_populations(0, f)
+    z = np.arange(L) - (L - 1) / 2.0
+    c0 = 0.5 + grad * z
+    mode = np.cos(np.pi * (np.arange(L) + 0.5) / L)  # slowest Neumann mode
+    amps = []
+    for n in (300, 300):
+        lat.step(n)
+        dc = _row_concentration(lat.read_populations(0)) - c0
+        amps.append(dc @ mode)
+    D = (tau_d - 0.5) / 3.0
+    rate = np.log(amps[0] / amps[1]) / 300
+    say(f"decay rate {rate:.6e} vs D (pi/L)^2 = {D * (np.pi / L) ** 2:.6e}")
+    assert abs(rate / (D * (np.pi / L) ** 2) - 1) < 0.01
+    lat.step(40000)
+    dc = _row_concentration(lat.read_populations(0)) - c0
+    say(f"max |c - c0| after 40600 steps: {np.abs(dc).max():.2e}")
+    assert np.abs(dc).max() < 1e-12
+    lat.close()
