@@ -175,6 +175,7 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
     R.state_off = state_elems;
     state_elems += 18 * R.plane;
     const int nkx = p.Lx / 2 + 1;
+    field_d = (field_d + 31) / 32 * 32;  // 256-byte aligned (paired loads of the row pass)
     R.field_off = field_d;
     field_d += (int64_t)nf * p.Lz * p.Lx;
     R.spec_off = spec_c;

@@ -106,48 +106,76 @@ __global__ __launch_bounds__(256) void k_row_transform(const RepInfo* reps, cons
   };
   double psum = 0.0;
   bool bad = false;
-  if (live) {
+  // The sampled field(s) of node x from its 3 x 3 stencil of density
+  // deviations (W, C, E of the rows below, at and above) of both species; c is
+  // the node's byte offset (for the momenta).
+  struct Stencil {
+    double D, DW, DE, C, W, E, U, UW, UE;
+  };
+  auto eval = [&](int x, uint32_t c, const Stencil& A, const Stencil& B) {
+    const double rhoA = rAj + A.C, rhoB = rBj + B.C;
+    const double rho = rhoA + rhoB;
+    double2 v;
+    if (pair == 0) {
+      const double drho = A.C + B.C;
+      const double dc = (A.C - c0 * drho) / rho;
+      const double sA = sAref + (1.0 / 9.0) * ((A.E + A.W) + (A.U + A.D)) +
+                        (1.0 / 18.0) * ((A.UE + A.UW) + (A.DE + A.DW));
+      const double sB = sBref + (1.0 / 9.0) * ((B.E + B.W) + (B.U + B.D)) +
+                        (1.0 / 18.0) * ((B.UE + B.UW) + (B.DE + B.DW));
+      const double dP = drho * (1.0 / 3.0) + G * 0.25 * (rhoA * sB + rhoB * sA) - dPref;
+      psum += dP;
+      bad = bad || !(rhoA > 0.0) || !(rhoB > 0.0) || !(dc + c0 > 0.0) || !(dc + c0 < 1.0) ||
+            !isfinite(dP);
+      v = make_double2(dc, drho);
+    } else {
+      // total force -G (rho^A s^B + rho^B s^A) with s^S = sum_l w_l c_l rho^S(r + c_l)
+      // (the a_* and non-equilibrium parts cancel between the species)
+      const double vAx = (1.0 / 9.0) * (A.E - A.W) + (1.0 / 36.0) * ((A.UE - A.UW) + (A.DE - A.DW));
+      const double vBx = (1.0 / 9.0) * (B.E - B.W) + (1.0 / 36.0) * ((B.UE - B.UW) + (B.DE - B.DW));
+      const double vAz =
+          (1.0 / 9.0) * (A.U - A.D) + (1.0 / 36.0) * ((A.UE + A.UW) - (A.DE + A.DW)) + szref;
+      const double vBz =
+          (1.0 / 9.0) * (B.U - B.D) + (1.0 / 36.0) * ((B.UE + B.UW) - (B.DE + B.DW)) - szref;
+      const double Fx = -G * (rhoA * vBx + rhoB * vAx);
+      const double Fz = -G * (rhoA * vBz + rhoB * vAz);
+      v = make_double2((ld(mX, c) + 0.5 * Fx) / rho, wall ? 0.0 : (ld(mZ, c) + 0.5 * Fz) / rho);
+    }
+    lds[(size_t)r * N + (R.pow2 ? bitrev(x, bits) : x)] = v;
+  };
+  if (live && (N & 1) == 0) {
+    // even rows: a thread takes two neighbouring nodes, reading each row of
+    // each species as one 16-byte pair (aligned: x and the row length are
+    // even) and the pair's two outer neighbours
+    auto ld2 = [](const double* base, uint32_t off) {
+      return *(const double2*)((const char*)base + off);
+    };
+    for (int x = 2 * t2; x < N; x += 2 * gsz) {
+      const uint32_t x8 = 8u * x, xm8 = x == 0 ? 8u * (N - 1) : x8 - 8u,
+                     xq8 = x + 2 == N ? 0u : x8 + 16u;
+      Stencil A0, A1, B0, B1;
+      auto rows = [&](const double* base, Stencil& S0, Stencil& S1) {
+        const double2 mD = ld2(base, oD + x8), mC = ld2(base, oC + x8), mU = ld2(base, oU + x8);
+        const double lD = ld(base, oD + xm8), lC = ld(base, oC + xm8), lU = ld(base, oU + xm8);
+        const double rD = ld(base, oD + xq8), rC = ld(base, oC + xq8), rU = ld(base, oU + xq8);
+        S0 = Stencil{mD.x, lD, mD.y, mC.x, lC, mC.y, mU.x, lU, mU.y};
+        S1 = Stencil{mD.y, mD.x, rD, mC.y, mC.x, rC, mU.y, mU.x, rU};
+      };
+      rows(dA, A0, A1);
+      rows(dB, B0, B1);
+      eval(x, oC + x8, A0, B0);
+      eval(x + 1, oC + x8 + 8u, A1, B1);
+    }
+  } else if (live) {
     for (int x = t2; x < N; x += gsz) {
       const uint32_t x8 = 8u * x, xm8 = x == 0 ? 8u * (N - 1) : x8 - 8u,
                      xp8 = x == N - 1 ? 0u : x8 + 8u;
-      const uint32_t c = oC + x8, cW = oC + xm8, cE = oC + xp8;
-      const uint32_t u = oU + x8, uW = oU + xm8, uE = oU + xp8;
-      const uint32_t d = oD + x8, dW = oD + xm8, dE = oD + xp8;
-      const double aC = ld(dA, c), aW = ld(dA, cW), aE = ld(dA, cE), aU = ld(dA, u),
-                   aUW = ld(dA, uW), aUE = ld(dA, uE), aD = ld(dA, d), aDW = ld(dA, dW),
-                   aDE = ld(dA, dE);
-      const double bC = ld(dB, c), bW = ld(dB, cW), bE = ld(dB, cE), bU = ld(dB, u),
-                   bUW = ld(dB, uW), bUE = ld(dB, uE), bD = ld(dB, d), bDW = ld(dB, dW),
-                   bDE = ld(dB, dE);
-      const double rhoA = rAj + aC, rhoB = rBj + bC;
-      const double rho = rhoA + rhoB;
-      double2 v;
-      if (pair == 0) {
-        const double drho = aC + bC;
-        const double dc = (aC - c0 * drho) / rho;
-        const double sA = sAref + (1.0 / 9.0) * ((aE + aW) + (aU + aD)) +
-                          (1.0 / 18.0) * ((aUE + aUW) + (aDE + aDW));
-        const double sB = sBref + (1.0 / 9.0) * ((bE + bW) + (bU + bD)) +
-                          (1.0 / 18.0) * ((bUE + bUW) + (bDE + bDW));
-        const double dP = drho * (1.0 / 3.0) + G * 0.25 * (rhoA * sB + rhoB * sA) - dPref;
-        psum += dP;
-        bad = bad || !(rhoA > 0.0) || !(rhoB > 0.0) || !(dc + c0 > 0.0) || !(dc + c0 < 1.0) ||
-              !isfinite(dP);
-        v = make_double2(dc, drho);
-      } else {
-        // total force -G (rho^A s^B + rho^B s^A) with s^S = sum_l w_l c_l rho^S(r + c_l)
-        // (the a_* and non-equilibrium parts cancel between the species)
-        const double vAx = (1.0 / 9.0) * (aE - aW) + (1.0 / 36.0) * ((aUE - aUW) + (aDE - aDW));
-        const double vBx = (1.0 / 9.0) * (bE - bW) + (1.0 / 36.0) * ((bUE - bUW) + (bDE - bDW));
-        const double vAz =
-            (1.0 / 9.0) * (aU - aD) + (1.0 / 36.0) * ((aUE + aUW) - (aDE + aDW)) + szref;
-        const double vBz =
-            (1.0 / 9.0) * (bU - bD) + (1.0 / 36.0) * ((bUE + bUW) - (bDE + bDW)) - szref;
-        const double Fx = -G * (rhoA * vBx + rhoB * vAx);
-        const double Fz = -G * (rhoA * vBz + rhoB * vAz);
-        v = make_double2((ld(mX, c) + 0.5 * Fx) / rho, wall ? 0.0 : (ld(mZ, c) + 0.5 * Fz) / rho);
-      }
-      lds[(size_t)r * N + (R.pow2 ? bitrev(x, bits) : x)] = v;
+      auto row3 = [&](const double* base) {
+        return Stencil{ld(base, oD + x8), ld(base, oD + xm8), ld(base, oD + xp8),
+                       ld(base, oC + x8), ld(base, oC + xm8), ld(base, oC + xp8),
+                       ld(base, oU + x8), ld(base, oU + xm8), ld(base, oU + xp8)};
+      };
+      eval(x, oC + x8, row3(dA), row3(dB));
     }
   }
   if (pair == 0) {
