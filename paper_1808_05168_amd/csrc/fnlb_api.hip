@@ -349,11 +349,8 @@ hipError_t observe(fnlb_handle* h, hipStream_t s, double* acc = nullptr) {
                                       P.max_row_lds, h->d_fields(), h->d_spec(), h->d_tw(),
                                       h->d_ppart(), h->d_watchdog(), s);
   if (e != hipSuccess) return e;
-  e = launch_col_transform(h->d_reps(), h->d_cols(), (int)P.cols.size(), P.max_col_lds,
-                           h->d_spec(), acc, h->d_tw(), s);
-  if (e != hipSuccess) return e;
-  return launch_pressure_reduce(h->d_reps(), (int)P.info.size(), P.max_lz, h->d_ppart(), acc,
-                                s);
+  return launch_col_transform(h->d_reps(), h->d_cols(), (int)P.cols.size(), P.max_col_lds,
+                              h->d_spec(), acc, h->d_tw(), h->d_ppart(), s);
 }
 
 void drop_graphs(fnlb_handle* h) {

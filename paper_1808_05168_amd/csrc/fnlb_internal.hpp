@@ -100,11 +100,10 @@ hipError_t launch_row_transform(const RepInfo* reps, const RowRef* rows, int n_r
                                 int n_pairs, int max_row_lds, const double* fields, double2* spec,
                                 const double2* tw, double* ppart, int32_t* watchdog,
                                 hipStream_t stream);
+// (also reduces each replica's pressure row sums in ppart)
 hipError_t launch_col_transform(const RepInfo* reps, const ColRef* cols, int n_cols,
                                 int max_lds_cols, const double2* spec, double* acc,
-                                const double2* tw, hipStream_t stream);
-hipError_t launch_pressure_reduce(const RepInfo* reps, int n_rep, int max_lz,
-                                  const double* ppart, double* acc, hipStream_t stream);
+                                const double2* tw, const double* ppart, hipStream_t stream);
 hipError_t launch_advance_time(int64_t* t_base, int64_t dt, hipStream_t stream);
 
 // Adjoint of the step (single replica, FP64 storage); see k_adjoint.hip.

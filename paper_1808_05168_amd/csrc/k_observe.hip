@@ -240,11 +240,45 @@ __global__ __launch_bounds__(256) void k_row_transform(const RepInfo* reps, cons
   }
 }
 
+// Pressure of a sample for one replica, by one block: the row sums go into the
+// profile (row means), then a fixed-shape tree over the rows gives the spatial
+// mean.  Layout of the replica's block: {sum, sum2, profile[Lz]}.  rows: LDS
+// scratch of at least the next power of two >= Lz doubles.
+__device__ void pressure_reduce(const RepInfo& R, const double* ppart, double* acc,
+                                double* rows) {
+  const int Lz = R.Lz;
+  const double* pp = ppart + R.ppart_off;  // row sums of P - P_ref
+  double* pa = acc + R.pacc_off;
+  int P2 = 1;
+  while (P2 < Lz) P2 <<= 1;
+  for (int j = threadIdx.x; j < P2; j += blockDim.x) {
+    double s = 0.0;
+    if (j < Lz) {
+      s = pp[j];
+      pa[2 + j] += s / (double)R.Lx;
+    }
+    rows[j] = s;
+  }
+  for (int h = P2 >> 1; h >= 1; h >>= 1) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < h; j += blockDim.x) rows[j] += rows[j + h];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double mean = rows[0] / ((double)R.Lx * (double)Lz);
+    pa[0] += mean;
+    pa[1] += mean * mean;
+  }
+}
+
 // Column pass: one block per (replica, field, tile of 2^ltile k_x columns).
+// The block of the first tile of the first field also reduces the replica's
+// pressure (the row pass has written all row sums).
 // LDS: the tile's columns, then (power-of-two columns) the M/2 twiddles.
 __global__ __launch_bounds__(256) void k_col_transform(const RepInfo* reps, const ColRef* cols,
                                                        const double2* spec, double* acc,
-                                                       const double2* tw_base) {
+                                                       const double2* tw_base,
+                                                       const double* ppart) {
   extern __shared__ double2 lds[];
   const ColRef cr = cols[blockIdx.x];
   const RepInfo& R = reps[cr.rep];
@@ -348,35 +382,9 @@ __global__ __launch_bounds__(256) void k_col_transform(const RepInfo* reps, cons
       aim[o] += im;
     }
   }
-}
-
-// Pressure: one block per replica.  Row means into the profile, then a
-// fixed-shape tree over rows for the spatial mean.  Layout of the replica's block: {sum, sum2, profile[Lz]}.
-__global__ void k_pressure_reduce(const RepInfo* reps, const double* ppart, double* acc) {
-  extern __shared__ double rows[];
-  const RepInfo& R = reps[blockIdx.x];
-  const int Lz = R.Lz;
-  const double* pp = ppart + R.ppart_off;  // row sums of P - P_ref
-  double* pa = acc + R.pacc_off;
-  int P2 = 1;
-  while (P2 < Lz) P2 <<= 1;
-  for (int j = threadIdx.x; j < P2; j += blockDim.x) {
-    double s = 0.0;
-    if (j < Lz) {
-      s = pp[j];
-      pa[2 + j] += s / (double)R.Lx;
-    }
-    rows[j] = s;
-  }
-  for (int h = P2 >> 1; h >= 1; h >>= 1) {
-    __syncthreads();
-    for (int j = threadIdx.x; j < h; j += blockDim.x) rows[j] += rows[j + h];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double mean = rows[0] / ((double)R.Lx * (double)Lz);
-    pa[0] += mean;
-    pa[1] += mean * mean;
+  if (cr.field == 0 && cr.kx0 == 0) {
+    __syncthreads();  // the tile's LDS is free again (it holds >= Lz double2)
+    pressure_reduce(R, ppart, acc, (double*)lds);
   }
 }
 
@@ -418,20 +426,11 @@ hipError_t launch_row_transform(const RepInfo* reps, const RowRef* rows, int n_r
 
 hipError_t launch_col_transform(const RepInfo* reps, const ColRef* cols, int n_cols,
                                 int max_lds_cols, const double2* spec, double* acc,
-                                const double2* tw, hipStream_t stream) {
+                                const double2* tw, const double* ppart, hipStream_t stream) {
   if (n_cols <= 0) return hipSuccess;
   const size_t lds = (size_t)max_lds_cols * sizeof(double2);
   hipLaunchKernelGGL(k_col_transform, dim3(n_cols), dim3(256), lds, stream, reps, cols, spec,
-                     acc, tw);
-  return hipGetLastError();
-}
-
-hipError_t launch_pressure_reduce(const RepInfo* reps, int n_rep, int max_lz, const double* ppart,
-                                  double* acc, hipStream_t stream) {
-  int P2 = 1;
-  while (P2 < max_lz) P2 <<= 1;
-  hipLaunchKernelGGL(k_pressure_reduce, dim3(n_rep), dim3(256), (size_t)P2 * sizeof(double),
-                     stream, reps, ppart, acc);
+                     acc, tw, ppart);
   return hipGetLastError();
 }
 
