@@ -372,13 +372,25 @@ def main():
         return
     if args.summarize_trace:
         d, name, title = args.summarize_trace
-        summarize_trace(d, os.path.join(ROOT, "profiles", name + ".md"), title,
-                        args.profile_command)
+        cmd = args.profile_command or (
+            "rocprofv3 --kernel-trace --stats --output-format csv -d <out>/pa -o run -- "
+            "python3 bench.py --adjoint-only\n"
+            f"python3 bench.py --summarize-trace <out>/pa {name} \"{title}\"")
+        summarize_trace(d, os.path.join(ROOT, "profiles", name + ".md"), title, cmd)
         return
 
     if args.summarize_profile:
         out = os.path.join(ROOT, "profiles", "k_step_batched96_fp32dev.md")
-        summarize_profile(*args.summarize_profile, out, args.profile_command)
+        leg = "--no-cpu-baseline --no-compare --no-adjoint --chunk-rows 8"
+        cmd = args.profile_command or "\n".join([
+            "rocprofv3 --kernel-trace --stats --output-format csv -d <out>/pt -o run -- "
+            f"python3 bench.py --steps 200 --warmup 20 {leg}",
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pf -o run -- "
+            f"python3 bench.py --steps 10 --warmup 2 {leg} --copy-calibration-mb 1024",
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/pw -o run -- "
+            f"python3 bench.py --steps 10 --warmup 2 {leg} --copy-calibration-mb 1024",
+            "python3 bench.py --summarize-profile <out>/pt <out>/pf <out>/pw"])
+        summarize_profile(*args.summarize_profile, out, cmd)
         return
 
     if args.gpus != 1:
