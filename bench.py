@@ -9,9 +9,16 @@ Default workload (N = 1): the batched ensemble of 96 replicas with L in
 {32, 64, 128, 256}, Lx = 2L, FP32-deviation storage, sampled every 10 steps.
 Printed as one JSON line:
   value        MLUPS over the whole batch (one update = both species at one node)
+  value_without_sampling
+               the same batch with sampling off
   roofline     the step kernel alone (sampling off), HBM-bound: algorithmic
-               bytes (18 reads + 18 writes per node) / measured launch time
-  compare      plain FP64 storage on the single 512 x 256 lattice, same timing
+               bytes (18 reads + 18 writes per node) / measured launch time;
+               measured HBM bytes per launch from the committed counter record
+               (ensemble only, while the kernel sources match it); a plain
+               device-copy ceiling measured in the same run
+  compare      plain FP64 storage on the same batch and on the single 512 x 256
+               lattice, and the agreement of the two storage forms
+  adjoint      one gradient of the S(q) misfit on 256 x 128 (FP64, 2000 steps)
   cpu_baseline the FP64 CPU oracle on a bounded sample of the same workload
 """
 from __future__ import annotations
@@ -456,7 +463,8 @@ def main():
     t_launch = ms_r / 1e3 / nr
     achieved = bytes_per_node * nodes / t_launch / 1e9
     del lat_r
-    traffic = _traffic_from_profiles()
+    # the counter record is of the ensemble's step kernel
+    traffic = _traffic_from_profiles() if args.workload == "batched96" else None
     copy_gbs = copy_ceiling_gbs()
 
     out = {
