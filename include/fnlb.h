@@ -116,7 +116,10 @@ int fnlb_bytes_required(const fnlb_replica_params* reps, int32_t n_rep,
  * sets time t = 0, initialises every replica to the state of rest on the
  * imposed profile (f^S_l = w_l rho_0^S(z), rho_0^A = rho_bar c_0(z),
  * rho_0^B = rho_bar (1 - c_0(z)), U = 0; Fig. 1) and clears the accumulators.
- * hip_stream is a hipStream_t (NULL = default stream).  Asynchronous. */
+ * hip_stream is a hipStream_t (NULL = default stream).  Synchronises that
+ * stream before returning (the host-side tables it uploads are temporary).
+ * Errors: FNLB_EINVAL (parameters, null or unaligned buffers), FNLB_ENOMEM
+ * (a buffer smaller than fnlb_bytes_required), FNLB_EDEVICE. */
 int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep,
               const fnlb_options* options, void* d_state, size_t state_bytes,
               void* d_accum, size_t accum_bytes, void* d_work,
