@@ -255,7 +255,10 @@ int fnlb_pressure_misfit_gradient(fnlb_handle* h, const double* P_target, const 
                                   int64_t horizon, int32_t ckpt_every, void* d_adj,
                                   size_t adj_bytes, double* J, double* grad);
 
-/* Frees the handle's host metadata.  Caller buffers are untouched. */
+/* Frees the handle's host metadata and its streams, events and captured
+ * graphs.  Call it once the work enqueued for the handle has finished (for
+ * example after a read call, which synchronises).  Caller buffers are
+ * untouched. */
 int fnlb_destroy(fnlb_handle* h);
 
 /* Static message for an error code. */
