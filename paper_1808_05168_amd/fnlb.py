@@ -161,6 +161,9 @@ class Lattice:
     # -- lifetime --
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
+            # finish the handle's work before its graphs go and torch may
+            # hand its buffers to someone else
+            self.stream.synchronize()
             self._lib.fnlb_destroy(self._h)
             self._h = ctypes.c_void_p()
 
