@@ -200,6 +200,17 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   // - rho_ref^A(j+1)) = -w_l rho_bar grad_c0; species B has the opposite sign
   const Real shA1 = (Real)(-rAs / 9.0), shA5 = (Real)(-rAs / 36.0);
 
+  // noise amplitudes of the moments 1 and 3..8, read once before the row loop
+  // (reloading them per row cost 5% of the step): those at the reference
+  // densities, or with local noise the factors that multiply the square roots
+  // of the local densities
+  const bool loc = (flags & FNLB_NOISE_LOC) != 0;
+  const double* sgA = loc ? R.sig_base : R.sig[0];
+  const double* sgB = loc ? R.sig_base : R.sig[1];
+  const Real sig0d = (Real)sgA[1];
+  const Real sig0[5] = {(Real)sgA[3], (Real)sgA[4], (Real)sgA[5], (Real)sgA[6], (Real)sgA[8]};
+  const Real sig1[5] = {(Real)sgB[3], (Real)sgB[4], (Real)sgB[5], (Real)sgB[6], (Real)sgB[8]};
+
   const int j0 = it.j0, j1 = it.j1;
   // Rows whose densities the item needs: its own and one more on each side
   // inside the walls.  The item marches from jfirst in direction dir (items
@@ -340,7 +351,13 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
       const Real rhoA = (Real)rAj + (Real)dAc;
       const Real rhoB = (Real)(rho0 - rAj) + (Real)dBc;
       const Real rho = rhoA + rhoB;
-      const Real inv_rho = (Real)1 / rho;
+      // FP32: the hardware reciprocal (1 ulp) instead of a correctly rounded
+      // division sequence
+      Real inv_rho;
+      if constexpr (sizeof(Real) == 4)
+        inv_rho = __builtin_amdgcn_rcpf(rho);
+      else
+        inv_rho = (Real)1 / rho;
 
       // s^S = sum_l w_l c_l rho^S(r + c_l) (deviation part + reference part)
       const Real sAx = w1 * (Real)(aEc - aWc) + w5 * (Real)((aEp - aWp) + (aEm - aWm));
@@ -401,25 +418,25 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
       const Real Uz = (jAz + jBz + (Real)0.5 * (FAz + FBz)) * inv_rho;
       const Real Uxx = Ux * Ux, Uzz = Uz * Uz, Uxz = Ux * Uz;
 
-      // noise amplitudes (reference densities, or local ones)
-      Real sd = (Real)R.sig[0][1];
-      Real sA3 = (Real)R.sig[0][3], sA4 = (Real)R.sig[0][4], sA5 = (Real)R.sig[0][5],
-           sA6 = (Real)R.sig[0][6], sA8 = (Real)R.sig[0][8];
-      Real sB3 = (Real)R.sig[1][3], sB4 = (Real)R.sig[1][4], sB5 = (Real)R.sig[1][5],
-           sB6 = (Real)R.sig[1][6], sB8 = (Real)R.sig[1][8];
-      if (flags & FNLB_NOISE_LOC) {
-        const Real qa = sqrt(rhoA), qb = sqrt(rhoB);
-        sd = (Real)R.sig_base[1] * sqrt(rhoA * rhoB * inv_rho);
-        sA3 = (Real)R.sig_base[3] * qa;
-        sA4 = (Real)R.sig_base[4] * qa;
-        sA5 = (Real)R.sig_base[5] * qa;
-        sA6 = (Real)R.sig_base[6] * qa;
-        sA8 = (Real)R.sig_base[8] * qa;
-        sB3 = (Real)R.sig_base[3] * qb;
-        sB4 = (Real)R.sig_base[4] * qb;
-        sB5 = (Real)R.sig_base[5] * qb;
-        sB6 = (Real)R.sig_base[6] * qb;
-        sB8 = (Real)R.sig_base[8] * qb;
+      // noise amplitudes: at the reference densities, or with local noise the
+      // base amplitudes times the square roots of the local densities, applied
+      // to the normals (the amplitudes themselves stay loop-invariant)
+      const Real sd = sig0d;
+      const Real sA3 = sig0[0], sA4 = sig0[1], sA5 = sig0[2], sA6 = sig0[3], sA8 = sig0[4];
+      const Real sB3 = sig1[0], sB4 = sig1[1], sB5 = sig1[2], sB6 = sig1[3], sB8 = sig1[4];
+      if (loc) {
+        const Real qa = sqrt(rhoA), qb = sqrt(rhoB), qd = sqrt(rhoA * rhoB * inv_rho);
+        gA0[0] *= qd;
+        gA0[1] *= qd;
+        gA0[2] *= qa;
+        gA0[3] *= qa;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          gA1[k] *= qa;
+          gB0[k] *= qb;
+        }
+        gB1[0] *= qb;
+        gB1[1] *= qb;
       }
       const Real xi1 = sd * gA0[0], xi2 = sd * gA0[1];
 
