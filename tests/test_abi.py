@@ -63,6 +63,13 @@ def test_bytes_required_and_validation(lib):
         F.bytes_required([W.parity_small()], precision=7)
     with pytest.raises(F.FnlbError):
         F.bytes_required([W.parity_small()], flags=64)
+    # no replicas, negative sampling interval or row-range length
+    for reps, kw in (([], {}), ([W.parity_small()], dict(sample_every=-1)),
+                     ([W.parity_small()], dict(chunk_rows=-2))):
+        with pytest.raises(F.FnlbError):
+            F.bytes_required(reps, **kw)
+    # a row range longer than the lattice is one work item per segment column
+    assert F.bytes_required([W.parity_small()], chunk_rows=1000)[0] == s
 
 
 def test_init_rejects_null_and_small_buffers(lib):
