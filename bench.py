@@ -356,6 +356,10 @@ def main():
                     help="first run a plain device copy of this size (3 times), the "
                          "reference for scaling HBM byte counters")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch every step directly instead of replaying the captured "
+                         "sampling period (a kernel trace then times the transforms of a "
+                         "sample without the steps running beside them)")
     ap.add_argument("--chunk-rows", type=int, default=0,
                     help="fixed rows per work item (skips the autotuner); profiles use it "
                          "so that every pass times the same launch configuration")
@@ -379,10 +383,15 @@ def main():
         return
     if args.summarize_trace:
         d, name, title = args.summarize_trace
+        # the run each committed trace summary is taken from
+        runs = {"sample_passes_batched96_fp32dev":
+                ("ps", "--steps 300 --warmup 20 --no-cpu-baseline --no-compare --no-adjoint "
+                       "--chunk-rows 8 --no-graph")}
+        sub, run_args = runs.get(name, ("pa", "--adjoint-only"))
         cmd = args.profile_command or (
-            "rocprofv3 --kernel-trace --stats --output-format csv -d <out>/pa -o run -- "
-            "python3 bench.py --adjoint-only\n"
-            f"python3 bench.py --summarize-trace <out>/pa {name} \"{title}\"")
+            f"rocprofv3 --kernel-trace --stats --output-format csv -d <out>/{sub} -o run -- "
+            f"python3 bench.py {run_args}\n"
+            f"python3 bench.py --summarize-trace <out>/{sub} {name} \"{title}\"")
         summarize_trace(d, os.path.join(ROOT, "profiles", name + ".md"), title, cmd)
         return
 
@@ -441,7 +450,9 @@ def main():
     store_bytes = 4 if prec == F.FP32_DEV else 8
     bytes_per_node = 36 * store_bytes
 
-    lat = F.Lattice(reps, precision=prec, sample_every=every, chunk_rows=args.chunk_rows)
+    flags = F.DEFAULT_FLAGS | (F.NO_GRAPH if args.no_graph else 0)
+    lat = F.Lattice(reps, precision=prec, sample_every=every, flags=flags,
+                    chunk_rows=args.chunk_rows)
     if args.chunk_rows > 0:
         chunk = args.chunk_rows
     else:
@@ -456,7 +467,8 @@ def main():
     mlups = nodes * args.steps / sec / 1e6
 
     # roofline leg: the step kernel alone (no sampling), same batch
-    lat_r = F.Lattice(reps, precision=prec, sample_every=0, chunk_rows=args.chunk_rows)
+    lat_r = F.Lattice(reps, precision=prec, sample_every=0, flags=flags,
+                      chunk_rows=args.chunk_rows)
     lat_r.step(min(args.warmup, 100))
     nr = max(50, min(args.steps, 1000))
     ms_r = _events_time(lat_r, nr)
