@@ -257,6 +257,27 @@ def test_parity_4096x1024_fp32_deviation(F):
     compare_observables(lat, acc, 0, rep, TOL32)
 
 
+def test_parity_batched96_ensemble_fp32_deviation(F):
+    """The 96-replica ensemble in the launch configuration the benchmark times
+    (FP32-deviation storage, autotuned row ranges, sampled every 10 steps):
+    every population of every replica, and the structure-factor and pressure
+    sums of its two samples, against the oracle."""
+    reps = W.batched_ensemble(96)
+    say("case: 96-replica ensemble fp32-dev, autotuned, 21 steps sampled every 10")
+    lat = F.Lattice(reps, precision=F.FP32_DEV, sample_every=10)
+    lat.autotune(5)
+    lat.step(21)
+    worst = 0.0
+    for i, rep in enumerate(reps):
+        f_o, acc = run_oracle(rep, 21, every=10)
+        assert acc.n_samples == 2
+        err = dev_norm(lat.read_populations(i), f_o, rep)
+        worst = max(worst, err)
+        assert err <= TOL32, (i, err)
+        compare_observables(lat, acc, i, rep, TOL32)
+    say(f"  worst population error over the 96 replicas {worst:.3e}")
+
+
 def test_parity_512x256_fp64(F):
     rep = W.single_512x256(grad_c0=5e-4)
     say("case: 512x256 fp64, 40 steps every 10")
