@@ -1,0 +1,101 @@
+"""Host logic of the benchmark: the rocprofv3 summaries it commits and the
+traffic record it reports only while the step-kernel sources match it.
+Synthetic profiler outputs, no GPU."""
+import csv
+import json
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+import workloads as W  # noqa: E402
+
+STEP0 = "void fnlb::(anonymous namespace)::k_step<float, float, 0>(fnlb::StepArgs)"
+STEP1 = "void fnlb::(anonymous namespace)::k_step<float, float, 1>(fnlb::StepArgs)"
+COPY = "__amd_rocclr_copyBuffer"
+
+
+def _write_csv(path, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+
+
+@pytest.fixture
+def profiler_dirs(tmp_path):
+    pt, pf, pw = (tmp_path / d for d in ("pt", "pf", "pw"))
+    for d in (pt, pf, pw):
+        d.mkdir()
+    _write_csv(pt / "run_kernel_stats.csv", [
+        dict(Name=STEP0, Calls=5, AverageNs=1000.0, Percentage=80.0),
+        dict(Name=STEP1, Calls=1, AverageNs=2000.0, Percentage=20.0)])
+
+    def launch(name, start, dur, grid):
+        return dict(Kernel_Name=name, Start_Timestamp=start, End_Timestamp=start + dur,
+                    Grid_Size_X=grid)
+    # a plain step before the last sampling step (excluded), the sampling step,
+    # two plain steps at the timed grid after it (averaged), one at another grid
+    _write_csv(pt / "run_kernel_trace.csv", [
+        launch(STEP0, 100, 5000, 1024), launch(STEP1, 200, 9000, 1024),
+        launch(STEP0, 300, 1000, 1024), launch(STEP0, 400, 3000, 1024),
+        launch(STEP0, 500, 7000, 2048), launch(STEP0, 600, 1000, 2048)][::-1])
+
+    def counter(name, kernel, value, grid=0):
+        return dict(Kernel_Name=kernel, Counter_Name=name, Counter_Value=value, Grid_Size=grid)
+    # the plain 1 GiB copies read half the counter's nominal bytes (so FETCH is
+    # scaled x2) and write all of them (x1); a small copy is ignored
+    _write_csv(pf / "run_counter_collection.csv", [
+        counter("FETCH_SIZE", COPY, 524288.0), counter("FETCH_SIZE", COPY, 524288.0),
+        counter("FETCH_SIZE", COPY, 10.0), counter("FETCH_SIZE", STEP0, 100.0, 1024),
+        counter("FETCH_SIZE", STEP0, 300.0, 1024), counter("FETCH_SIZE", STEP0, 9999.0, 2048)])
+    _write_csv(pw / "run_counter_collection.csv", [
+        counter("WRITE_SIZE", COPY, 1048576.0), counter("WRITE_SIZE", STEP0, 50.0, 1024)])
+    return pt, pf, pw
+
+
+def test_summarize_profile_scales_counters_and_picks_the_roofline_leg(
+        profiler_dirs, tmp_path, monkeypatch):
+    traffic = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_JSON", str(traffic))
+    pt, pf, pw = profiler_dirs
+    md = tmp_path / "summary.md"
+    bench.summarize_profile(str(pt), str(pf), str(pw), str(md), "the commands")
+    d = json.loads(traffic.read_text())
+    assert d["grid"] == 1024
+    assert d["step_avg_us"] == pytest.approx(2.0)  # (1000 + 3000) ns / 2
+    assert d["read_bytes"] == round(200.0 * 2 * 1024)  # mean FETCH x2, in bytes
+    assert d["write_bytes"] == round(50.0 * 1024)
+    assert d["bytes_per_launch"] == d["read_bytes"] + d["write_bytes"]
+    assert d["algorithmic_bytes"] == 144 * sum(r.Lx * r.Lz for r in W.batched_ensemble(96))
+    assert d["source_sha256"] == bench._step_source_hash()
+    text = md.read_text()
+    assert "the commands" in text and "FETCH x2.0000, WRITE x1.0000" in text
+    # the record is reported while the kernel sources match it, and not after
+    assert bench._traffic_from_profiles() == d["bytes_per_launch"]
+    d["source_sha256"] = "0" * 64
+    traffic.write_text(json.dumps(d))
+    assert bench._traffic_from_profiles() is None
+    monkeypatch.setattr(bench, "TRAFFIC_JSON", str(tmp_path / "missing.json"))
+    assert bench._traffic_from_profiles() is None
+
+
+def test_summarize_trace_writes_the_command_and_table(profiler_dirs, tmp_path):
+    pt, _, _ = profiler_dirs
+    md = tmp_path / "trace.md"
+    bench.summarize_trace(str(pt), str(md), "A title", "cmd line 1\ncmd line 2")
+    text = md.read_text().splitlines()
+    assert text[0] == "# A title"
+    assert "cmd line 1" in text and "cmd line 2" in text
+    assert any(line.startswith(f"| {STEP0[:90]} | 5 | 1.0 | 80.00 |") for line in text)
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
