@@ -121,3 +121,37 @@ def test_noise_free_relaxation_to_the_imposed_profile(F):
     say(f"max |c - c0| after 40600 steps: {np.abs(dc).max():.2e}")
     assert np.abs(dc).max() < 1e-12
     lat.close()
+
+
+def test_velocity_spectrum_unchanged_by_the_gradient(F):
+    """Sec. IV.A, Eq. (31): S_U = kT / rho_bar at every q, and a concentration
+    gradient leaves it unchanged.  At G = 0 the total momentum does not see the
+    concentration, so two replicas that differ only in grad c0 (same seed)
+    give the same velocity sums up to rounding, while the concentration
+    spectrum of the graded one rises at small q.  The wall fix is off, so that
+    the wall rows carry the same velocity noise as the bulk (the fix zeroes U_z
+    there)."""
+    import workloads as W
+    kT = 1e-4
+    reps = [W.Replica(Lx=32, Lz=16, grad_c0=g, kT=kT, seed=7) for g in (0.0, 0.02)]
+    say("case: velocity spectra, 32x16 fp64, grad c0 0 and 0.02, same seed")
+    lat = F.Lattice(reps, precision=F.FP64, sample_every=10,
+                    flags=F.ASTAR | F.SAMPLE_VELOCITY)
+    lat.step(1000)
+    lat.reset_accumulators()
+    lat.step(8000)
+    mask = np.ones((16, 17), bool)
+    mask[0, 0] = False
+    for fld in (F.FIELD_UX, F.FIELD_UZ):
+        a, b = lat.read_structure_factor(0, fld), lat.read_structure_factor(1, fld)
+        assert a[3] == b[3] == 800
+        for x, y in zip(a[:3], b[:3]):
+            np.testing.assert_allclose(y, x, rtol=0, atol=1e-9 * np.abs(x).max())
+        S = lat.structure_factor(0, fld) / kT
+        say(f"  field {fld}: S_U rho_bar / kT = {S[mask].mean():.4f}")
+        assert abs(S[mask].mean() - 1.0) < 0.04
+    s0 = lat.structure_factor(0, F.FIELD_C)[1, 1:4].mean()
+    s1 = lat.structure_factor(1, F.FIELD_C)[1, 1:4].mean()
+    say(f"  S_c(k_z = 1, k_x = 1..3): graded / flat = {s1 / s0:.4f}")
+    assert s1 > 1.02 * s0
+    lat.close()
