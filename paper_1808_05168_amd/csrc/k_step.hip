@@ -76,14 +76,17 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   constexpr int kRow = kSeg + 2;
   __shared__ DT ring[4][2][kRow];
   __shared__ Store edge[2][36];  // pulled populations of the two edge columns
-  // With FP32 storage a lane parks the pulled populations of the rows it has
-  // loaded but not yet collided in LDS (two slots, private to the lane).  That
-  // frees the registers to receive the loads of the row after next while the
-  // current row is collided, so a row's loads are in flight for a whole
-  // iteration.  FP64 keeps the row in registers (its LDS share would cost
-  // blocks per compute unit).
-  constexpr bool kStage = sizeof(Store) == 4;
-  __shared__ Store pbuf[kStage ? 2 : 1][18][kStage ? kBlock : 1];
+  // A lane parks the pulled populations of the rows it has loaded but not yet
+  // collided in LDS (slots private to the lane).  That frees the registers to
+  // receive the loads of the row after next while the current row is
+  // collided, so a row's loads are in flight for a whole iteration.  FP32 uses
+  // two slots: the row ahead is parked before the barrier and the current row
+  // read back after it.  FP64 uses one (37 KiB): the lane reads the current
+  // row back at the top of the iteration, before it parks the row ahead; two
+  // slots would cost it one of the two blocks per compute unit its registers
+  // allow.
+  constexpr int kSlots = sizeof(Store) == 4 ? 2 : 1;
+  __shared__ Store pbuf[kSlots][18][kBlock];
 
   // XCD-aware block order: consecutive hardware blocks go to different XCDs,
   // so give each XCD a contiguous range of work items (neighbouring segments
@@ -221,10 +224,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   const int jfirst = dir > 0 ? j0 : j1 - 1;
   auto needed = [&](int jr) { return jr >= lo && jr <= hi; };
   auto stage = [&](int jr, const Store(&o)[18]) {
-    if constexpr (kStage) {
 #pragma unroll
-      for (int q = 0; q < 18; ++q) pbuf[jr & 1][q][tid] = o[q];
-    }
+    for (int q = 0; q < 18; ++q) pbuf[kSlots == 2 ? (jr & 1) : 0][q][tid] = o[q];
   };
   Store cur[18], nxt[18];
   load_pulled(in, link_b, row_b, jfirst, Lz, xb, xmb, xpb, cur);
@@ -247,12 +248,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   }
 
   Store ev = (Store)0;
-  if constexpr (kStage) {
-    // the first row ahead is in flight before the loop
-    if (needed(jfirst + dir)) {
-      load_pulled(in, link_b, row_b, jfirst + dir, Lz, xb, xmb, xpb, nxt);
-      ev = pull_edges(jfirst + dir);
-    }
+  // the first row ahead is in flight before the loop
+  if (needed(jfirst + dir)) {
+    load_pulled(in, link_b, row_b, jfirst + dir, Lz, xb, xmb, xpb, nxt);
+    ev = pull_edges(jfirst + dir);
   }
 
   for (int i = 0; i < j1 - j0; ++i) {
@@ -260,11 +259,9 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     const bool top = (j == Lz - 1), bot = (j == 0);
     const int ja = j + dir;  // the row ahead
     const bool ahead = needed(ja);
-    if constexpr (!kStage) {
-      if (ahead) {
-        load_pulled(in, link_b, row_b, ja, Lz, xb, xmb, xpb, nxt);
-        ev = pull_edges(ja);
-      }
+    if constexpr (kSlots == 1) {
+#pragma unroll
+      for (int q = 0; q < 18; ++q) cur[q] = pbuf[0][q][tid];
     }
 
     // thermal noise of this node: 14 standard normals, drawn while the next
@@ -286,16 +283,14 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
       put_edges(ja, ev);
       stage(ja, nxt);
     }
-    if constexpr (kStage) {
-      // the row after next: its loads run through the barrier and the collision
-      if (needed(ja + dir)) {
-        load_pulled(in, link_b, row_b, ja + dir, Lz, xb, xmb, xpb, nxt);
-        ev = pull_edges(ja + dir);
-      }
+    // the row after next: its loads run through the barrier and the collision
+    if (needed(ja + dir)) {
+      load_pulled(in, link_b, row_b, ja + dir, Lz, xb, xmb, xpb, nxt);
+      ev = pull_edges(ja + dir);
     }
     __syncthreads();
     if (ahead) sum_edges(ja);
-    if constexpr (kStage) {
+    if constexpr (kSlots == 2) {
 #pragma unroll
       for (int q = 0; q < 18; ++q) cur[q] = pbuf[j & 1][q][tid];
     }
@@ -504,11 +499,6 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
         emit(1, dB, -shA1, -shA5);
       }
      }
-    }
-
-    if constexpr (!kStage) {
-#pragma unroll
-      for (int q = 0; q < 18; ++q) cur[q] = nxt[q];
     }
   }
 }
