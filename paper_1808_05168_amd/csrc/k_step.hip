@@ -76,17 +76,12 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   constexpr int kRow = kSeg + 2;
   __shared__ DT ring[4][2][kRow];
   __shared__ Store edge[2][36];  // pulled populations of the two edge columns
-  // A lane parks the pulled populations of the rows it has loaded but not yet
-  // collided in LDS (slots private to the lane).  That frees the registers to
-  // receive the loads of the row after next while the current row is
-  // collided, so a row's loads are in flight for a whole iteration.  FP32 uses
-  // two slots: the row ahead is parked before the barrier and the current row
-  // read back after it.  FP64 uses one (37 KiB): the lane reads the current
-  // row back at the top of the iteration, before it parks the row ahead; two
-  // slots would cost it one of the two blocks per compute unit its registers
-  // allow.
-  constexpr int kSlots = sizeof(Store) == 4 ? 2 : 1;
-  __shared__ Store pbuf[kSlots][18][kBlock];
+  // A lane parks the pulled populations of the row ahead in LDS (a slot
+  // private to the lane) and reads them back at the top of the next iteration.
+  // That frees the registers to receive the loads of the row after next while
+  // the current row is collided, so a row's loads are in flight for a whole
+  // iteration.
+  __shared__ Store pbuf[18][kBlock];
 
   // XCD-aware block order: consecutive hardware blocks go to different XCDs,
   // so give each XCD a contiguous range of work items (neighbouring segments
@@ -223,14 +218,14 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   const int lo = max(j0 - 1, 0), hi = min(j1, Lz - 1);
   const int jfirst = dir > 0 ? j0 : j1 - 1;
   auto needed = [&](int jr) { return jr >= lo && jr <= hi; };
-  auto stage = [&](int jr, const Store(&o)[18]) {
+  auto park = [&](const Store(&o)[18]) {
 #pragma unroll
-    for (int q = 0; q < 18; ++q) pbuf[kSlots == 2 ? (jr & 1) : 0][q][tid] = o[q];
+    for (int q = 0; q < 18; ++q) pbuf[q][tid] = o[q];
   };
   Store cur[18], nxt[18];
   load_pulled(in, link_b, row_b, jfirst, Lz, xb, xmb, xpb, cur);
   put_row(jfirst, cur);
-  stage(jfirst, cur);
+  park(cur);
   if (needed(jfirst - dir)) {  // the row behind the first one
     Store tmp[18];
     load_pulled(in, link_b, row_b, jfirst - dir, Lz, xb, xmb, xpb, tmp);
@@ -259,10 +254,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     const bool top = (j == Lz - 1), bot = (j == 0);
     const int ja = j + dir;  // the row ahead
     const bool ahead = needed(ja);
-    if constexpr (kSlots == 1) {
+    // the populations of this row, parked in the previous iteration (or
+    // before the loop)
 #pragma unroll
-      for (int q = 0; q < 18; ++q) cur[q] = pbuf[0][q][tid];
-    }
+    for (int q = 0; q < 18; ++q) cur[q] = pbuf[q][tid];
 
     // thermal noise of this node: 14 standard normals, drawn while the next
     // row's loads are in flight (species A uses g_0..g_7 from calls 0 and 1,
@@ -281,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     if (ahead) {
       put_row(ja, nxt);
       put_edges(ja, ev);
-      stage(ja, nxt);
+      park(nxt);
     }
     // the row after next: its loads run through the barrier and the collision
     if (needed(ja + dir)) {
@@ -290,10 +285,6 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     }
     __syncthreads();
     if (ahead) sum_edges(ja);
-    if constexpr (kSlots == 2) {
-#pragma unroll
-      for (int q = 0; q < 18; ++q) cur[q] = pbuf[j & 1][q][tid];
-    }
 
     // the 3 x 3 density stencil; ghost rows beyond the walls repeat the wall row
     const int jU = top ? j : j + 1, jD = bot ? j : j - 1;
