@@ -456,7 +456,7 @@ def main():
     if args.chunk_rows > 0:
         chunk = args.chunk_rows
     else:
-        chunk = lat.autotune(20) if not args.no_autotune else 0
+        chunk = lat.autotune(50) if not args.no_autotune else 0
     lat.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

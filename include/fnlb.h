@@ -139,8 +139,9 @@ int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep,
 int fnlb_step(fnlb_handle* h, int64_t n);
 
 /* Chooses the number of rows each work item of the step kernel covers by
- * timing steps_per_trial >= 1 launches of each candidate (1 to 128 rows) and
- * keeps the fastest for this handle and, for the rest of the process, for
+ * timing steps_per_trial >= 1 launches of each candidate (1 to 128 rows),
+ * twice in turn, and keeps the one whose faster round is fastest for this
+ * handle and, for the rest of the process, for
  * any handle with the same precision and set of lattice shapes created with
  * options->chunk_rows = 0.  Trial steps read the current state and write the
  * spare copy, so the state and the time are unchanged.  Synchronises the

@@ -569,30 +569,42 @@ int fnlb_autotune(fnlb_handle* h, int32_t steps_per_trial, int32_t* chunk_rows_o
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
+  // Two rounds over the candidates, each timed by its faster round, so that
+  // neither the order of the trials (clocks still ramping up during the first
+  // ones) nor one disturbed trial decides: neighbouring lengths often differ
+  // by only a few percent.
+  constexpr int kCands = (int)(sizeof(cands) / sizeof(cands[0]));
+  float cand_ms[kCands];
+  for (float& m : cand_ms) m = 1e30f;
+  for (int round = 0; round < 2; ++round)
+    for (int ci = 0; ci < kCands; ++ci) {
+      const int c = cands[ci];
+      if (e != hipSuccess) break;
+      if (c > 2 * max_lz && c != 4) continue;
+      make_items(P, c);
+      e = hipMemcpyAsync(h->d_items(), P.items.data(), P.items.size() * sizeof(Item),
+                         hipMemcpyHostToDevice, h->stream);
+      // trial steps read the current copy and write the spare one: the state
+      // and the time are unchanged
+      StepArgs a = step_args(h, h->t - h->t_dev);
+      for (int w = 0; w < 2 && e == hipSuccess; ++w)
+        e = launch_step(h->opt.precision, kStep, a, h->stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+      for (int k = 0; k < steps_per_trial && e == hipSuccess; ++k)
+        e = launch_step(h->opt.precision, kStep, a, h->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess) cand_ms[ci] = std::min(cand_ms[ci], ms);
+    }
   int best = P.chunk;
   float best_ms = 1e30f;
-  for (int c : cands) {
-    if (e != hipSuccess) break;
-    if (c > 2 * max_lz && c != 4) continue;
-    make_items(P, c);
-    e = hipMemcpyAsync(h->d_items(), P.items.data(), P.items.size() * sizeof(Item),
-                       hipMemcpyHostToDevice, h->stream);
-    // trial steps read the current copy and write the spare one: the state
-    // and the time are unchanged
-    StepArgs a = step_args(h, h->t - h->t_dev);
-    for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step(h->opt.precision, kStep, a, h->stream);
-    if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-    for (int k = 0; k < steps_per_trial && e == hipSuccess; ++k)
-      e = launch_step(h->opt.precision, kStep, a, h->stream);
-    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e == hipSuccess && ms < best_ms) {
-      best_ms = ms;
-      best = c;
+  for (int ci = 0; ci < kCands; ++ci)
+    if (cand_ms[ci] < best_ms) {
+      best_ms = cand_ms[ci];
+      best = cands[ci];
     }
-  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   make_items(P, best);
