@@ -30,7 +30,9 @@
 // two segment-edge columns, pulled by 36 lanes of the first wavefront with one
 // load, or wrapped when the segment is a whole periodic row), and after one
 // barrier per row reads the eight neighbour densities of the non-local force
-// from LDS.  Stores are the node's own 18 post-collision values; in the tiled
+// from LDS.  The pulled populations wait in an LDS slot of the lane until
+// the row is collided, while the loads of the row after next are in flight.
+// Stores are the node's own 18 post-collision values; in the tiled
 // layout each link of a wavefront's row is one contiguous 256-byte run.  A
 // step that samples also writes, per node, the FP64 density deviations of the
 // state it pulled (and the FP64 momenta for velocity sampling); the transform
