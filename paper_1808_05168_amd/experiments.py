@@ -20,6 +20,10 @@
 * ``correlation``: the translation-averaged two-point correlation of a sampled
   field's fluctuations from its structure factor (Wiener-Khinchin on the
   lattice), for the real-space correlations of Sec. IV.B.
+* ``run_config`` / ``run``: a batch described by a JSON or YAML file (replicas,
+  storage form, options, warm-up and sampled steps), its structure factors and
+  pressure sums written to an ``.npz`` file, optionally from and to a
+  checkpoint image.
 
 Every time step, sample, transform and reduction runs in the GPU library; this
 module chooses replicas, drives runs and combines the sums it reads back.
@@ -310,6 +314,115 @@ def gradient_scan(Lx: int = 512, Lz: int = 256, grads: Iterable[float] = (0.0, 5
                         P_mean=P_mean, P_shift=P_shift)
 
 
+_RUN_FIELDS = {f.name for f in dataclasses.fields(_Run)}
+_RUN_OPTIONS = {"astar": _f.ASTAR, "wall_uz_fix": _f.WALL_UZ_FIX, "noise_loc": _f.NOISE_LOC,
+                "force_literal": _f.FORCE_LITERAL, "velocity": _f.SAMPLE_VELOCITY}
+_RUN_KEYS = {"precision", "sample_every", "warmup", "steps", "options", "autotune", "replicas"}
+
+
+def run_config(cfg: dict):
+    """Checks a run description and returns (replicas, precision, flags,
+    sample_every, warmup, steps, autotune).
+
+    Keys: ``replicas`` (a list of objects with the fields of a replica --
+    ``Lx``, ``Lz``, ``grad_c0``, ``kT``, ``G``, ``seed``, optional ``rho0`` and
+    ``tau_*`` -- and optionally ``copies``: that many replicas with seeds
+    ``seed``, ``seed + 1``, ...), ``precision`` ("fp32" for FP32-deviation
+    storage, or "fp64"), ``sample_every`` (default 10), ``warmup`` and ``steps``
+    (sampled steps after the warm-up), ``options`` (booleans ``astar``,
+    ``wall_uz_fix`` -- both default true --, ``noise_loc``, ``force_literal``,
+    ``velocity``) and ``autotune`` (default true).  Unknown keys are errors."""
+    if not isinstance(cfg, dict):
+        raise ValueError("run description: expected a mapping")
+    bad = set(cfg) - _RUN_KEYS
+    if bad:
+        raise ValueError(f"run description: unknown keys {sorted(bad)}")
+    prec = {"fp32": _f.FP32_DEV, "fp64": _f.FP64}.get(cfg.get("precision", "fp64"))
+    if prec is None:
+        raise ValueError("run description: precision must be 'fp32' or 'fp64'")
+    opts = {"astar": True, "wall_uz_fix": True}
+    given = cfg.get("options", {}) or {}
+    bad = set(given) - set(_RUN_OPTIONS)
+    if bad:
+        raise ValueError(f"run description: unknown options {sorted(bad)}")
+    opts.update({k: bool(v) for k, v in given.items()})
+    flags = sum(bit for name, bit in _RUN_OPTIONS.items() if opts.get(name))
+    every = int(cfg.get("sample_every", 10))
+    warmup, steps = int(cfg.get("warmup", 0)), int(cfg.get("steps", 0))
+    if every < 1 or warmup < 0 or steps < 1:
+        raise ValueError("run description: need sample_every >= 1, warmup >= 0, steps >= 1")
+    reps = []
+    for i, r in enumerate(cfg.get("replicas") or []):
+        r = dict(r)
+        copies = int(r.pop("copies", 1))
+        bad = set(r) - _RUN_FIELDS
+        missing = {"Lx", "Lz"} - set(r)
+        if bad or missing or copies < 1:
+            raise ValueError(f"run description: replica {i}: unknown {sorted(bad)}, "
+                             f"missing {sorted(missing)}, copies {copies}")
+        base = {"grad_c0": 0.0, "kT": 0.0, "G": 0.0, "seed": 1, **r}
+        for c in range(copies):
+            reps.append(_Run(**{**base, "seed": int(base["seed"]) + c}))
+    if not reps:
+        raise ValueError("run description: no replicas")
+    return reps, prec, flags, every, warmup, steps, bool(cfg.get("autotune", True))
+
+
+def load_run_config(path: str) -> dict:
+    """A run description from a JSON file, or a YAML file (``.yaml``/``.yml``,
+    read with the safe loader)."""
+    with open(path) as fh:
+        if path.endswith((".yaml", ".yml")):
+            import yaml
+            return yaml.safe_load(fh)
+        import json
+        return json.load(fh)
+
+
+def run(cfg: dict, out: str, checkpoint: str = "", resume: str = "",
+        device: str = "cuda:0") -> dict:
+    """Runs the batch of a run description and writes to ``out`` (``.npz``),
+    per replica i: ``rep{i}_{c,rho[,Ux,Uz]}_sums`` (sums of |Phi|^2, Re Phi,
+    Im Phi over the samples, [3][k_z][k_x]) and ``rep{i}_{...}_S`` (the
+    structure factor mean |Phi|^2 - |mean Phi|^2), ``rep{i}_P`` (sum and sum of
+    squares of the spatial mean of P - P_ref, sample count) and
+    ``rep{i}_P_profile`` (its row sums), with ``samples``, ``time`` and the
+    description itself as JSON.  With ``resume`` the handle starts from that
+    checkpoint image (accumulators included) and skips the warm-up; with
+    ``checkpoint`` the final image is saved there.  Returns a short summary."""
+    import json
+    reps, prec, flags, every, warmup, steps, tune = run_config(cfg)
+    lat = _f.Lattice(reps, precision=prec, sample_every=every, flags=flags, device=device)
+    try:
+        if tune:
+            lat.autotune(20)
+        if resume:
+            lat.load(np.load(resume, allow_pickle=False))
+        else:
+            lat.step(warmup)
+            lat.reset_accumulators()
+        lat.step(steps)
+        names = ["c", "rho"] + (["Ux", "Uz"] if flags & _f.SAMPLE_VELOCITY else [])
+        res = {"config": np.array(json.dumps(cfg)), "time": np.array(lat.time)}
+        n_samples = 0
+        for i in range(len(reps)):
+            for fld, name in enumerate(names):
+                a2, re, im, n = lat.read_structure_factor(i, fld)
+                res[f"rep{i}_{name}_sums"] = np.stack([a2, re, im])
+                res[f"rep{i}_{name}_S"] = lat.structure_factor(i, fld)
+                n_samples = n
+            s, s2, prof, n = lat.read_pressure(i)
+            res[f"rep{i}_P"] = np.array([s, s2, n])
+            res[f"rep{i}_P_profile"] = prof
+        res["samples"] = np.array(n_samples)
+        np.savez(out, **res)
+        if checkpoint:
+            np.save(checkpoint, lat.save(), allow_pickle=False)
+        return {"replicas": len(reps), "time": lat.time, "samples": n_samples, "out": out}
+    finally:
+        lat.close()
+
+
 def _main(argv=None) -> None:
     import argparse
     ap = argparse.ArgumentParser(prog="python -m paper_1808_05168_amd.experiments",
@@ -342,7 +455,16 @@ def _main(argv=None) -> None:
     c.add_argument("--warmup", type=int, default=20000)
     c.add_argument("--steps", type=int, default=180000)
     c.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    d = sub.add_parser("run", help="a batch from a JSON or YAML description; sums to .npz")
+    d.add_argument("config")
+    d.add_argument("--out", required=True, help="output .npz file")
+    d.add_argument("--checkpoint", default="", help="save the final image here (.npy)")
+    d.add_argument("--resume", default="", help="start from this image (.npy)")
     args = ap.parse_args(argv)
+    if args.what == "run":
+        print(run(load_run_config(args.config), args.out, checkpoint=args.checkpoint,
+                  resume=args.resume))
+        return
     if args.what == "gradscan":
         r = gradient_scan(args.Lx, args.Lz, args.grad, kT=args.kT, G=args.G,
                           warmup=args.warmup, steps=args.steps,

@@ -141,3 +141,44 @@ def test_gradient_scan_matches_oracle(F):
     for g in grads:
         assert abs(res.P_mean[g][0] - P[g]) <= 1e-12 * scale
         assert abs(res.P_shift[g][0] - (P[g] - P[grads[0]])) <= 2e-12 * scale
+
+
+def test_run_description_end_to_end(F, tmp_path):
+    """``experiments.run``: the sums it writes are those of the same batch run
+    directly (and match the oracle), and a run resumed from its checkpoint
+    image continues the accumulators exactly as an uninterrupted run."""
+    from paper_1808_05168_amd import experiments as X
+    cfg = {"precision": "fp64", "sample_every": 5, "warmup": 20, "steps": 40,
+           "options": {"velocity": True}, "autotune": False,
+           "replicas": [{"Lx": 24, "Lz": 12, "grad_c0": 5e-3, "kT": 1e-4, "G": 0.5,
+                         "seed": 11, "copies": 2}]}
+    say("case: run description, 2 x (24x12) fp64, 20 + 40 steps, checkpoint + resume")
+    out1, ck = str(tmp_path / "a.npz"), str(tmp_path / "a.npy")
+    info = X.run(cfg, out1, checkpoint=ck)
+    assert info["samples"] == 8 and info["time"] == 60
+    r1 = np.load(out1, allow_pickle=False)
+    # the second replica (seed 12) against the oracle
+    reps, *_ = X.run_config(cfg)
+    f = O.init_state(reps[1], flags=O.DEFAULT_FLAGS | O.VELOCITY)
+    O.run(reps[1], f, 0, 20, flags=O.DEFAULT_FLAGS | O.VELOCITY)
+    acc = O.Accum(24, 12, nfields=4)
+    O.run(reps[1], f, 20, 40, acc, flags=O.DEFAULT_FLAGS | O.VELOCITY, sample_every=5)
+    assert acc.n_samples == 8
+    for fld, name in enumerate(["c", "rho", "Ux", "Uz"]):
+        sums = r1[f"rep1_{name}_sums"]
+        scale = np.abs(acc.sq[fld]).max()
+        assert np.abs(sums - acc.sq[fld]).max() <= 1e-12 * scale, name
+    np.testing.assert_allclose(r1["rep1_P_profile"], acc.prof, rtol=0,
+                               atol=1e-12 * np.abs(acc.prof).max())
+    assert r1["rep1_P"][2] == 8
+    # resumed for 40 more steps == one run of 20 + 80 steps
+    out2 = str(tmp_path / "b.npz")
+    X.run(cfg, out2, resume=ck)
+    cfg_long = {**cfg, "steps": 80}
+    out3 = str(tmp_path / "c.npz")
+    X.run(cfg_long, out3)
+    r2, r3 = np.load(out2, allow_pickle=False), np.load(out3, allow_pickle=False)
+    assert int(r2["time"]) == int(r3["time"]) == 100 and int(r2["samples"]) == 16
+    for k in r3.files:
+        if k != "config":
+            np.testing.assert_array_equal(r2[k], r3[k], err_msg=k)
