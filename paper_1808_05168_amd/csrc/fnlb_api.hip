@@ -175,7 +175,8 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
     R.state_off = state_elems;
     state_elems += 18 * R.plane;
     const int nkx = p.Lx / 2 + 1;
-    field_d = (field_d + 31) / 32 * 32;  // 256-byte aligned (paired loads of the row pass)
+    // 256-byte aligned (paired loads of the row pass)
+    field_d = (field_d + 256 / P.store_size - 1) / (256 / P.store_size) * (256 / P.store_size);
     R.field_off = field_d;
     field_d += (int64_t)nf * p.Lz * p.Lx;
     R.spec_off = spec_c;
@@ -274,7 +275,7 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
   P.o_tw = o;
   o = align_up(o + (size_t)tw_c * 16);
   P.o_fields = o;
-  o = align_up(o + (size_t)field_d * 8);
+  o = align_up(o + (size_t)field_d * P.store_size);
   P.o_spec = o;
   o = align_up(o + (size_t)spec_c * 16);
   P.o_ppart = o;
@@ -312,7 +313,7 @@ struct fnlb_handle {
   int64_t* d_time() { return (int64_t*)(work + plan.o_misc); }
   int32_t* d_watchdog() { return (int32_t*)(work + plan.o_misc + 8); }
   double2* d_tw() { return (double2*)(work + plan.o_tw); }
-  double* d_fields() { return (double*)(work + plan.o_fields); }
+  void* d_fields() { return (void*)(work + plan.o_fields); }
   double2* d_spec() { return (double2*)(work + plan.o_spec); }
   double* d_ppart() { return (double*)(work + plan.o_ppart); }
   char* state_copy(int k) { return state + (size_t)k * plan.state_half; }
@@ -346,7 +347,8 @@ hipError_t observe(fnlb_handle* h, hipStream_t s, double* acc = nullptr) {
   const Plan& P = h->plan;
   if (!acc) acc = (double*)h->accum;
   hipError_t e = launch_row_transform(h->d_reps(), h->d_rows(), (int)P.rows.size(), P.n_pairs,
-                                      P.max_row_lds, h->d_fields(), h->d_spec(), h->d_tw(),
+                                      P.max_row_lds, h->opt.precision, h->d_fields(),
+                                      h->d_spec(), h->d_tw(),
                                       h->d_ppart(), h->d_watchdog(), s);
   if (e != hipSuccess) return e;
   return launch_col_transform(h->d_reps(), h->d_cols(), (int)P.cols.size(), P.max_col_lds,

@@ -35,7 +35,7 @@ struct alignas(256) RepInfo {
   int32_t pitch;          // row length rounded up to whole 64-column tiles (>= Lx)
   int64_t plane;          // elements per (species, link) plane
   int64_t state_off;      // element offset of this replica in one state copy
-  int64_t field_off;      // double offset of the sample inputs [2 or 4][Lz][Lx]
+  int64_t field_off;      // element offset of the sample inputs [2 or 4][Lz][Lx] (storage type)
   int64_t spec_off;       // double2 offset of the row spectra [2][Lz][Lx/2+1]
   int64_t acc_off;        // double offset of [2][3][Lz][Lx/2+1] sums
   int64_t pacc_off;       // double offset of {sum, sum2, profile[Lz]}
@@ -87,7 +87,7 @@ struct StepArgs {
   void* state_out;        // next state copy
   const int64_t* t_base;  // device time counter (graph replays advance it)
   int64_t t_off;          // time = *t_base + t_off
-  double* fields;         // sample inputs base (double)
+  void* fields;           // sample inputs base (float for FP32-deviation storage, else double)
 };
 
 // Launchers (asynchronous on `stream`).
@@ -97,7 +97,8 @@ hipError_t launch_twiddles(const RepInfo* d_reps, const RepInfo* h_reps, int n_r
                            double2* tw_base, hipStream_t stream);
 // watchdog: set non-zero when a sample sees a bad state
 hipError_t launch_row_transform(const RepInfo* reps, const RowRef* rows, int n_rows,
-                                int n_pairs, int max_row_lds, const double* fields, double2* spec,
+                                int n_pairs, int max_row_lds, int precision, const void* fields,
+                                double2* spec,
                                 const double2* tw, double* ppart, int32_t* watchdog,
                                 hipStream_t stream);
 // (also reduces each replica's pressure row sums in ppart)

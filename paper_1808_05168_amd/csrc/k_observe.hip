@@ -3,8 +3,8 @@
 // sum_{x,j} dphi e^{-i q.r}, S(q) = <|Phi(q)|^2> on the lattice; Sec. IV.A for
 // S_U) and the mean pressure (Sec. IV.C).
 //
-// The step kernel writes the FP64 density deviations (and momenta) of a
-// sample.  A row pass forms the real fields and the pressure from them,
+// The step kernel writes the density deviations (and momenta) of a sample in
+// the storage type (FP32 with FP32-deviation storage, else FP64).  A row pass forms the real fields and the pressure from them,
 // transforms two fields of a row at once as one complex sequence (z = delta c
 // + i delta rho, and z = U_x + i U_z) and splits the result by Hermitian
 // symmetry into the half spectra k_x = 0..Lx/2; a column pass transforms each
@@ -50,9 +50,9 @@ constexpr int kBatch = 8;
 
 // Row pass of a sample: one block per group of consecutive rows of one
 // replica (several short rows share a block) and field pair (blockIdx.y).
-// The step kernel leaves, per node, the FP64 deviations of the two species
-// densities from the row references (and, with velocity sampling, the FP64
-// total momenta).  This pass forms the sampled fields from them: pair 0 is
+// The step kernel leaves, per node, the deviations of the two species
+// densities from the row references (and, with velocity sampling, the total
+// momenta), of type FT; this pass works in FP64.  It forms the sampled fields from them: pair 0 is
 // delta c + i delta rho, together with the pressure of every node (reading
 // R11: P = rho/3 + (G/4) sum_l w_l |c_l|^2 [rho^A rho^B(r + c_l) + rho^B
 // rho^A(r + c_l)], ghost rows repeating the wall row) summed per row in a
@@ -61,8 +61,9 @@ constexpr int kBatch = 8;
 // are read from global memory (L2) with 32-bit offsets shared by both species.
 // Each row is then transformed and split into the two half spectra.  LDS: the
 // rows, then (power-of-two rows) the N/2 twiddles the FFT uses.
+template <typename FT>
 __global__ __launch_bounds__(256) void k_row_transform(const RepInfo* reps, const RowRef* rows,
-                                                       const double* fields, double2* spec,
+                                                       const void* fields, double2* spec,
                                                        const double2* tw_base, double* ppart,
                                                        int32_t* watchdog) {
   extern __shared__ double2 lds[];
@@ -72,10 +73,10 @@ __global__ __launch_bounds__(256) void k_row_transform(const RepInfo* reps, cons
   const int N = R.Lx, Lz = R.Lz, nkx = N / 2 + 1, nr = rr.nrows;
   const int pair = blockIdx.y;
   const size_t plane = (size_t)Lz * N;
-  const double* dA = fields + R.field_off;  // density deviations [Lz][Lx]
-  const double* dB = dA + plane;
-  const double* mX = dB + plane;  // total momenta (velocity sampling)
-  const double* mZ = mX + plane;
+  const FT* dA = (const FT*)fields + R.field_off;  // density deviations [Lz][Lx]
+  const FT* dB = dA + plane;
+  const FT* mX = dB + plane;  // total momenta (velocity sampling)
+  const FT* mZ = mX + plane;
   const double2* tw = tw_base + R.tw_off;
   const size_t orow = (size_t)(2 * pair) * Lz + rr.j0;  // first field of the pair
   double2* out_c = spec + R.spec_off + orow * nkx;
@@ -99,10 +100,12 @@ __global__ __launch_bounds__(256) void k_row_transform(const RepInfo* reps, cons
   const double c0 = rAj / rho0, dPref = R.p_ref - rho0 / 3.0;
   const bool wall = (R.flags & FNLB_WALL_UZ_FIX) && (j == 0 || j == Lz - 1);
   // byte offsets of the three rows (Lx, Lz <= 4096, so 8 Lx Lz < 2^32: the
-  // planes are read through 32-bit offsets from a uniform base)
-  const uint32_t oC = (uint32_t)j * N * 8u, oU = (uint32_t)jU * N * 8u, oD = (uint32_t)jD * N * 8u;
-  auto ld = [](const double* base, uint32_t off) {
-    return *(const double*)((const char*)base + off);
+  // planes are read through 32-bit offsets from a uniform base); FS bytes per
+  // value
+  constexpr uint32_t FS = sizeof(FT);
+  const uint32_t oC = (uint32_t)j * N * FS, oU = (uint32_t)jU * N * FS, oD = (uint32_t)jD * N * FS;
+  auto ld = [](const FT* base, uint32_t off) {
+    return (double)*(const FT*)((const char*)base + off);
   };
   double psum = 0.0;
   bool bad = false;
@@ -145,16 +148,21 @@ __global__ __launch_bounds__(256) void k_row_transform(const RepInfo* reps, cons
   };
   if (live && (N & 1) == 0) {
     // even rows: a thread takes two neighbouring nodes, reading each row of
-    // each species as one 16-byte pair (aligned: x and the row length are
-    // even) and the pair's two outer neighbours
-    auto ld2 = [](const double* base, uint32_t off) {
-      return *(const double2*)((const char*)base + off);
+    // each species as one aligned pair (x and the row length are even) and
+    // the pair's two outer neighbours
+    auto ld2 = [](const FT* base, uint32_t off) {
+      if constexpr (sizeof(FT) == 8) {
+        return *(const double2*)((const char*)base + off);
+      } else {
+        const float2 v = *(const float2*)((const char*)base + off);
+        return make_double2((double)v.x, (double)v.y);
+      }
     };
     for (int x = 2 * t2; x < N; x += 2 * gsz) {
-      const uint32_t x8 = 8u * x, xm8 = x == 0 ? 8u * (N - 1) : x8 - 8u,
-                     xq8 = x + 2 == N ? 0u : x8 + 16u;
+      const uint32_t x8 = FS * x, xm8 = x == 0 ? FS * (N - 1) : x8 - FS,
+                     xq8 = x + 2 == N ? 0u : x8 + 2 * FS;
       Stencil A0, A1, B0, B1;
-      auto rows = [&](const double* base, Stencil& S0, Stencil& S1) {
+      auto rows = [&](const FT* base, Stencil& S0, Stencil& S1) {
         const double2 mD = ld2(base, oD + x8), mC = ld2(base, oC + x8), mU = ld2(base, oU + x8);
         const double lD = ld(base, oD + xm8), lC = ld(base, oC + xm8), lU = ld(base, oU + xm8);
         const double rD = ld(base, oD + xq8), rC = ld(base, oC + xq8), rU = ld(base, oU + xq8);
@@ -164,13 +172,13 @@ __global__ __launch_bounds__(256) void k_row_transform(const RepInfo* reps, cons
       rows(dA, A0, A1);
       rows(dB, B0, B1);
       eval(x, oC + x8, A0, B0);
-      eval(x + 1, oC + x8 + 8u, A1, B1);
+      eval(x + 1, oC + x8 + FS, A1, B1);
     }
   } else if (live) {
     for (int x = t2; x < N; x += gsz) {
-      const uint32_t x8 = 8u * x, xm8 = x == 0 ? 8u * (N - 1) : x8 - 8u,
-                     xp8 = x == N - 1 ? 0u : x8 + 8u;
-      auto row3 = [&](const double* base) {
+      const uint32_t x8 = FS * x, xm8 = x == 0 ? FS * (N - 1) : x8 - FS,
+                     xp8 = x == N - 1 ? 0u : x8 + FS;
+      auto row3 = [&](const FT* base) {
         return Stencil{ld(base, oD + x8), ld(base, oD + xm8), ld(base, oD + xp8),
                        ld(base, oC + x8), ld(base, oC + xm8), ld(base, oC + xp8),
                        ld(base, oU + x8), ld(base, oU + xm8), ld(base, oU + xp8)};
@@ -414,13 +422,17 @@ hipError_t launch_twiddles(const RepInfo* d_reps, const RepInfo* h_reps, int n_r
 }
 
 hipError_t launch_row_transform(const RepInfo* reps, const RowRef* rows, int n_rows, int n_pairs,
-                                int max_row_lds, const double* fields, double2* spec,
-                                const double2* tw, double* ppart, int32_t* watchdog,
-                                hipStream_t stream) {
+                                int max_row_lds, int precision, const void* fields,
+                                double2* spec, const double2* tw, double* ppart,
+                                int32_t* watchdog, hipStream_t stream) {
   if (n_rows <= 0) return hipSuccess;
   const size_t lds = (size_t)max_row_lds * sizeof(double2);
-  hipLaunchKernelGGL(k_row_transform, dim3(n_rows, n_pairs), dim3(256), lds, stream, reps, rows,
-                     fields, spec, tw, ppart, watchdog);
+  if (precision == FNLB_FP64)
+    hipLaunchKernelGGL(k_row_transform<double>, dim3(n_rows, n_pairs), dim3(256), lds, stream,
+                       reps, rows, fields, spec, tw, ppart, watchdog);
+  else
+    hipLaunchKernelGGL(k_row_transform<float>, dim3(n_rows, n_pairs), dim3(256), lds, stream,
+                       reps, rows, fields, spec, tw, ppart, watchdog);
   return hipGetLastError();
 }
 

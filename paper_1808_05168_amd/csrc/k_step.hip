@@ -34,9 +34,10 @@
 // the row is collided, while the loads of the row after next are in flight.
 // Stores are the node's own 18 post-collision values; in the tiled
 // layout each link of a wavefront's row is one contiguous 256-byte run.  A
-// step that samples also writes, per node, the FP64 density deviations of the
-// state it pulled (and the FP64 momenta for velocity sampling); the transform
-// pass forms the observables from them.
+// step that samples also writes, per node, the density deviations of the
+// state it pulled (and the momenta for velocity sampling), summed in FP64 and
+// stored in the storage type; the transform pass forms the observables from
+// them in FP64.
 #include "fnlb.h"
 #include "fnlb_device.hpp"
 #include "fnlb_internal.hpp"
@@ -296,22 +297,24 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     const double szref = rAs * (double)(jU - jD) * (1.0 / 6.0);  // species A
 
     if constexpr (MODE != kStep) {
-      // sample of f(t): the FP64 density deviations of this node and, for
-      // velocity sampling, its FP64 total momentum; the transform pass forms
-      // the observables from them
+      // sample of f(t): the density deviations of this node and, for velocity
+      // sampling, its total momentum, summed in FP64 and stored in the storage
+      // type (in FP32 the rounding, 6e-8 relative, stays far inside the
+      // 1e-5 bar of that storage form); the transform pass forms the
+      // observables from them
       if (act) {
         double da, db;
         density<double>(cur, da, db);
-        double* fld = a.fields + R.field_off;
+        Store* fld = (Store*)a.fields + R.field_off;
         const int64_t plane = (int64_t)Lz * Lx, n = (int64_t)j * Lx + x;
-        fld[n] = da;
-        fld[plane + n] = db;
+        fld[n] = (Store)da;
+        fld[plane + n] = (Store)db;
         if (flags & FNLB_SAMPLE_VELOCITY) {
           double d[9];
 #pragma unroll
           for (int l = 0; l < 9; ++l) d[l] = (double)cur[l] + (double)cur[9 + l];
-          fld[2 * plane + n] = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
-          fld[3 * plane + n] = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+          fld[2 * plane + n] = (Store)((d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]));
+          fld[3 * plane + n] = (Store)((d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]));
         }
       }
     }
