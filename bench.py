@@ -193,14 +193,15 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, out_md, command):
     runs first."""
     import csv
     from collections import Counter, defaultdict
-    step_name = "k_step<float, float, 0>"
+    # template arguments: compute type, storage type, mode (0 plain, 1 sampling), ...
+    step_name = "k_step<float, float, 0,"
     stats = list(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_stats.csv"))))
     rows = sorted(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_trace.csv"))),
                   key=lambda r: int(r["Start_Timestamp"]))
     trace = [r for r in rows if step_name in r["Kernel_Name"]]
     grid = Counter(r["Grid_Size_X"] for r in trace).most_common(1)[0][0]
     last_sample = max((int(r["Start_Timestamp"]) for r in rows
-                       if "k_step<float, float, 1>" in r["Kernel_Name"]), default=-1)
+                       if "k_step<float, float, 1," in r["Kernel_Name"]), default=-1)
     durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace
             if r["Grid_Size_X"] == grid and int(r["Start_Timestamp"]) > last_sample]
     avg_us = sum(durs) / len(durs) / 1e3

@@ -334,6 +334,7 @@ StepArgs step_args(fnlb_handle* h, int64_t t_off) {
   a.n_items = (int)h->plan.items.size();
   const int nb = (a.n_items + 7) / 8 * 8;
   a.n_blocks = nb;
+  a.chunk_rows = h->plan.chunk;
   a.state_in = h->state_copy(h->cur);
   a.state_out = h->state_copy(1 - h->cur);
   a.t_base = h->d_time();

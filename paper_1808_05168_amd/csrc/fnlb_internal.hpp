@@ -83,6 +83,7 @@ struct StepArgs {
   const Item* items;
   int32_t n_items;
   int32_t n_blocks;       // blocks launched (multiple of 8 for the XCD map)
+  int32_t chunk_rows;     // rows per work item (FP64: >= 4 reads the tables from LDS)
   const void* state_in;   // current state copy
   void* state_out;        // next state copy
   const int64_t* t_base;  // device time counter (graph replays advance it)

@@ -70,7 +70,9 @@ __device__ __forceinline__ void edge_pull(Rsrc r, uint32_t link_b, uint32_t row_
               col_offset(cp, SB), o);
 }
 
-template <typename Real, typename Store, int MODE>
+// TAB_LDS (FP64 only): the block copies the Box-Muller tables into LDS first,
+// which pays off for work items of several rows.
+template <typename Real, typename Store, int MODE, bool TAB_LDS>
 __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   // Density ring in LDS (row slot, species, column + 1) in the compute type:
   // the collision reads the same sums whether or not the step samples, so
@@ -213,6 +215,19 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   const Real sig1[5] = {(Real)sgB[3], (Real)sgB[4], (Real)sgB[5], (Real)sgB[6], (Real)sgB[8]};
 
   const int j0 = it.j0, j1 = it.j1;
+  // FP64 Box-Muller tables: gathered by table index, from LDS when the item
+  // has several rows (the copy is one more barrier before the first row)
+  const BmTables* bmt = R.bm;
+  if constexpr (TAB_LDS) {
+    static_assert(sizeof(Real) == 8, "tables are used by the FP64 form only");
+    __shared__ BmTables bm_lds;
+    const double2* src = (const double2*)R.bm;
+    double2* dst = (double2*)&bm_lds;
+    constexpr int n2 = (int)(sizeof(BmTables) / sizeof(double2));
+    for (int q = tid; q < n2; q += kBlock) dst[q] = src[q];
+    __syncthreads();
+    bmt = &bm_lds;
+  }
   // Rows whose densities the item needs: its own and one more on each side
   // inside the walls.  The item marches from jfirst in direction dir (items
   // alternate, so that two sharing a boundary read its rows at the same time);
@@ -269,10 +284,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     Real gA0[4], gA1[4], gB0[4], gB1[4];
     if constexpr (MODE != kSampleOnly) {
       if (wave_act) {
-        node_normals(node, (uint64_t)t, 2u, k0, k1, gB0, R.bm);
-        node_normals(node, (uint64_t)t, 3u, k0, k1, gB1, R.bm);
-        node_normals(node, (uint64_t)t, 0u, k0, k1, gA0, R.bm);
-        node_normals(node, (uint64_t)t, 1u, k0, k1, gA1, R.bm);
+        node_normals(node, (uint64_t)t, 2u, k0, k1, gB0, bmt);
+        node_normals(node, (uint64_t)t, 3u, k0, k1, gB1, bmt);
+        node_normals(node, (uint64_t)t, 0u, k0, k1, gA0, bmt);
+        node_normals(node, (uint64_t)t, 1u, k0, k1, gA1, bmt);
       }
     }
 
@@ -499,18 +514,18 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   }
 }
 
-template <typename Real, typename Store>
+template <typename Real, typename Store, bool TAB_LDS>
 hipError_t launch_typed(int mode, const StepArgs& a, hipStream_t s) {
   const dim3 grid(a.n_blocks), block(kBlock);
   switch (mode) {
     case kStep:
-      hipLaunchKernelGGL((k_step<Real, Store, kStep>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_step<Real, Store, kStep, TAB_LDS>), grid, block, 0, s, a);
       break;
     case kStepSample:
-      hipLaunchKernelGGL((k_step<Real, Store, kStepSample>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_step<Real, Store, kStepSample, TAB_LDS>), grid, block, 0, s, a);
       break;
     case kSampleOnly:
-      hipLaunchKernelGGL((k_step<Real, Store, kSampleOnly>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_step<Real, Store, kSampleOnly, TAB_LDS>), grid, block, 0, s, a);
       break;
     default:
       return hipErrorInvalidValue;
@@ -522,8 +537,10 @@ hipError_t launch_typed(int mode, const StepArgs& a, hipStream_t s) {
 
 hipError_t launch_step(int precision, int mode, const StepArgs& a, hipStream_t stream) {
   if (a.n_items <= 0) return hipSuccess;
-  if (precision == FNLB_FP64) return launch_typed<double, double>(mode, a, stream);
-  return launch_typed<float, float>(mode, a, stream);
+  if (precision == FNLB_FP64)
+    return a.chunk_rows >= 4 ? launch_typed<double, double, true>(mode, a, stream)
+                             : launch_typed<double, double, false>(mode, a, stream);
+  return launch_typed<float, float, false>(mode, a, stream);
 }
 
 }  // namespace fnlb

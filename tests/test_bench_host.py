@@ -13,8 +13,8 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 import workloads as W  # noqa: E402
 
-STEP0 = "void fnlb::(anonymous namespace)::k_step<float, float, 0>(fnlb::StepArgs)"
-STEP1 = "void fnlb::(anonymous namespace)::k_step<float, float, 1>(fnlb::StepArgs)"
+STEP0 = "void fnlb::(anonymous namespace)::k_step<float, float, 0, false>(fnlb::StepArgs)"
+STEP1 = "void fnlb::(anonymous namespace)::k_step<float, float, 1, false>(fnlb::StepArgs)"
 COPY = "__amd_rocclr_copyBuffer"
 
 
