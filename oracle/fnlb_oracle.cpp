@@ -43,7 +43,7 @@
 //       the non-local interaction part (G/4) sum_l w_l |c_l|^2
 //       [rho^A(r) rho^B(r+c_l) + rho^B(r) rho^A(r+c_l)].
 //   R12 the z-transform runs over the L fluid rows with q_z = 2 pi k_z / L.
-//   R17 the velocity fields of S_U(q) (Sec. IV.A, Eq. (25)) are the
+//   R17 the velocity fields of S_U(q) (Sec. IV.A, Eq. (31)) are the
 //       barycentric U of Eq. (10) of f(t), after the wall fix, as it enters
 //       the collision of the sampled step (flag ORA_VELOCITY).
 //
@@ -740,6 +740,41 @@ int ora_velocity(const ora_params* p, const double* f, double* U) {
       sim.macros(rho, x, j, fl, F, ux, uz);
       U[(size_t)j * p->Lx + x] = ux;
       U[sim.n + (size_t)j * p->Lx + x] = uz;
+    }
+  return 0;
+}
+
+// Per-node macroscopic quantities of the state f as the collision uses them:
+// the node's populations after the wall fix, fl_out[s][l][j][x] (Sec. III.A,
+// R7; equal to the pulled populations off the wall rows), the force
+// densities F[s][component][j][x] (Eqs. (11)-(13) with the a_* footnote) and
+// the barycentric velocity U[component][j][x] (Eq. (10)).  Any output may be
+// NULL.
+int ora_macros(const ora_params* p, const double* f, double* fl_out, double* F_out,
+               double* U_out) {
+  if (check_params(p)) return -1;
+  Theta<double> th{p->tau_d, p->tau_s, p->G};
+  Sim<double> sim(*p, th);
+  std::vector<double> rho;
+  sim.densities(f, rho);
+  const size_t n = sim.n;
+  for (int j = 0; j < p->Lz; ++j)
+    for (int x = 0; x < p->Lx; ++x) {
+      const size_t k = (size_t)j * p->Lx + x;
+      double fl[2][Q], F[2][2], ux, uz;
+      for (int s = 0; s < 2; ++s)
+        for (int l = 0; l < Q; ++l) fl[s][l] = f[sim.idx(s, l, j, x)];
+      sim.macros(rho, x, j, fl, F, ux, uz);
+      for (int s = 0; s < 2; ++s) {
+        if (fl_out)
+          for (int l = 0; l < Q; ++l) fl_out[sim.idx(s, l, j, x)] = fl[s][l];
+        if (F_out)
+          for (int d = 0; d < 2; ++d) F_out[(size_t)(2 * s + d) * n + k] = F[s][d];
+      }
+      if (U_out) {
+        U_out[k] = ux;
+        U_out[n + k] = uz;
+      }
     }
   return 0;
 }

@@ -209,6 +209,21 @@ def velocity(rep, f: np.ndarray, flags: int = DEFAULT_FLAGS) -> np.ndarray:
     return U
 
 
+def macros(rep, f: np.ndarray, flags: int = DEFAULT_FLAGS):
+    """(fl, F, U) of the state f as the collision uses them: populations after
+    the wall fix fl[2][9][Lz][Lx], force densities F[species][component][Lz][Lx]
+    and barycentric velocity U[component][Lz][Lx]."""
+    p = params(rep, flags)
+    fl = np.zeros_like(f)
+    F = np.zeros((2, 2, rep.Lz, rep.Lx))
+    U = np.zeros((2, rep.Lz, rep.Lx))
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib().ora_macros.argtypes = [ctypes.POINTER(OraParams), dp, dp, dp, dp]
+    if lib().ora_macros(ctypes.byref(p), _dp(f), _dp(fl), _dp(F), _dp(U)) != 0:
+        raise ValueError("oracle: invalid parameters")
+    return fl, F, U
+
+
 def _misfit_argtypes():
     dp = ctypes.POINTER(ctypes.c_double)
     pp = ctypes.POINTER(OraParams)

@@ -198,3 +198,52 @@ def test_density_spectrum_fdt_without_wall_fix(ora):
     assert S[1][0, 0] < 1e-20
     assert abs(S[2][mask].mean() / kT - 1) < 0.04
     assert abs(S[3][mask].mean() / kT - 1) < 0.04
+
+
+def test_wall_rule_zeroes_normal_velocity(ora):
+    """Sec. III.A: on the two wall rows the normal barycentric velocity is set
+    to zero at every step by readjusting the rest population (reading R7).
+    Checked from the populations the collision receives, recomputed here:
+    rho U_z = sum_s sum_l c_lz f^S_l + (F^A_z + F^B_z)/2 vanishes on rows 0
+    and L-1, each species keeps its mass, only f_0 and the bounced-back normal
+    population (f_2 at the bottom, f_4 at the top) change, the change is split
+    between species in proportion to rho^S/rho, and nothing changes in the
+    bulk.  A sign slip in the fix at either wall doubles rho U_z there."""
+    Lx, Lz = 12, 8
+    rep = W.Replica(Lx=Lx, Lz=Lz, grad_c0=5e-3, kT=1e-4, G=0.5, tau_s=0.7, tau_d=0.8,
+                    seed=11)
+    c, w, T, N = ora.tables()
+    cz = c[:, 1]
+    f = ora.init_state(rep)
+    ora.run(rep, f, 0, 40)
+    # a state away from any stationary one, so that the walls carry momentum
+    f = f + 1e-3 * np.random.default_rng(5).standard_normal(f.shape) * w[None, :, None, None]
+    fl, F, U = ora.macros(rep, f)
+    rho_s = f.sum(axis=1)
+    jz = lambda g: np.einsum("l,slzx->zx", cz, g)
+    Fz = F[0, 1] + F[1, 1]
+    Pi_before = jz(f) + 0.5 * Fz
+    Pi_after = jz(fl) + 0.5 * Fz
+    for row in (0, Lz - 1):
+        assert np.abs(Pi_before[row]).min() > 1e-7        # the fix has work to do
+        assert np.abs(Pi_after[row]).max() < 1e-17
+        assert np.abs(U[1, row]).max() < 1e-17
+    # the velocity the collision uses is that of the fixed populations
+    r = rho_s.sum(axis=0)
+    np.testing.assert_allclose(U[1], Pi_after / r, rtol=0, atol=1e-17)
+    np.testing.assert_allclose(fl.sum(axis=1), rho_s, rtol=0, atol=4e-16)
+    np.testing.assert_array_equal(fl[:, :, 1:Lz - 1], f[:, :, 1:Lz - 1])
+    for row, moved in ((0, 2), (Lz - 1, 4)):
+        d = fl[:, :, row] - f[:, :, row]
+        untouched = [l for l in range(9) if l not in (0, moved)]
+        np.testing.assert_array_equal(d[:, untouched], 0.0)
+        # the normal population loses rho^S/rho of the excess, f_0 gains it
+        share = rho_s[:, row] / r[row]
+        sign = -1.0 if row == 0 else 1.0
+        np.testing.assert_allclose(d[:, moved], sign * share * Pi_before[row], rtol=1e-9,
+                                   atol=1e-19)
+        np.testing.assert_allclose(d[:, 0], -d[:, moved], rtol=0, atol=6e-17)
+    # with the fix off nothing is touched and the walls keep their momentum
+    fl0, _, U0 = ora.macros(rep, f, flags=ora.ASTAR)
+    np.testing.assert_array_equal(fl0, f)
+    assert np.abs(U0[1, 0]).min() > 1e-8 and np.abs(U0[1, Lz - 1]).min() > 1e-8
