@@ -296,48 +296,79 @@ def summarize_counters(pmc_dir, out_md, command):
     print("\n".join(lines))
 
 
-def cpu_baseline(reps, budget_s: float):
-    """The oracle as it stands, on one replica of each lattice size, for as many
-    steps as fit the budget (at least 20)."""
+def host_threads() -> int:
+    """Threads the oracle runs on: OMP_NUM_THREADS where it is set (the host's
+    CPU share for one GPU on a shared machine), else every CPU this process may
+    run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def _oracle_rate(O, reps, steps, t0=0, acc=None, every=0):
+    """Node updates per second of the oracle over `steps` steps of each replica
+    (each from its rest state), and the elapsed seconds."""
+    f = [O.init_state(r) for r in reps]
+    t = time.perf_counter()
+    for r, fr in zip(reps, f):
+        O.run(r, fr, t0, steps, acc, sample_every=every)
+    dt = time.perf_counter() - t
+    return sum(r.Lx * r.Lz for r in reps) * steps / dt, dt
+
+
+def cpu_baseline(reps, c4_steps: int = 50, steps: int = 200, steps_1thread: int = 20):
+    """The oracle as it stands (plain FP64 C++ at -O2, OpenMP over rows), on the
+    host's cores and on one thread.
+
+    value: one replica of each lattice size of the benchmark's ensemble, `steps`
+    steps each, no sampling (the rate of the timed workload's mix of sizes).
+    protocol: the 64 x 32 run end to end (5000 steps sampled every 10) with the
+    time of its sampling (the direct Fourier sums) reported apart from the
+    rate; 512 x 256 over `steps` steps; 4096 x 1024 over `c4_steps` steps; the
+    ensemble sample on one thread over `steps_1thread` steps.  Every figure is a
+    measured rate over the stated steps; nothing is extrapolated."""
+    import workloads as W
     from oracle import oracle as O
-    threads = min(os.cpu_count() or 1, 16)
+    threads = host_threads()
     O.set_threads(threads)
     seen, sample = set(), []
     for r in reps:
         if (r.Lx, r.Lz) not in seen:
             seen.add((r.Lx, r.Lz))
             sample.append(r)
-    # calibrate with a few steps, then run the budget
-    f = [O.init_state(r) for r in sample]
-    t = time.perf_counter()
-    for r, fr in zip(sample, f):
-        O.run(r, fr, 0, 5)
-    cal = (time.perf_counter() - t) / 5
-    steps = max(20, int(budget_s / max(cal, 1e-9)))
-    t = time.perf_counter()
-    for r, fr in zip(sample, f):
-        O.run(r, fr, 5, steps)
-    dt = time.perf_counter() - t
-    nodes = sum(r.Lx * r.Lz for r in sample)
-    # the same sample on one thread, for a third of the budget
+    rate, dt = _oracle_rate(O, sample, steps)
+    proto = {}
+    c1 = W.parity_small()
+    acc = O.Accum(c1.Lx, c1.Lz)
+    r_s, t_s = _oracle_rate(O, [c1], 5000, acc=acc, every=10)
+    r_p, t_p = _oracle_rate(O, [c1], 5000)
+    proto["c1_64x32_5000_steps"] = {"mlups_sampled": round(r_s / 1e6, 3), "seconds": round(t_s, 2),
+                                    "mlups_without_sampling": round(r_p / 1e6, 3),
+                                    "sampling_seconds": round(t_s - t_p, 2),
+                                    "samples": acc.n_samples}
+    r2, t2 = _oracle_rate(O, [W.single_512x256()], steps)
+    proto["c2_512x256"] = {"mlups": round(r2 / 1e6, 3), "steps": steps, "seconds": round(t2, 2)}
+    r4, t4 = _oracle_rate(O, [W.large_4096x1024()], c4_steps)
+    proto["c4_4096x1024"] = {"mlups": round(r4 / 1e6, 3), "steps": c4_steps,
+                             "seconds": round(t4, 2)}
     O.set_threads(1)
-    t = time.perf_counter()
-    for r, fr in zip(sample, f):
-        O.run(r, fr, 5 + steps, 2)
-    cal1 = (time.perf_counter() - t) / 2
-    steps1 = max(3, int(budget_s / 3 / max(cal1, 1e-9)))
-    t = time.perf_counter()
-    for r, fr in zip(sample, f):
-        O.run(r, fr, 7 + steps, steps1)
-    dt1 = time.perf_counter() - t
+    r1, t1 = _oracle_rate(O, sample, steps_1thread)
     O.set_threads(threads)
-    return {"value": round(nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+    proto["ensemble_sample_1thread"] = {"mlups": round(r1 / 1e6, 3), "steps": steps_1thread,
+                                        "seconds": round(t1, 2)}
+    return {"value": round(rate / 1e6, 3), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
-            "value_1thread": round(nodes * steps1 / dt1 / 1e6, 3),
-            "sample": f"{len(sample)} replicas (one per size: "
+            "value_1thread": round(r1 / 1e6, 3),
+            "host_cpus_visible": os.cpu_count(),
+            "sample": f"{len(sample)} replicas (one per size of the ensemble: "
                       + ", ".join(f"{r.Lx}x{r.Lz}" for r in sample)
-                      + f"), {steps} steps each, FP64, no sampling, {dt:.1f} s; one thread: "
-                      f"{steps1} steps each, {dt1:.1f} s"}
+                      + f"), {steps} steps each from rest, FP64, no sampling, {dt:.1f} s on "
+                      f"{threads} threads",
+            "protocol": proto}
 
 
 def main():
@@ -347,7 +378,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="batched96",
                     choices=["batched96", "large4096x1024", "single512x256"])
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-c4-steps", type=int, default=50,
+                    help="steps of the 4096 x 1024 oracle run in cpu_baseline.protocol")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -533,7 +565,7 @@ def main():
         out["adjoint"] = adjoint_leg(F, W)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(reps, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(reps, c4_steps=args.cpu_c4_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -118,6 +118,9 @@ int fnlb_bytes_required(const fnlb_replica_params* reps, int32_t n_rep,
  * rho_0^B = rho_bar (1 - c_0(z)), U = 0; Fig. 1) and clears the accumulators.
  * hip_stream is a hipStream_t (NULL = default stream).  Synchronises that
  * stream before returning (the host-side tables it uploads are temporary).
+ * Unless FNLB_NO_GRAPH is set, it also captures the HIP graphs of the
+ * sampling period that fnlb_step replays (periods up to 1024 steps), so that
+ * fnlb_step itself never captures or instantiates a graph.
  * Errors: FNLB_EINVAL (parameters, null or unaligned buffers), FNLB_ENOMEM
  * (a buffer smaller than fnlb_bytes_required), FNLB_EDEVICE. */
 int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep,
@@ -132,7 +135,8 @@ int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep,
  * Samples according to options->sample_every.  All replicas advance in one
  * kernel launch per step.  Whole sampling periods (sample_every steps, or 16
  * steps without sampling) that start on a period boundary are replayed from a
- * HIP graph captured on first use (unless FNLB_NO_GRAPH).  In the graph the
+ * HIP graph captured by fnlb_init or fnlb_autotune (periods longer than 1024
+ * steps: on first use; none with FNLB_NO_GRAPH).  In the graph the
  * transforms of a sample run on a branch of their own beside the steps that
  * follow it, joined before the period ends; results are identical either
  * way.  Asynchronous: all of it is ordered on the caller's stream. */
@@ -144,8 +148,9 @@ int fnlb_step(fnlb_handle* h, int64_t n);
  * handle and, for the rest of the process, for
  * any handle with the same precision and set of lattice shapes created with
  * options->chunk_rows = 0.  Trial steps read the current state and write the
- * spare copy, so the state and the time are unchanged.  Synchronises the
- * stream; *chunk_rows_out (nullable) receives the choice. */
+ * spare copy, so the state and the time are unchanged.  The period graphs are
+ * captured again for the chosen work items.  Synchronises the stream;
+ * *chunk_rows_out (nullable) receives the choice. */
 int fnlb_autotune(fnlb_handle* h, int32_t steps_per_trial, int32_t* chunk_rows_out);
 
 /* Samples the current state f(t) of every replica now: adds |Phi(q)|^2,
@@ -264,6 +269,11 @@ int fnlb_destroy(fnlb_handle* h);
 
 /* Static message for an error code. */
 const char* fnlb_strerror(int code);
+
+/* Static string identifying the sources the library was built from (a hash
+ * of the kernel, runtime and header sources, set by the build), so that a
+ * binding can refuse a library older than its sources. */
+const char* fnlb_build_id(void);
 
 #ifdef __cplusplus
 }

@@ -420,6 +420,19 @@ hipError_t capture_period(fnlb_handle* h, int parity) {
   return e;
 }
 
+// Periods up to this many steps are captured when the handle is created (and
+// again after fnlb_autotune changes the work items), so that fnlb_step never
+// captures or instantiates a graph; longer periods are captured on first use.
+constexpr int64_t kPrecapturePeriod = 1024;
+
+hipError_t prepare_graphs(fnlb_handle* h) {
+  if ((h->opt.flags & FNLB_NO_GRAPH) || h->period > kPrecapturePeriod) return hipSuccess;
+  hipError_t e = hipSuccess;
+  for (int parity = 0; parity < 2 && e == hipSuccess; ++parity)
+    if (!h->graph[parity]) e = capture_period(h, parity);
+  return e;
+}
+
 // Runs one captured period on the caller's stream.
 int replay_period(fnlb_handle* h) {
   hipError_t e = hipSuccess;
@@ -482,9 +495,14 @@ int fnlb_bytes_required(const fnlb_replica_params* reps, int32_t n_rep,
   return FNLB_OK;
 }
 
-int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options* options,
-              void* d_state, size_t state_bytes, void* d_accum, size_t accum_bytes,
-              void* d_work, size_t work_bytes, void* hip_stream, fnlb_handle** out) {
+}  // extern "C"
+
+namespace {
+
+// fnlb_init over a given workspace.
+int init_handle(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options* options,
+                void* d_state, size_t state_bytes, void* d_accum, size_t accum_bytes,
+                void* d_work, size_t work_bytes, void* hip_stream, fnlb_handle** out) {
   if (!out) return FNLB_EINVAL;
   *out = nullptr;
   int rc = validate(reps, n_rep, options);
@@ -527,13 +545,26 @@ int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options
   if (e == hipSuccess) e = launch_fill_zero(h->state, P.state_bytes, s);
   if (e == hipSuccess) e = launch_fill_zero(h->accum, P.accum_bytes, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = prepare_graphs(h);
   if (e != hipSuccess) {
-    delete h;
+    fnlb_destroy(h);
     return FNLB_EDEVICE;
   }
   *out = h;
   return FNLB_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options* options,
+              void* d_state, size_t state_bytes, void* d_accum, size_t accum_bytes,
+              void* d_work, size_t work_bytes, void* hip_stream, fnlb_handle** out) {
+  return init_handle(reps, n_rep, options, d_state, state_bytes, d_accum, accum_bytes, d_work,
+                     work_bytes, hip_stream, out);
+}
+
 
 int fnlb_step(fnlb_handle* h, int64_t n) {
   if (!h || n < 0) return FNLB_EINVAL;
@@ -617,6 +648,8 @@ int fnlb_autotune(fnlb_handle* h, int32_t steps_per_trial, int32_t* chunk_rows_o
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return dev_err(h, e);
   drop_graphs(h);
+  e = prepare_graphs(h);
+  if (e != hipSuccess) return dev_err(h, e);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[tune_key(h->reps.data(), (int)h->reps.size(), h->opt.precision)] = best;
@@ -1068,6 +1101,12 @@ int fnlb_destroy(fnlb_handle* h) {
   delete h;
   return FNLB_OK;
 }
+
+#ifndef FNLB_BUILD_ID
+#define FNLB_BUILD_ID "unknown"
+#endif
+
+const char* fnlb_build_id(void) { return FNLB_BUILD_ID; }
 
 const char* fnlb_strerror(int code) {
   switch (code) {

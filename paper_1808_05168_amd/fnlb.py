@@ -47,17 +47,25 @@ EXPORTS = ["fnlb_bytes_required", "fnlb_init", "fnlb_step", "fnlb_autotune",
            "fnlb_read_pressure", "fnlb_read_populations", "fnlb_write_populations",
            "fnlb_reset_accumulators", "fnlb_get_time", "fnlb_set_time", "fnlb_destroy",
            "fnlb_strerror", "fnlb_adjoint_bytes_required", "fnlb_sq_misfit_gradient",
-           "fnlb_checkpoint_bytes", "fnlb_save", "fnlb_load", "fnlb_pressure_misfit_gradient"]
+           "fnlb_checkpoint_bytes", "fnlb_save", "fnlb_load", "fnlb_pressure_misfit_gradient",
+           "fnlb_build_id"]
 
 
 def load(path: str = LIB_PATH):
-    """Loads libfnlb.so; raises if it has not been built."""
+    """Loads libfnlb.so; raises if it has not been built, or if it was built
+    from other sources than the ones next to it (a stale build)."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
         raise FnlbError(f"{path} not found: build it with `python -m paper_1808_05168_amd.build`")
     lib = ctypes.CDLL(path)
+    lib.fnlb_build_id.restype = ctypes.c_char_p
+    from . import build as _build
+    built, current = lib.fnlb_build_id().decode(), _build.source_id()
+    if built != current:
+        raise FnlbError(f"{path} was built from other sources (build id {built}, sources "
+                        f"{current}): rebuild it with `python -m paper_1808_05168_amd.build`")
     vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
     i64p = ctypes.POINTER(ctypes.c_int64)
     szp = ctypes.POINTER(ctypes.c_size_t)
@@ -147,9 +155,9 @@ class Lattice:
         # torch's caching allocator returns 512-byte aligned blocks
         self.state = torch.empty(sb, dtype=torch.uint8, device=self.device)
         self.accum = torch.empty(ab, dtype=torch.uint8, device=self.device)
-        self.work = torch.empty(wb, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
+        self.work = torch.empty(wb, dtype=torch.uint8, device=self.device)
         _check(lib.fnlb_init(self._params, len(self.reps), ctypes.byref(self._opts),
                              ctypes.c_void_p(self.state.data_ptr()), sb,
                              ctypes.c_void_p(self.accum.data_ptr()), ab,

@@ -41,10 +41,20 @@ def sq_from_sums(a2, re, im, n):
     return a2 / n - ((re / n) ** 2 + (im / n) ** 2)
 
 
-def compare_observables(lat, acc, rep_index, rep, tol):
+def compare_observables(lat, acc, rep_index, rep, tol, kx0_tol=None, diag=None):
     """Structure factors (every sampled field) and pressure sums against the
-    oracle."""
+    oracle.
+
+    S(q) uses the norm of the parity contract, max_q |dS(q)| / mean_q S,
+    asserted at `tol` over the whole half spectrum.  `kx0_tol` (a per-case
+    tolerance, default `tol`) applies to the k_x = 0 column alone: there
+    S = <|Phi|^2> - |<Phi>|^2 subtracts the mean profile of the run, and where
+    that profile drifts (|<Phi>|^2 >> S) the difference amplifies the storage
+    rounding of Phi by about 2 |<Phi>|^2 / S.  `diag` (a dict, optional)
+    receives, unasserted, the same error scaled by mean S + |<Phi(q)>|^2,
+    which shows that amplification."""
     out = {}
+    kx0 = {}
     for fld in range(acc.sq.shape[0]):
         a2, re, im, n = lat.read_structure_factor(rep_index, fld)
         assert n == acc.n_samples, (n, acc.n_samples)
@@ -52,14 +62,15 @@ def compare_observables(lat, acc, rep_index, rep, tol):
             continue
         S_g = sq_from_sums(a2, re, im, n)
         S_o = sq_from_sums(acc.sq[fld, 0], acc.sq[fld, 1], acc.sq[fld, 2], n)
-        # S(q) norm of the parity contract (needs fluctuations and >= 2 samples):
-        # |dS(q)| against mean_q S, plus |<Phi(q)>|^2 where the run's mean field
-        # is not negligible.  S = <|Phi|^2> - |<Phi>|^2 is then a difference of
-        # two sums each known to the storage precision; where |<Phi>|^2 << S
-        # this is exactly max |dS| / mean S.
+        # S(q) norm of the parity contract (needs fluctuations and >= 2 samples)
         if rep.kT > 0 and n >= 2:
-            m2 = (acc.sq[fld, 1] / n) ** 2 + (acc.sq[fld, 2] / n) ** 2
-            out[f"S{fld}"] = (np.abs(S_g - S_o) / (np.abs(S_o).mean() + m2)).max()
+            dS = np.abs(S_g - S_o) / np.abs(S_o).mean()
+            if dS.shape[1] > 1:
+                out[f"S{fld}"] = dS[:, 1:].max()
+            kx0[f"S{fld}_kx0"] = dS[:, 0].max()
+            if diag is not None:
+                m2 = (acc.sq[fld, 1] / n) ** 2 + (acc.sq[fld, 2] / n) ** 2
+                diag[f"S{fld}_scaled"] = (np.abs(S_g - S_o) / (np.abs(S_o).mean() + m2)).max()
         # raw sums: max-norm relative to the largest entry.  The q = 0 entry of
         # delta rho is the total mass deviation, identically zero up to rounding:
         # it is checked as a conservation property instead.
@@ -91,6 +102,10 @@ def compare_observables(lat, acc, rep_index, rep, tol):
         out["P_sum"] = abs(s - acc.pr[0]) / scale
     for k, v in out.items():
         assert v <= tol, f"{k}: {v:.3e} > {tol:.1e}"
+    t0 = tol if kx0_tol is None else kx0_tol
+    for k, v in kx0.items():
+        assert v <= t0, f"{k}: {v:.3e} > {t0:.1e}"
+    out.update(kx0)
     return out
 
 
