@@ -128,6 +128,30 @@ int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep,
               void* d_accum, size_t accum_bytes, void* d_work,
               size_t work_bytes, void* hip_stream, fnlb_handle** out);
 
+/* For callers that cannot allocate device memory (code that will run under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * fnlb_init without the caller's workspace.  The workspace is instead a static
+ * device array of FNLB_STATIC_WORK_BYTES inside the library, one per GPU,
+ * held from the library's load until the process ends; the caller still
+ * passes the state and accumulator buffers (fnlb_bytes_required sizes them)
+ * and the stream.  The handle launches every step directly on that stream, as
+ * with FNLB_NO_GRAPH (which is implied), so a caller may capture fnlb_step into
+ * a graph of its own.  Neither this call nor the handle's other calls
+ * allocate device memory.  The array is shared by everything on one GPU: only
+ * one handle made by this call may exist per device at a time (a second call
+ * on that device returns FNLB_ESTATE until fnlb_destroy of the first), and
+ * the array keeps the last handle's contents, which this call overwrites
+ * before use.  Work of such a handle that overlaps other use of the array on
+ * the same GPU races.  The device is the current HIP device.
+ * Errors: as fnlb_init; FNLB_ENOMEM also when the workspace
+ * fnlb_bytes_required reports exceeds FNLB_STATIC_WORK_BYTES; FNLB_ESTATE as
+ * above. */
+#define FNLB_STATIC_WORK_BYTES (128u << 20)
+int fnlb_init_static_work(const fnlb_replica_params* reps, int32_t n_rep,
+                          const fnlb_options* options, void* d_state,
+                          size_t state_bytes, void* d_accum, size_t accum_bytes,
+                          void* hip_stream, fnlb_handle** out);
+
 /* Advances every replica by n >= 0 time steps of Eq. (6): per node,
  * densities, non-ideal and non-equilibrium forces, wall U_z fix, barycentric
  * velocity (Eq. (10)), MRT collision with forcing moments and noise (Eq. (14)),

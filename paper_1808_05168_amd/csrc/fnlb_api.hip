@@ -17,6 +17,13 @@
 
 using namespace fnlb;
 
+// The static workspace of fnlb_init_static_work: one array per device, part
+// of the library's code object, held until the process ends.  In host code
+// `scratch` names a host-side stand-in, not device memory; its device address
+// comes from hipGetSymbolAddress, taken once per device with that device
+// current, and only that address is handed to kernels.
+static __device__ __align__(256) char scratch[FNLB_STATIC_WORK_BYTES];
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -305,6 +312,7 @@ struct fnlb_handle {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int64_t period = 0;
+  int static_dev = -1;   // device whose static workspace this handle holds, or -1
 
   RepInfo* d_reps() { return (RepInfo*)(work + plan.o_reps); }
   Item* d_items() { return (Item*)(work + plan.o_items); }
@@ -499,10 +507,12 @@ int fnlb_bytes_required(const fnlb_replica_params* reps, int32_t n_rep,
 
 namespace {
 
-// fnlb_init over a given workspace.
+// fnlb_init over a given workspace; static_dev >= 0 marks the workspace as the
+// static array of that device (released by fnlb_destroy).
 int init_handle(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options* options,
                 void* d_state, size_t state_bytes, void* d_accum, size_t accum_bytes,
-                void* d_work, size_t work_bytes, void* hip_stream, fnlb_handle** out) {
+                void* d_work, size_t work_bytes, void* hip_stream, int static_dev,
+                fnlb_handle** out) {
   if (!out) return FNLB_EINVAL;
   *out = nullptr;
   int rc = validate(reps, n_rep, options);
@@ -519,6 +529,7 @@ int init_handle(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_optio
     delete h;
     return FNLB_ENOMEM;
   }
+  h->static_dev = static_dev;
   h->state = (char*)d_state;
   h->accum = (char*)d_accum;
   h->work = (char*)d_work;
@@ -547,12 +558,19 @@ int init_handle(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_optio
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) e = prepare_graphs(h);
   if (e != hipSuccess) {
+    h->static_dev = -1;  // the caller still owns the static workspace
     fnlb_destroy(h);
     return FNLB_EDEVICE;
   }
   *out = h;
   return FNLB_OK;
 }
+
+constexpr size_t kStaticWorkBytes = (size_t)FNLB_STATIC_WORK_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+bool g_static_busy[kMaxDevices] = {};
 
 }  // namespace
 
@@ -562,9 +580,50 @@ int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options
               void* d_state, size_t state_bytes, void* d_accum, size_t accum_bytes,
               void* d_work, size_t work_bytes, void* hip_stream, fnlb_handle** out) {
   return init_handle(reps, n_rep, options, d_state, state_bytes, d_accum, accum_bytes, d_work,
-                     work_bytes, hip_stream, out);
+                     work_bytes, hip_stream, -1, out);
 }
 
+int fnlb_init_static_work(const fnlb_replica_params* reps, int32_t n_rep,
+                          const fnlb_options* options, void* d_state, size_t state_bytes,
+                          void* d_accum, size_t accum_bytes, void* hip_stream,
+                          fnlb_handle** out) {
+  if (!out) return FNLB_EINVAL;
+  *out = nullptr;
+  const int rc = validate(reps, n_rep, options);
+  if (rc) return rc;
+  // the handle launches every step directly on the caller's stream: no graph,
+  // stream or event of its own
+  fnlb_options opt = *options;
+  opt.flags |= FNLB_NO_GRAPH;
+  {
+    Plan P;
+    make_plan(reps, n_rep, &opt, P);
+    if (P.work_bytes > kStaticWorkBytes) return FNLB_ENOMEM;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return FNLB_EDEVICE;
+  if (dev < 0 || dev >= kMaxDevices) return FNLB_EDEVICE;
+  void* work = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_busy[dev]) return FNLB_ESTATE;  // one such handle per device
+    if (!g_static_ptr[dev]) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+        return FNLB_EDEVICE;
+      g_static_ptr[dev] = p;
+    }
+    work = g_static_ptr[dev];
+    g_static_busy[dev] = true;
+  }
+  const int r = init_handle(reps, n_rep, &opt, d_state, state_bytes, d_accum, accum_bytes, work,
+                            kStaticWorkBytes, hip_stream, dev, out);
+  if (r != FNLB_OK) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    g_static_busy[dev] = false;
+  }
+  return r;
+}
 
 int fnlb_step(fnlb_handle* h, int64_t n) {
   if (!h || n < 0) return FNLB_EINVAL;
@@ -1093,6 +1152,10 @@ int fnlb_pressure_misfit_gradient(fnlb_handle* h, const double* P_target, const 
 
 int fnlb_destroy(fnlb_handle* h) {
   if (!h) return FNLB_OK;
+  if (h->static_dev >= 0) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    g_static_busy[h->static_dev] = false;
+  }
   drop_graphs(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->obs_stream) (void)hipStreamDestroy(h->obs_stream);

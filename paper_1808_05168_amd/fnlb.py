@@ -48,7 +48,8 @@ EXPORTS = ["fnlb_bytes_required", "fnlb_init", "fnlb_step", "fnlb_autotune",
            "fnlb_reset_accumulators", "fnlb_get_time", "fnlb_set_time", "fnlb_destroy",
            "fnlb_strerror", "fnlb_adjoint_bytes_required", "fnlb_sq_misfit_gradient",
            "fnlb_checkpoint_bytes", "fnlb_save", "fnlb_load", "fnlb_pressure_misfit_gradient",
-           "fnlb_build_id"]
+           "fnlb_build_id", "fnlb_init_static_work"]
+STATIC_WORK_BYTES = 128 << 20  # FNLB_STATIC_WORK_BYTES
 
 
 def load(path: str = LIB_PATH):
@@ -73,6 +74,8 @@ def load(path: str = LIB_PATH):
     lib.fnlb_bytes_required.argtypes = [rp, ctypes.c_int32, op, szp, szp, szp]
     lib.fnlb_init.argtypes = [rp, ctypes.c_int32, op, vp, ctypes.c_size_t, vp, ctypes.c_size_t,
                               vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.fnlb_init_static_work.argtypes = [rp, ctypes.c_int32, op, vp, ctypes.c_size_t, vp,
+                                          ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     lib.fnlb_step.argtypes = [vp, ctypes.c_int64]
     lib.fnlb_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.fnlb_accumulate_structure_factor.argtypes = [vp]
@@ -136,11 +139,15 @@ class Lattice:
     """A batch of one or more replicas on one GPU.
 
     reps: objects with the fields of ``fnlb_replica_params`` (e.g.
-    ``workloads.Replica``).  precision: FP64 or FP32_DEV.
+    ``workloads.Replica``).  precision: FP64 or FP32_DEV.  static_work: create
+    the handle with ``fnlb_init_static_work`` (the library's static workspace
+    instead of a torch-allocated one; steps launch without graphs; one such
+    handle per GPU at a time).
     """
 
     def __init__(self, reps: Iterable, precision: int = FP64, sample_every: int = 0,
-                 flags: int = DEFAULT_FLAGS, chunk_rows: int = 0, device: str = "cuda:0"):
+                 flags: int = DEFAULT_FLAGS, chunk_rows: int = 0, device: str = "cuda:0",
+                 static_work: bool = False):
         import torch
         self.reps: List = list(reps)
         self.precision = precision
@@ -157,13 +164,23 @@ class Lattice:
         self.accum = torch.empty(ab, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        self.work = torch.empty(wb, dtype=torch.uint8, device=self.device)
-        _check(lib.fnlb_init(self._params, len(self.reps), ctypes.byref(self._opts),
-                             ctypes.c_void_p(self.state.data_ptr()), sb,
-                             ctypes.c_void_p(self.accum.data_ptr()), ab,
-                             ctypes.c_void_p(self.work.data_ptr()), wb,
-                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
-               "fnlb_init")
+        if static_work:
+            self.work = None
+            with torch.cuda.device(self.device):
+                _check(lib.fnlb_init_static_work(
+                    self._params, len(self.reps), ctypes.byref(self._opts),
+                    ctypes.c_void_p(self.state.data_ptr()), sb,
+                    ctypes.c_void_p(self.accum.data_ptr()), ab,
+                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                    "fnlb_init_static_work")
+        else:
+            self.work = torch.empty(wb, dtype=torch.uint8, device=self.device)
+            _check(lib.fnlb_init(self._params, len(self.reps), ctypes.byref(self._opts),
+                                 ctypes.c_void_p(self.state.data_ptr()), sb,
+                                 ctypes.c_void_p(self.accum.data_ptr()), ab,
+                                 ctypes.c_void_p(self.work.data_ptr()), wb,
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                   "fnlb_init")
         self._h = h
 
     # -- lifetime --
