@@ -106,6 +106,50 @@ def storage_agreement(F, reps, every: int, steps: int = 200) -> dict:
             "populations_rel": float(f"{df:.3g}")}
 
 
+def equal_error(F, reps, every: int, warm: int = 500, n_blocks: int = 10,
+                block_samples: int = 20) -> dict:
+    """The survey's "equal S(q) error" check on the benchmark's own replicas.
+    Both storage forms run the same replicas with the same seeds (the same
+    noise).  After `warm` steps the accumulators are cleared; then
+    `n_blocks` blocks of `block_samples` samples each are summed separately.
+    From the FP64 blocks, eps_S is the relative standard error of the block
+    means of S_c(q_x, 0) (k_z = 0), averaged over the band k_x >= 1 of every
+    replica.  The FP32-deviation result over the same blocks must differ from
+    the FP64 one by much less: `max_rel_diff` is the largest
+    |S32 - S64| / S64 over that band (block means), `ratio` = that / eps_S,
+    and the bar is 0.1."""
+    import numpy as np
+    lats = {p: F.Lattice(reps, precision=p, sample_every=every) for p in (F.FP64, F.FP32_DEV)}
+    blocks = {p: [] for p in lats}
+    for p, lat in lats.items():
+        lat.step(warm)
+        lat.reset_accumulators()
+        for _ in range(n_blocks):
+            lat.step(block_samples * every)
+            row = []
+            for i in range(len(reps)):
+                a2, re, im, n = lat.read_structure_factor(i, F.FIELD_C)
+                S = a2 / n - (re / n) ** 2 - (im / n) ** 2
+                row.append(S[0, 1:].copy())
+            blocks[p].append(row)
+            lat.reset_accumulators()
+        lat.close()
+    rel_se, diff = [], []
+    for i in range(len(reps)):
+        b64 = np.array([blk[i] for blk in blocks[F.FP64]])      # [block][k_x]
+        b32 = np.array([blk[i] for blk in blocks[F.FP32_DEV]])
+        m64 = b64.mean(axis=0)
+        se = b64.std(axis=0, ddof=1) / np.sqrt(n_blocks)
+        rel_se.append(se / m64)
+        diff.append(np.abs(b32.mean(axis=0) - m64) / m64)
+    eps = float(np.mean(np.concatenate(rel_se)))
+    dmax = float(np.max(np.concatenate(diff)))
+    return {"eps_S": float(f"{eps:.3g}"), "max_rel_diff": float(f"{dmax:.3g}"),
+            "ratio": float(f"{dmax / eps:.3g}"), "bar": 0.1,
+            "blocks": n_blocks, "samples_per_block": block_samples, "warm_steps": warm,
+            "field": "S_c(q_x, 0), k_x >= 1, every replica"}
+
+
 def adjoint_leg(F, W, reps_done: int = 3) -> dict:
     """Time of one gradient of the structure-factor misfit by the adjoint
     (256 x 128 FP64, horizon 2000 sampled every 10, checkpoints every 100),
@@ -555,6 +599,9 @@ def main():
             out["compare"][name] = round(n_nodes * n64 / (ms64 / 1e3) / 1e6, 1)
             del lat64
         out["compare"]["fp32_vs_fp64_storage"] = storage_agreement(F, reps, every)
+        out["compare"]["equal_error"] = equal_error(F, reps, every)
+        out["compare"]["speedup_vs_fp64_single_512x256"] = round(
+            out["value"] / out["compare"]["fp64_single_512x256_mlups"], 2)
         out["compare"]["note"] = (f"plain FP64 storage, sampled every {every} steps; both "
                                   "storage forms give S(q) within 1e-5 of the FP64 oracle "
                                   "(parity tests) and of each other (fp32_vs_fp64_storage), far "

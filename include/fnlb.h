@@ -219,6 +219,15 @@ int fnlb_write_populations(fnlb_handle* h, int32_t rep, const double* in);
  * Asynchronous. */
 int fnlb_reset_accumulators(fnlb_handle* h);
 
+/* Replaces the physical parameters and seeds of every replica (n_rep and each
+ * Lx, Lz must equal the handle's, else FNLB_EINVAL) and starts over as
+ * fnlb_init does: rest state on the imposed profile, t = 0, accumulators
+ * cleared.  Buffers, work items, autotuned row ranges and captured graphs are
+ * kept, so a caller that evaluates many parameter sets on one shape (a
+ * parameter scan, an optimisation loop) creates one handle.  Synchronises the
+ * stream. */
+int fnlb_reinit(fnlb_handle* h, const fnlb_replica_params* reps, int32_t n_rep);
+
 /* Current time t (number of steps taken since init). */
 int fnlb_get_time(const fnlb_handle* h, int64_t* t);
 
@@ -248,9 +257,42 @@ int fnlb_load(fnlb_handle* h, const void* host_buf, size_t n);
  * of `horizon` steps with populations checkpointed every `ckpt_every` steps:
  * ceil(horizon/ckpt_every) + ckpt_every + 2 state copies plus O(Lx Lz)
  * adjoint fields.  FNLB_EINVAL when the handle does not meet the
- * requirements of fnlb_sq_misfit_gradient. */
+ * requirements of fnlb_sq_misfit_gradient (sampling aside). */
 int fnlb_adjoint_bytes_required(const fnlb_handle* h, int64_t horizon, int32_t ckpt_every,
                                 size_t* bytes);
+
+/* Forward half of fnlb_sq_misfit_gradient: J only.  Runs the forward sweep
+ * (populations checkpointed every ckpt_every steps in d_adj) and leaves in
+ * d_adj what fnlb_misfit_backward needs to differentiate it.  Requirements,
+ * workspace and effects as for fnlb_sq_misfit_gradient. */
+int fnlb_sq_misfit(fnlb_handle* h, int32_t field, const double* S_target,
+                   const double* weight, int64_t horizon, int32_t ckpt_every,
+                   void* d_adj, size_t adj_bytes, double* J);
+
+/* Forward half of fnlb_pressure_misfit_gradient: J only (as fnlb_sq_misfit). */
+int fnlb_pressure_misfit(fnlb_handle* h, const double* P_target, const double* weight,
+                         int64_t horizon, int32_t ckpt_every, void* d_adj,
+                         size_t adj_bytes, double* J);
+
+/* Reverse half: grad = dJ/d(tau_s, tau_d, G) of the last fnlb_sq_misfit or
+ * fnlb_pressure_misfit on this handle, by the adjoint sweep over its
+ * checkpoints.  d_adj and adj_bytes must be those of that call, its contents
+ * untouched, and the handle's time unchanged since (else FNLB_ESTATE;
+ * fnlb_reinit and a failed misfit call also end the pairing).  May be called
+ * again for the same forward sweep.  Synchronises the stream. */
+int fnlb_misfit_backward(fnlb_handle* h, void* d_adj, size_t adj_bytes, double* grad);
+
+/* Vector-Jacobian product of one step of the current state f(t) (Eq. (6)
+ * with the collision of Eq. (14), noise of Eqs. (22)-(23) held fixed):
+ * given mu_next = dJ/df(t+1), returns mu = (df(t+1)/df(t))^T mu_next and
+ * dtheta = mu_next . df(t+1)/d(tau_s, tau_d, G).  mu_next and mu: host
+ * arrays in the layout of fnlb_read_populations ([species][l][z][x],
+ * 2*9*Lz*Lx doubles); dtheta: 3 doubles.  Requirements as for
+ * fnlb_sq_misfit_gradient except sampling (any sample_every); workspace:
+ * d_adj of adj_bytes >= fnlb_adjoint_bytes_required(h, 1, 1).  The handle's
+ * state and time are unchanged.  Synchronises the stream. */
+int fnlb_step_vjp(fnlb_handle* h, const double* mu_next, double* mu, double* dtheta,
+                  void* d_adj, size_t adj_bytes);
 
 /* Structure-factor misfit and its gradient by the discrete adjoint of the
  * step, with the noise stream held fixed (the Gaussian variates of every node

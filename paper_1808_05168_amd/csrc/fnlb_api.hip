@@ -313,6 +313,15 @@ struct fnlb_handle {
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int64_t period = 0;
   int static_dev = -1;   // device whose static workspace this handle holds, or -1
+  // the last forward sweep of a misfit, kept for its reverse sweep
+  struct {
+    bool valid = false;
+    const void* d_adj = nullptr;
+    size_t bytes = 0;
+    int64_t horizon = 0, t0 = 0, nsamp = 0;
+    int32_t K = 0, field = 0;
+    bool pressure = false;
+  } adj;
 
   RepInfo* d_reps() { return (RepInfo*)(work + plan.o_reps); }
   Item* d_items() { return (Item*)(work + plan.o_items); }
@@ -835,6 +844,41 @@ int fnlb_reset_accumulators(fnlb_handle* h) {
   return FNLB_OK;
 }
 
+int fnlb_reinit(fnlb_handle* h, const fnlb_replica_params* reps, int32_t n_rep) {
+  if (!h || !reps) return FNLB_EINVAL;
+  if (h->error) return h->error;
+  if (n_rep != (int32_t)h->reps.size()) return FNLB_EINVAL;
+  for (int r = 0; r < n_rep; ++r)
+    if (reps[r].Lx != h->reps[r].Lx || reps[r].Lz != h->reps[r].Lz) return FNLB_EINVAL;
+  const int rc = validate(reps, n_rep, &h->opt);
+  if (rc) return rc;
+  // same shapes and row ranges: the same buffer plan, work items, transform
+  // tables and twiddles; only the replica table changes, so the captured
+  // graphs stay valid
+  fnlb_options o = h->opt;
+  o.chunk_rows = h->plan.chunk;
+  Plan P;
+  make_plan(reps, n_rep, &o, P);
+  for (RepInfo& R : P.info) R.bm = (const BmTables*)(h->work + h->plan.o_bm);
+  h->reps.assign(reps, reps + n_rep);
+  h->plan.info = P.info;
+  h->adj.valid = false;
+  const Plan& Q = h->plan;
+  hipStream_t s = h->stream;
+  hipError_t e = hipMemcpyAsync(h->work + Q.o_reps, Q.info.data(), Q.info.size() * sizeof(RepInfo),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_fill_zero(h->work + Q.o_misc, 16, s);
+  if (e == hipSuccess) e = launch_fill_zero(h->work + Q.o_ppart, Q.work_bytes - Q.o_ppart, s);
+  if (e == hipSuccess) e = launch_fill_zero(h->state, Q.state_bytes, s);
+  if (e == hipSuccess) e = launch_fill_zero(h->accum, Q.accum_bytes, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dev_err(h, e);
+  h->cur = 0;
+  h->t = h->t_dev = 0;
+  h->nsamples = 0;
+  return FNLB_OK;
+}
+
 int fnlb_get_time(const fnlb_handle* h, int64_t* t) {
   if (!h || !t) return FNLB_EINVAL;
   *t = h->t;
@@ -959,8 +1003,7 @@ struct AdjPlan {
 };
 
 int adj_plan(const fnlb_handle* h, int64_t horizon, int32_t K, AdjPlan& A) {
-  if (h->reps.size() != 1 || h->opt.precision != FNLB_FP64 || h->opt.sample_every <= 0)
-    return FNLB_EINVAL;
+  if (h->reps.size() != 1 || h->opt.precision != FNLB_FP64) return FNLB_EINVAL;
   if ((h->opt.flags & ~FNLB_NO_GRAPH) != (FNLB_ASTAR | FNLB_WALL_UZ_FIX)) return FNLB_EINVAL;
   if (horizon < 1 || K < 1) return FNLB_EINVAL;
   const RepInfo& R = h->plan.info[0];
@@ -1012,61 +1055,80 @@ int fnlb_adjoint_bytes_required(const fnlb_handle* h, int64_t horizon, int32_t c
 
 namespace {
 
-// The checkpointed adjoint of a misfit over a horizon: the structure factor of
-// `field` (pressure false) or the pressure row profile (pressure true).
-int adjoint_gradient(fnlb_handle* h, bool pressure, int32_t field, const double* S_target,
-                     const double* weight, int64_t horizon, int32_t ckpt_every, void* d_adj,
-                     size_t adj_bytes, double* J, double* grad) {
-  if (!h || !S_target || !weight || !d_adj || !J || !grad) return FNLB_EINVAL;
-  if (h->error) return h->error;
+// Pointers of the adjoint workspace and of the handle that both sweeps use.
+struct AdjCtx {
+  fnlb_handle* h;
   AdjPlan A;
-  int rc = adj_plan(h, horizon, ckpt_every, A);
-  if (rc) return rc;
-  if (adj_bytes < A.total) return FNLB_ENOMEM;
-  if ((uintptr_t)d_adj % kAlign) return FNLB_EINVAL;
-  char* W = (char*)d_adj;
-  hipStream_t s = h->stream;
-  const RepInfo& R = h->plan.info[0];
-  const RepInfo* dR = h->d_reps();
-  const size_t SH = h->plan.state_half, N = (size_t)R.Lx * R.Lz;
-  const size_t P = (size_t)R.Lz * (R.Lx / 2 + 1);
-  const int every = h->opt.sample_every;
-  const int64_t t0 = h->t;
-  const int K = ckpt_every;
-  auto ckpt = [&](int64_t k) { return W + A.ckpt + (size_t)k * SH; };
-  auto seg = [&](int64_t k) { return W + A.seg + (size_t)k * SH; };
-  char* mu[2] = {W + A.mu, W + A.mu + SH};
-  double* acc = (double*)(W + A.acc);
-  double* theta = (double*)(W + A.small);
-  double* dJ = theta + 4;
-  auto sampled = [&](int64_t t) { return t >= 1 && t % every == 0; };
+  char* W;
+  hipStream_t s;
+  const RepInfo* R;
+  const RepInfo* dR;
+  size_t SH, N, P;
+  int every;
+  double* acc;
+  double* theta;  // [0..2] parameter partials, [4] J
+  char* mu[2];
+
+  AdjCtx(fnlb_handle* hh, const AdjPlan& a, void* d_adj)
+      : h(hh), A(a), W((char*)d_adj), s(hh->stream), R(&hh->plan.info[0]), dR(hh->d_reps()),
+        SH(hh->plan.state_half), N((size_t)R->Lx * R->Lz), P((size_t)R->Lz * (R->Lx / 2 + 1)),
+        every(hh->opt.sample_every), acc((double*)(W + a.acc)), theta((double*)(W + a.small)) {
+    mu[0] = W + A.mu;
+    mu[1] = W + A.mu + SH;
+  }
+  char* ckpt(int64_t k) const { return W + A.ckpt + (size_t)k * SH; }
+  char* seg(int64_t k) const { return W + A.seg + (size_t)k * SH; }
+  bool sampled(int64_t t) const { return every > 0 && t >= 1 && t % every == 0; }
   // The step of a sample time runs the sampling variant of the step kernel
   // both in the forward sweep and when a segment is recomputed, so that every
   // recomputed state is bit-identical to the forward one whatever the
   // checkpoint interval (the two kernel variants may round differently).
-  auto step_from = [&](const char* in, char* out, int64_t t, bool observe_sample) {
+  hipError_t step_from(const char* in, char* out, int64_t t, bool observe_sample) const {
     StepArgs a = step_args(h, t - h->t_dev);
     a.state_in = in;
     a.state_out = out;
     hipError_t e = launch_step(FNLB_FP64, sampled(t) ? kStepSample : kStep, a, s);
     if (e == hipSuccess && observe_sample && sampled(t)) e = observe(h, s, acc);
     return e;
-  };
+  }
+};
 
-  const size_t nt = pressure ? (size_t)R.Lz : P;  // target and weight entries
-  hipError_t e = hipMemcpyAsync(W + A.target, S_target, nt * 8, hipMemcpyHostToDevice, s);
+// Forward sweep of a misfit over a horizon (the structure factor of `field`,
+// or with `pressure` the pressure row profile): populations checkpointed every
+// ckpt_every steps and the samples summed privately in the workspace, then J
+// and its sensitivities to the sampled spectrum (or row profile).  The handle
+// remembers the sweep so that misfit_reverse can differentiate it.
+int misfit_forward(fnlb_handle* h, bool pressure, int32_t field, const double* target,
+                   const double* weight, int64_t horizon, int32_t ckpt_every, void* d_adj,
+                   size_t adj_bytes, double* J) {
+  if (!h || !target || !weight || !d_adj || !J) return FNLB_EINVAL;
+  if (h->error) return h->error;
+  h->adj.valid = false;
+  if (h->opt.sample_every <= 0) return FNLB_EINVAL;
+  AdjPlan A;
+  int rc = adj_plan(h, horizon, ckpt_every, A);
+  if (rc) return rc;
+  if (adj_bytes < A.total) return FNLB_ENOMEM;
+  if ((uintptr_t)d_adj % kAlign) return FNLB_EINVAL;
+  const AdjCtx C(h, A, d_adj);
+  char* W = C.W;
+  hipStream_t s = C.s;
+  const int64_t t0 = h->t;
+  const int K = ckpt_every;
+  double* dJ = C.theta + 4;
+  const size_t nt = pressure ? (size_t)C.R->Lz : C.P;  // target and weight entries
+  hipError_t e = hipMemcpyAsync(W + A.target, target, nt * 8, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(W + A.weight, weight, nt * 8, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_fill_zero(acc, h->plan.accum_bytes, s);
+  if (e == hipSuccess) e = launch_fill_zero(C.acc, h->plan.accum_bytes, s);
   if (e == hipSuccess) e = launch_fill_zero(W + A.small, 64, s);
-  // forward sweep: checkpoints every K steps, samples into private sums
   if (e == hipSuccess)
-    e = hipMemcpyAsync(mu[0], h->state_copy(h->cur), SH, hipMemcpyDeviceToDevice, s);
+    e = hipMemcpyAsync(C.mu[0], h->state_copy(h->cur), C.SH, hipMemcpyDeviceToDevice, s);
   int64_t nsamp = 0;
   int cur = 0;
   for (int64_t k = 0; k < horizon && e == hipSuccess; ++k) {
-    if (k % K == 0) e = hipMemcpyAsync(ckpt(k / K), mu[cur], SH, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = step_from(mu[cur], mu[cur ^ 1], t0 + k, true);
-    if (sampled(t0 + k)) ++nsamp;
+    if (k % K == 0) e = hipMemcpyAsync(C.ckpt(k / K), C.mu[cur], C.SH, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = C.step_from(C.mu[cur], C.mu[cur ^ 1], t0 + k, true);
+    if (C.sampled(t0 + k)) ++nsamp;
     cur ^= 1;
   }
   if (nsamp == 0) return e == hipSuccess ? FNLB_EINVAL : dev_err(h, e);
@@ -1074,80 +1136,200 @@ int adjoint_gradient(fnlb_handle* h, bool pressure, int32_t field, const double*
   if (pressure) {
     // Wq holds lam_j = dJ/d(P - P_ref) of a node of row j in one sample
     if (e == hipSuccess)
-      e = launch_adj_pmisfit(dR, R, acc, (const double*)(W + A.target),
+      e = launch_adj_pmisfit(C.dR, *C.R, C.acc, (const double*)(W + A.target),
                              (const double*)(W + A.weight), ns, (double*)(W + A.Wq), dJ, s);
   } else {
     if (e == hipSuccess)
-      e = launch_adj_misfit(dR, R, h->d_tw(), acc, (const double*)(W + A.target),
+      e = launch_adj_misfit(C.dR, *C.R, h->d_tw(), C.acc, (const double*)(W + A.target),
                             (const double*)(W + A.weight), (double*)(W + A.Wq),
                             (double2*)(W + A.mean), (double*)(W + A.jpart), field, ns, s);
     if (e == hipSuccess)
-      e = launch_sum((const double*)(W + A.jpart), (int)((P + 255) / 256), dJ, s);
+      e = launch_sum((const double*)(W + A.jpart), (int)((C.P + 255) / 256), dJ, s);
   }
-  // reverse sweep over the checkpointed segments; the parameter partials of
-  // each block run over the whole sweep and are summed once at its end
-  if (e == hipSuccess) e = launch_fill_zero(mu[0], 2 * SH, s);
-  if (e == hipSuccess) e = launch_fill_zero(W + A.tpart, ((N + 63) / 64) * 3 * 8, s);
+  double Jv = 0.0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&Jv, dJ, 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dev_err(h, e);
+  *J = Jv;
+  h->adj.valid = true;
+  h->adj.d_adj = d_adj;
+  h->adj.bytes = adj_bytes;
+  h->adj.horizon = horizon;
+  h->adj.t0 = t0;
+  h->adj.nsamp = nsamp;
+  h->adj.K = K;
+  h->adj.field = field;
+  h->adj.pressure = pressure;
+  return FNLB_OK;
+}
+
+// Reverse sweep of the last forward sweep over the same workspace: per
+// checkpointed segment the states are recomputed with the step kernel, then
+// each step is differentiated backwards; dJ/d(tau_s, tau_d, G) into grad.
+int misfit_reverse(fnlb_handle* h, void* d_adj, size_t adj_bytes, double* grad) {
+  if (!h || !d_adj || !grad) return FNLB_EINVAL;
+  if (h->error) return h->error;
+  if (!h->adj.valid || h->adj.d_adj != d_adj || h->adj.bytes != adj_bytes ||
+      h->t != h->adj.t0)
+    return FNLB_ESTATE;
+  AdjPlan A;
+  const int rc = adj_plan(h, h->adj.horizon, h->adj.K, A);
+  if (rc) return rc;
+  const AdjCtx C(h, A, d_adj);
+  char* W = C.W;
+  hipStream_t s = C.s;
+  const int64_t t0 = h->adj.t0, horizon = h->adj.horizon;
+  const int K = h->adj.K, field = h->adj.field;
+  const bool pressure = h->adj.pressure;
+  const double ns = (double)h->adj.nsamp;
+  // the parameter partials of each block run over the whole sweep and are
+  // summed once at its end (J, in theta[4], is kept)
+  hipError_t e = launch_fill_zero(C.theta, 32, s);
+  if (e == hipSuccess) e = launch_fill_zero(C.mu[0], 2 * C.SH, s);
+  if (e == hipSuccess) e = launch_fill_zero(W + A.tpart, ((C.N + 63) / 64) * 3 * 8, s);
   int nx = 0;  // mu[nx] holds dJ/dS_{t+1}
   for (int64_t sgi = A.nck - 1; sgi >= 0 && e == hipSuccess; --sgi) {
     const int64_t ts = sgi * K, te = std::min<int64_t>(horizon, ts + K);
-    e = hipMemcpyAsync(seg(0), ckpt(sgi), SH, hipMemcpyDeviceToDevice, s);
+    e = hipMemcpyAsync(C.seg(0), C.ckpt(sgi), C.SH, hipMemcpyDeviceToDevice, s);
     for (int64_t k = ts; k + 1 < te && e == hipSuccess; ++k)
-      e = step_from(seg(k - ts), seg(k - ts + 1), t0 + k, false);
+      e = C.step_from(C.seg(k - ts), C.seg(k - ts + 1), t0 + k, false);
     for (int64_t k = te - 1; k >= ts && e == hipSuccess; --k) {
-      const double* S = (const double*)seg(k - ts);
-      e = launch_adj_density(dR, R, S, (double*)(W + A.dens), s);
+      const double* S = (const double*)C.seg(k - ts);
+      e = launch_adj_density(C.dR, *C.R, S, (double*)(W + A.dens), s);
       const double* adjf = nullptr;
-      if (e == hipSuccess && sampled(t0 + k)) {
+      if (e == hipSuccess && C.sampled(t0 + k)) {
         if (pressure)
-          e = launch_adj_psample(dR, R, (const double*)(W + A.dens), (const double*)(W + A.Wq),
-                                 (double*)(W + A.adjf), (double*)(W + A.tpart), s);
+          e = launch_adj_psample(C.dR, *C.R, (const double*)(W + A.dens),
+                                 (const double*)(W + A.Wq), (double*)(W + A.adjf),
+                                 (double*)(W + A.tpart), s);
         else
-          e = launch_adj_sample(dR, R, h->d_tw(), (const double*)(W + A.Wq),
+          e = launch_adj_sample(C.dR, *C.R, h->d_tw(), (const double*)(W + A.Wq),
                                 (const double2*)(W + A.mean), field, ns,
                                 (const double*)(W + A.dens), (double2*)(W + A.rows),
                                 (double2*)(W + A.Gq), (double*)(W + A.adjf), s);
         adjf = (const double*)(W + A.adjf);
       }
       if (e == hipSuccess)
-        e = launch_adj_step(dR, R, S, (const double*)mu[nx], (double*)mu[nx ^ 1],
+        e = launch_adj_step(C.dR, *C.R, S, (const double*)C.mu[nx], (double*)C.mu[nx ^ 1],
                             (double*)(W + A.dens), (double*)(W + A.gf), (double*)(W + A.gs),
                             adjf, pressure ? kAdjPressure : field, t0 + k,
                             (double*)(W + A.tpart), s);
       nx ^= 1;
     }
   }
-  if (e == hipSuccess) e = launch_adj_theta(R, (const double*)(W + A.tpart), theta, s);
-  double out[5] = {0, 0, 0, 0, 0};
-  if (e == hipSuccess) e = hipMemcpyAsync(out, theta, 5 * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = launch_adj_theta(*C.R, (const double*)(W + A.tpart), C.theta, s);
+  double out[3] = {0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(out, C.theta, 3 * 8, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return dev_err(h, e);
   // dJ/dlambda -> dJ/dtau with lambda = 1/tau
-  const double ls = R.lam[4], ld = R.lam[1];
-  *J = out[4];
+  const double ls = C.R->lam[4], ld = C.R->lam[1];
   grad[0] = -ls * ls * out[0];
   grad[1] = -ld * ld * out[1];
   grad[2] = out[2];
   return FNLB_OK;
 }
 
+// Host conversion between the caller's layout [species][l][z][x] of the
+// populations f(t) and the stored elements of one replica: the element that
+// holds f_l(x, z) is pull_source(), a bijection, so a cotangent moves between
+// the two layouts by the same permutation (the reference shifts of the stored
+// deviations are constants and drop out).
+void to_stored(const RepInfo& R, const double* user, double* stored) {
+  const size_t n = (size_t)R.Lz * R.Lx;
+  for (int s = 0; s < 2; ++s)
+    for (int l = 0; l < 9; ++l)
+      for (int j = 0; j < R.Lz; ++j)
+        for (int x = 0; x < R.Lx; ++x)
+          stored[pull_source(R, s, l, j, x)] = user[(size_t)(s * 9 + l) * n + (size_t)j * R.Lx + x];
+}
+
+void from_stored(const RepInfo& R, const double* stored, double* user) {
+  const size_t n = (size_t)R.Lz * R.Lx;
+  for (int s = 0; s < 2; ++s)
+    for (int l = 0; l < 9; ++l)
+      for (int j = 0; j < R.Lz; ++j)
+        for (int x = 0; x < R.Lx; ++x)
+          user[(size_t)(s * 9 + l) * n + (size_t)j * R.Lx + x] = stored[pull_source(R, s, l, j, x)];
+}
+
 }  // namespace
 
 extern "C" {
 
+int fnlb_sq_misfit(fnlb_handle* h, int32_t field, const double* S_target, const double* weight,
+                   int64_t horizon, int32_t ckpt_every, void* d_adj, size_t adj_bytes,
+                   double* J) {
+  if (field != 0 && field != 1) return FNLB_EINVAL;
+  return misfit_forward(h, false, field, S_target, weight, horizon, ckpt_every, d_adj, adj_bytes,
+                        J);
+}
+
+int fnlb_pressure_misfit(fnlb_handle* h, const double* P_target, const double* weight,
+                         int64_t horizon, int32_t ckpt_every, void* d_adj, size_t adj_bytes,
+                         double* J) {
+  return misfit_forward(h, true, 0, P_target, weight, horizon, ckpt_every, d_adj, adj_bytes, J);
+}
+
+int fnlb_misfit_backward(fnlb_handle* h, void* d_adj, size_t adj_bytes, double* grad) {
+  return misfit_reverse(h, d_adj, adj_bytes, grad);
+}
+
 int fnlb_sq_misfit_gradient(fnlb_handle* h, int32_t field, const double* S_target,
                             const double* weight, int64_t horizon, int32_t ckpt_every,
                             void* d_adj, size_t adj_bytes, double* J, double* grad) {
-  if (field != 0 && field != 1) return FNLB_EINVAL;
-  return adjoint_gradient(h, false, field, S_target, weight, horizon, ckpt_every, d_adj,
-                          adj_bytes, J, grad);
+  if (!grad) return FNLB_EINVAL;
+  const int rc = fnlb_sq_misfit(h, field, S_target, weight, horizon, ckpt_every, d_adj,
+                                adj_bytes, J);
+  return rc ? rc : misfit_reverse(h, d_adj, adj_bytes, grad);
 }
 
 int fnlb_pressure_misfit_gradient(fnlb_handle* h, const double* P_target, const double* weight,
                                   int64_t horizon, int32_t ckpt_every, void* d_adj,
                                   size_t adj_bytes, double* J, double* grad) {
-  return adjoint_gradient(h, true, 0, P_target, weight, horizon, ckpt_every, d_adj, adj_bytes,
-                          J, grad);
+  if (!grad) return FNLB_EINVAL;
+  const int rc = fnlb_pressure_misfit(h, P_target, weight, horizon, ckpt_every, d_adj,
+                                      adj_bytes, J);
+  return rc ? rc : misfit_reverse(h, d_adj, adj_bytes, grad);
+}
+
+int fnlb_step_vjp(fnlb_handle* h, const double* mu_next, double* mu, double* dtheta, void* d_adj,
+                  size_t adj_bytes) {
+  if (!h || !mu_next || !mu || !dtheta || !d_adj) return FNLB_EINVAL;
+  if (h->error) return h->error;
+  AdjPlan A;
+  const int rc = adj_plan(h, 1, 1, A);
+  if (rc) return rc;
+  if (adj_bytes < A.total) return FNLB_ENOMEM;
+  if ((uintptr_t)d_adj % kAlign) return FNLB_EINVAL;
+  const AdjCtx C(h, A, d_adj);
+  const RepInfo& R = *C.R;
+  const size_t nel = 18 * (size_t)R.plane;  // stored elements of the replica
+  std::vector<double> st(nel, 0.0);
+  to_stored(R, mu_next, st.data());
+  hipStream_t s = C.s;
+  const double* S = (const double*)h->state_copy(h->cur);
+  hipError_t e = launch_fill_zero(C.mu[0], 2 * C.SH, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(C.mu[0], st.data(), nel * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_fill_zero(C.theta, 32, s);
+  if (e == hipSuccess) e = launch_fill_zero(C.W + A.tpart, ((C.N + 63) / 64) * 3 * 8, s);
+  if (e == hipSuccess) e = launch_adj_density(C.dR, R, S, (double*)(C.W + A.dens), s);
+  if (e == hipSuccess)
+    e = launch_adj_step(C.dR, R, S, (const double*)C.mu[0], (double*)C.mu[1],
+                        (double*)(C.W + A.dens), (double*)(C.W + A.gf), (double*)(C.W + A.gs),
+                        nullptr, 0, h->t, (double*)(C.W + A.tpart), s);
+  if (e == hipSuccess) e = launch_adj_theta(R, (const double*)(C.W + A.tpart), C.theta, s);
+  double out[3] = {0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(st.data(), C.mu[1], nel * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, C.theta, 3 * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return dev_err(h, e);
+  from_stored(R, st.data(), mu);
+  const double ls = R.lam[4], ld = R.lam[1];
+  dtheta[0] = -ls * ls * out[0];
+  dtheta[1] = -ld * ld * out[1];
+  dtheta[2] = out[2];
+  return FNLB_OK;
 }
 
 int fnlb_destroy(fnlb_handle* h) {

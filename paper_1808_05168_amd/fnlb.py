@@ -48,7 +48,8 @@ EXPORTS = ["fnlb_bytes_required", "fnlb_init", "fnlb_step", "fnlb_autotune",
            "fnlb_reset_accumulators", "fnlb_get_time", "fnlb_set_time", "fnlb_destroy",
            "fnlb_strerror", "fnlb_adjoint_bytes_required", "fnlb_sq_misfit_gradient",
            "fnlb_checkpoint_bytes", "fnlb_save", "fnlb_load", "fnlb_pressure_misfit_gradient",
-           "fnlb_build_id", "fnlb_init_static_work"]
+           "fnlb_build_id", "fnlb_init_static_work", "fnlb_reinit", "fnlb_sq_misfit",
+           "fnlb_pressure_misfit", "fnlb_misfit_backward", "fnlb_step_vjp"]
 STATIC_WORK_BYTES = 128 << 20  # FNLB_STATIC_WORK_BYTES
 
 
@@ -93,6 +94,13 @@ def load(path: str = LIB_PATH):
                                             ctypes.c_int32, vp, ctypes.c_size_t, dp, dp]
     lib.fnlb_pressure_misfit_gradient.argtypes = [vp, dp, dp, ctypes.c_int64, ctypes.c_int32,
                                                   vp, ctypes.c_size_t, dp, dp]
+    lib.fnlb_sq_misfit.argtypes = [vp, ctypes.c_int32, dp, dp, ctypes.c_int64, ctypes.c_int32,
+                                   vp, ctypes.c_size_t, dp]
+    lib.fnlb_pressure_misfit.argtypes = [vp, dp, dp, ctypes.c_int64, ctypes.c_int32, vp,
+                                         ctypes.c_size_t, dp]
+    lib.fnlb_misfit_backward.argtypes = [vp, vp, ctypes.c_size_t, dp]
+    lib.fnlb_step_vjp.argtypes = [vp, dp, dp, dp, vp, ctypes.c_size_t]
+    lib.fnlb_reinit.argtypes = [vp, rp, ctypes.c_int32]
     lib.fnlb_checkpoint_bytes.argtypes = [vp, szp]
     lib.fnlb_save.argtypes = [vp, vp, ctypes.c_size_t]
     lib.fnlb_load.argtypes = [vp, vp, ctypes.c_size_t]
@@ -182,6 +190,8 @@ class Lattice:
                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
                    "fnlb_init")
         self._h = h
+        self._adj_ws = None       # adjoint workspace, kept between forward and backward
+        self._misfit_token = 0    # counts forward sweeps (and reinits) of this handle
 
     # -- lifetime --
     def close(self) -> None:
@@ -209,27 +219,81 @@ class Lattice:
                "fnlb_autotune")
         return int(c.value)
 
-    def sq_misfit_gradient(self, S_target: np.ndarray, weight: np.ndarray, horizon: int,
-                           ckpt_every: int = 100, field: int = FIELD_C):
-        """(J, dJ/d(tau_s, tau_d, G)) of J = sum_q w_q (S(q) - S*(q))^2 over
-        `horizon` steps from the current state, by the adjoint of the step."""
+    def reinit(self, reps: Iterable) -> None:
+        """New parameters and seeds for the same shapes; back to the rest state
+        at t = 0 with cleared accumulators (buffers and graphs are kept)."""
+        reps = list(reps)
+        p = replica_params(reps)
+        _check(self._lib.fnlb_reinit(self._h, p, len(reps)), "fnlb_reinit")
+        self.reps, self._params = reps, p
+        self._misfit_token += 1
+
+    def _adj_workspace(self, horizon: int, ckpt_every: int):
         import torch
-        r = self.reps[0]
-        St = np.ascontiguousarray(S_target, dtype=np.float64).reshape(r.Lz, r.Lx // 2 + 1)
-        w = np.ascontiguousarray(weight, dtype=np.float64).reshape(r.Lz, r.Lx // 2 + 1)
         nb = ctypes.c_size_t()
         _check(self._lib.fnlb_adjoint_bytes_required(self._h, int(horizon), int(ckpt_every),
                                                      ctypes.byref(nb)),
                "fnlb_adjoint_bytes_required")
-        ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        if self._adj_ws is None or self._adj_ws.numel() != nb.value:
+            self._adj_ws = None
+            self._adj_ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        return ctypes.c_void_p(self._adj_ws.data_ptr()), nb.value
+
+    def _targets(self, target, weight, pressure: bool):
+        r = self.reps[0]
+        shape = (r.Lz,) if pressure else (r.Lz, r.Lx // 2 + 1)
+        return (np.ascontiguousarray(target, dtype=np.float64).reshape(shape),
+                np.ascontiguousarray(weight, dtype=np.float64).reshape(shape))
+
+    def sq_misfit(self, S_target: np.ndarray, weight: np.ndarray, horizon: int,
+                  ckpt_every: int = 100, field: int = FIELD_C) -> float:
+        """J = sum_q w_q (S(q) - S*(q))^2 over `horizon` steps from the current
+        state (forward sweep only; misfit_backward() differentiates it)."""
+        St, w = self._targets(S_target, weight, False)
+        ws, nb = self._adj_workspace(horizon, ckpt_every)
+        J = ctypes.c_double()
+        _check(self._lib.fnlb_sq_misfit(self._h, field, _dp(St), _dp(w), int(horizon),
+                                        int(ckpt_every), ws, nb, ctypes.byref(J)),
+               "fnlb_sq_misfit")
+        self._misfit_token += 1
+        return J.value
+
+    def pressure_misfit(self, P_target: np.ndarray, weight: np.ndarray, horizon: int,
+                        ckpt_every: int = 100) -> float:
+        """J = sum_j w_j (Pbar_j - P*_j)^2 over `horizon` steps from the current
+        state (forward sweep only; misfit_backward() differentiates it)."""
+        Pt, w = self._targets(P_target, weight, True)
+        ws, nb = self._adj_workspace(horizon, ckpt_every)
+        J = ctypes.c_double()
+        _check(self._lib.fnlb_pressure_misfit(self._h, _dp(Pt), _dp(w), int(horizon),
+                                              int(ckpt_every), ws, nb, ctypes.byref(J)),
+               "fnlb_pressure_misfit")
+        self._misfit_token += 1
+        return J.value
+
+    def misfit_backward(self) -> np.ndarray:
+        """dJ/d(tau_s, tau_d, G) of the last sq_misfit / pressure_misfit."""
+        if self._adj_ws is None:
+            raise FnlbError("misfit_backward needs a preceding sq_misfit or pressure_misfit")
+        g = np.zeros(3)
+        _check(self._lib.fnlb_misfit_backward(self._h, ctypes.c_void_p(self._adj_ws.data_ptr()),
+                                              self._adj_ws.numel(), _dp(g)),
+               "fnlb_misfit_backward")
+        return g
+
+    def sq_misfit_gradient(self, S_target: np.ndarray, weight: np.ndarray, horizon: int,
+                           ckpt_every: int = 100, field: int = FIELD_C):
+        """(J, dJ/d(tau_s, tau_d, G)) of J = sum_q w_q (S(q) - S*(q))^2 over
+        `horizon` steps from the current state, by the adjoint of the step."""
+        St, w = self._targets(S_target, weight, False)
+        ws, nb = self._adj_workspace(horizon, ckpt_every)
         J = ctypes.c_double()
         g = np.zeros(3)
         _check(self._lib.fnlb_sq_misfit_gradient(self._h, field, _dp(St), _dp(w), int(horizon),
-                                                 int(ckpt_every),
-                                                 ctypes.c_void_p(ws.data_ptr()), nb.value,
-                                                 ctypes.byref(J), _dp(g)),
+                                                 int(ckpt_every), ws, nb, ctypes.byref(J),
+                                                 _dp(g)),
                "fnlb_sq_misfit_gradient")
-        del ws
+        self._misfit_token += 1
         return J.value, g
 
     def pressure_misfit_gradient(self, P_target: np.ndarray, weight: np.ndarray, horizon: int,
@@ -237,24 +301,31 @@ class Lattice:
         """(J, dJ/d(tau_s, tau_d, G)) of J = sum_j w_j (Pbar_j - P*_j)^2 over
         `horizon` steps from the current state (Pbar_j: time-averaged row means
         of P - P_ref), by the adjoint of the step."""
-        import torch
-        r = self.reps[0]
-        Pt = np.ascontiguousarray(P_target, dtype=np.float64).reshape(r.Lz)
-        w = np.ascontiguousarray(weight, dtype=np.float64).reshape(r.Lz)
-        nb = ctypes.c_size_t()
-        _check(self._lib.fnlb_adjoint_bytes_required(self._h, int(horizon), int(ckpt_every),
-                                                     ctypes.byref(nb)),
-               "fnlb_adjoint_bytes_required")
-        ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        Pt, w = self._targets(P_target, weight, True)
+        ws, nb = self._adj_workspace(horizon, ckpt_every)
         J = ctypes.c_double()
         g = np.zeros(3)
         _check(self._lib.fnlb_pressure_misfit_gradient(self._h, _dp(Pt), _dp(w), int(horizon),
-                                                       int(ckpt_every),
-                                                       ctypes.c_void_p(ws.data_ptr()), nb.value,
+                                                       int(ckpt_every), ws, nb,
                                                        ctypes.byref(J), _dp(g)),
                "fnlb_pressure_misfit_gradient")
-        del ws
+        self._misfit_token += 1
         return J.value, g
+
+    def step_vjp(self, mu_next: np.ndarray):
+        """(mu, dtheta) of one step from the current state: mu = (df(t+1)/df(t))^T
+        mu_next and dtheta = mu_next . df(t+1)/d(tau_s, tau_d, G), arrays in the
+        layout of read_populations."""
+        r = self.reps[0]
+        y = np.ascontiguousarray(mu_next, dtype=np.float64)
+        if y.shape != (2, 9, r.Lz, r.Lx):
+            raise ValueError(f"cotangent of shape {y.shape}, expected {(2, 9, r.Lz, r.Lx)}")
+        mu = np.empty_like(y)
+        dth = np.zeros(3)
+        ws, nb = self._adj_workspace(1, 1)
+        _check(self._lib.fnlb_step_vjp(self._h, _dp(y), _dp(mu), _dp(dth), ws, nb),
+               "fnlb_step_vjp")
+        return mu, dth
 
     def accumulate_structure_factor(self) -> None:
         _check(self._lib.fnlb_accumulate_structure_factor(self._h),
@@ -331,8 +402,10 @@ class Lattice:
 def sq_misfit(theta, rep, S_target, weight, horizon: int, sample_every: int,
               ckpt_every: int = 100, field: int = FIELD_C, device: str = "cuda:0"):
     """Differentiable structure-factor misfit: theta = tensor([tau_s, tau_d, G]).
-    Forward runs the step from the rest state on the imposed profile; backward
-    returns the adjoint gradient (noise held fixed)."""
+    Forward runs the step from the rest state on the imposed profile and
+    returns J (one forward sweep, on a handle reused across calls); backward
+    runs the adjoint sweep over that forward sweep's checkpoints (noise held
+    fixed)."""
     return _SqMisfit.apply(theta, rep, S_target, weight, horizon, sample_every, ckpt_every,
                            field, device, "sq")
 
@@ -340,10 +413,28 @@ def sq_misfit(theta, rep, S_target, weight, horizon: int, sample_every: int,
 def p_misfit(theta, rep, P_target, weight, horizon: int, sample_every: int,
              ckpt_every: int = 100, device: str = "cuda:0"):
     """Differentiable pressure-profile misfit: theta = tensor([tau_s, tau_d, G]).
-    Forward runs the step from the rest state on the imposed profile; backward
-    returns the adjoint gradient (noise held fixed)."""
+    Forward runs the step from the rest state on the imposed profile and
+    returns J (one forward sweep, on a handle reused across calls); backward
+    runs the adjoint sweep over that forward sweep's checkpoints (noise held
+    fixed)."""
     return _SqMisfit.apply(theta, rep, P_target, weight, horizon, sample_every, ckpt_every,
                            FIELD_C, device, "p")
+
+
+_MISFIT_LATTICES = {}
+
+
+def _misfit_lattice(rep, sample_every: int, device: str) -> "Lattice":
+    """One handle per (shape, sampling interval, device), reused by the
+    differentiable misfits through fnlb_reinit."""
+    key = (rep.Lx, rep.Lz, int(sample_every), str(device))
+    lat = _MISFIT_LATTICES.get(key)
+    if lat is None:
+        lat = Lattice([rep], precision=FP64, sample_every=sample_every, device=device)
+        _MISFIT_LATTICES[key] = lat
+    else:
+        lat.reinit([rep])
+    return lat
 
 
 def _make_fn():
@@ -351,24 +442,35 @@ def _make_fn():
 
     import torch
 
+    def forward_sweep(lat, kind, target, weight, horizon, ckpt_every, field):
+        if kind == "p":
+            return lat.pressure_misfit(target, weight, horizon, ckpt_every)
+        return lat.sq_misfit(target, weight, horizon, ckpt_every, field)
+
     class SqMisfit(torch.autograd.Function):
         @staticmethod
         def forward(ctx, theta, rep, target, weight, horizon, sample_every, ckpt_every,
                     field, device, kind):
             t = [float(v) for v in theta.detach().cpu().tolist()]
             r = dataclasses.replace(rep, tau_s=t[0], tau_d=t[1], G=t[2])
-            lat = Lattice([r], precision=FP64, sample_every=sample_every, device=device)
-            if kind == "p":
-                J, g = lat.pressure_misfit_gradient(target, weight, horizon, ckpt_every)
-            else:
-                J, g = lat.sq_misfit_gradient(target, weight, horizon, ckpt_every, field)
-            lat.close()
-            ctx.save_for_backward(torch.as_tensor(g, dtype=theta.dtype))
+            lat = _misfit_lattice(r, sample_every, device)
+            J = forward_sweep(lat, kind, target, weight, horizon, ckpt_every, field)
+            ctx.lat, ctx.token = lat, lat._misfit_token
+            ctx.redo = (r, kind, target, weight, horizon, ckpt_every, field)
+            ctx.theta_dtype = theta.dtype
             return theta.new_tensor(J)
 
         @staticmethod
         def backward(ctx, gJ):
-            (g,) = ctx.saved_tensors
+            lat = ctx.lat
+            if lat._misfit_token != ctx.token:
+                # the handle has served another evaluation since this forward
+                # sweep: run it again before differentiating it
+                r, kind, target, weight, horizon, ckpt_every, field = ctx.redo
+                lat.reinit([r])
+                forward_sweep(lat, kind, target, weight, horizon, ckpt_every, field)
+                ctx.token = lat._misfit_token
+            g = torch.as_tensor(lat.misfit_backward(), dtype=ctx.theta_dtype)
             return ((gJ.cpu() * g).to(gJ.device), None, None, None, None, None, None, None, None,
                     None)
 

@@ -116,6 +116,9 @@ def phi_entries(dphi, qs):
     Lz, Lx = dphi.shape
     out = []
     for kz, kx in qs:
-        row = dphi @ np.exp(-2j * np.pi * kx * np.arange(Lx) / Lx)
-        out.append(row @ np.exp(-2j * np.pi * kz * np.arange(Lz) / Lz) / np.sqrt(Lx * Lz))
+        # angles reduced exactly in integers first: k x mod L, so the twiddles
+        # stay accurate to rounding at any size
+        row = dphi @ np.exp(-2j * np.pi * ((kx * np.arange(Lx)) % Lx) / Lx)
+        out.append(row @ np.exp(-2j * np.pi * ((kz * np.arange(Lz)) % Lz) / Lz)
+                   / np.sqrt(Lx * Lz))
     return np.array(out)

@@ -181,3 +181,94 @@ def test_pressure_autograd_function(F):
     J2, g = lat.pressure_misfit_gradient(P_t, w, H, ckpt_every=20)
     assert float(J.detach()) == J2
     np.testing.assert_array_equal(theta.grad.numpy(), g)
+
+
+def test_step_vjp_dot_product(F):
+    """Dot-product test of one adjoint step: for random y and x,
+    <(df(t+1)/df(t))^T y, x> from the adjoint kernels equals <y, A x> with A x
+    by central differences of the forward step (FP64, the noise of step t
+    reused), and the parameter partials y . df(t+1)/dtheta equal central
+    differences in tau_s, tau_d and G."""
+    rep = SMALL
+    say("case: step VJP dot product 32x16 at t = 30")
+    lat = F.Lattice([rep], precision=F.FP64, sample_every=0)
+    lat.step(30)
+    t = lat.time
+    f = lat.read_populations(0)
+    _, wts, _, _ = O.tables()
+    rng = np.random.default_rng(8)
+    y = rng.standard_normal(f.shape)
+    x = rng.standard_normal(f.shape) * 1e-3 * wts[None, :, None, None]
+    ATy, dth = lat.step_vjp(y)
+    assert lat.time == t
+    np.testing.assert_array_equal(lat.read_populations(0), f)
+
+    def one_step(g):
+        lat.write_populations(0, g)
+        lat.time = t
+        lat.step(1)
+        return lat.read_populations(0)
+
+    eps = 1e-4
+    Ax = (one_step(f + eps * x) - one_step(f - eps * x)) / (2 * eps)
+    lhs, rhs = float(np.vdot(y, Ax)), float(np.vdot(ATy, x))
+    say(f"  <y, Ax> = {lhs:.12e}  <A^T y, x> = {rhs:.12e}")
+    assert abs(lhs - rhs) <= 1e-8 * abs(lhs)
+    # parameter partials
+    for k, name in enumerate(("tau_s", "tau_d", "G")):
+        h = 1e-5 * max(abs(getattr(rep, name)), 1.0)
+        outs = []
+        for sgn in (1, -1):
+            lat.reinit([dataclasses.replace(rep, **{name: getattr(rep, name) + sgn * h})])
+            outs.append(one_step(f))
+        fd = float(np.vdot(y, (outs[0] - outs[1]) / (2 * h)))
+        say(f"  d/d{name}: adjoint {dth[k]:.10e}  differences {fd:.10e}")
+        assert abs(dth[k] - fd) <= 1e-6 * abs(fd)
+
+
+def test_misfit_forward_and_backward_halves(F):
+    """fnlb_sq_misfit (J only) and fnlb_misfit_backward give exactly what the
+    combined call gives, the backward half can be repeated, and it refuses
+    once the handle's time has moved."""
+    rep, H, every = SMALL, 60, 10
+    S_t, w = target(rep, H, every, 0)
+    lat = F.Lattice([rep], precision=F.FP64, sample_every=every)
+    J2, g2 = lat.sq_misfit_gradient(S_t, w, H, ckpt_every=20)
+    J = lat.sq_misfit(S_t, w, H, ckpt_every=20)
+    assert J == J2
+    np.testing.assert_array_equal(lat.misfit_backward(), g2)
+    np.testing.assert_array_equal(lat.misfit_backward(), g2)
+    lat.step(1)
+    with pytest.raises(F.FnlbError):
+        lat.misfit_backward()
+    P_t, pw = p_target(rep, H, every)
+    lat2 = F.Lattice([rep], precision=F.FP64, sample_every=every)
+    Jp2, gp2 = lat2.pressure_misfit_gradient(P_t, pw, H, ckpt_every=20)
+    assert lat2.pressure_misfit(P_t, pw, H, ckpt_every=20) == Jp2
+    np.testing.assert_array_equal(lat2.misfit_backward(), gp2)
+
+
+def test_reinit_equals_fresh_handle(F):
+    """fnlb_reinit with new parameters and seed is a fresh start: the same
+    populations and sums as a new handle, bit for bit, graphs included."""
+    reps = [W.Replica(Lx=64, Lz=16, grad_c0=5e-3, kT=1e-4, G=0.5, seed=41),
+            W.Replica(Lx=100, Lz=20, grad_c0=2e-3, kT=1e-4, seed=42)]
+    new = [dataclasses.replace(reps[0], tau_s=0.7, G=0.3, seed=43),
+           dataclasses.replace(reps[1], grad_c0=4e-3, kT=2e-5, seed=44)]
+    for prec in (F.FP64, F.FP32_DEV):
+        a = F.Lattice(reps, precision=prec, sample_every=5)
+        a.step(27)
+        a.reinit(new)
+        assert a.time == 0
+        a.step(33)
+        b = F.Lattice(new, precision=prec, sample_every=5)
+        b.step(33)
+        for i in range(2):
+            np.testing.assert_array_equal(a.read_populations(i), b.read_populations(i))
+            for fld in range(2):
+                for u, v in zip(a.read_structure_factor(i, fld), b.read_structure_factor(i, fld)):
+                    np.testing.assert_array_equal(u, v)
+        with pytest.raises(F.FnlbError):
+            a.reinit([dataclasses.replace(reps[0], Lx=32), reps[1]])
+        with pytest.raises(F.FnlbError):
+            a.reinit(new[:1])

@@ -300,23 +300,26 @@ def test_parity_512x256_fp64(F):
     compare_observables(lat, acc, 0, rep, TOL64)
 
 
-@pytest.mark.parametrize("shape", [(4096, 4096), (2047, 509)])
-def test_parity_maximum_sizes_fp32_deviation(F, shape):
+@pytest.mark.parametrize("shape,prec", [((4096, 4096), "fp32"), ((2047, 509), "fp32"),
+                                        ((4096, 4096), "fp64"), ((2047, 509), "fp64")])
+def test_parity_maximum_sizes(F, shape, prec):
     """The largest lattice the library accepts (4096 x 4096, power-of-two FFT
-    transforms) and the largest non-power-of-two row length (direct-sum
-    transforms): every population after 3 steps, and Phi(q) of the one sample
-    (t = 2) at selected q against direct sums over the oracle's fields."""
+    transforms; in FP64 its state copy is 2.4 GB, so byte offsets pass 2^31)
+    and the largest non-power-of-two row length (direct-sum transforms): every
+    population after 3 steps, and Phi(q) of the one sample (t = 2) at selected
+    q against direct sums over the oracle's fields."""
     Lx, Lz = shape
+    tol = TOL32 if prec == "fp32" else TOL64
     rep = W.Replica(Lx=Lx, Lz=Lz, grad_c0=1e-4, kT=1e-5, G=0.5, tau_s=0.7, seed=81)
-    say(f"case: maximum size {Lx}x{Lz} fp32-dev, 3 steps, sample at t=2")
-    lat = _gpu_run(F, [rep], 3, F.FP32_DEV, 2)
+    say(f"case: maximum size {Lx}x{Lz} {prec}, 3 steps, sample at t=2")
+    lat = _gpu_run(F, [rep], 3, F.FP32_DEV if prec == "fp32" else F.FP64, 2)
     f = O.init_state(rep)
     O.run(rep, f, 0, 2)
     _, dphi = O.fields(rep, f)
     O.run(rep, f, 2, 1)
     err = dev_norm(lat.read_populations(0), f, rep)
     say(f"  population error {err:.3e}")
-    assert err <= TOL32
+    assert err <= tol
     qs = [(0, 1), (1, 0), (1, 1), (3, 7), (Lz // 2, Lx // 2), (Lz - 1, Lx // 2), (Lz // 3, 5),
           (2, Lx // 2 - 1)]
     for fld in range(2):
@@ -327,6 +330,6 @@ def test_parity_maximum_sizes_fp32_deviation(F, shape):
         scale = np.sqrt(a2.mean())
         rel = np.abs(got - ref).max() / scale
         say(f"  field {fld}: max |dPhi| / rms |Phi| = {rel:.3e}")
-        assert rel <= TOL32
+        assert rel <= tol
         np.testing.assert_allclose([a2[kz, kx] for kz, kx in qs], np.abs(ref) ** 2,
-                                   rtol=0, atol=2 * TOL32 * scale ** 2)
+                                   rtol=0, atol=2 * tol * scale ** 2)
