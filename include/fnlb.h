@@ -63,6 +63,11 @@ extern "C" {
 #define FNLB_SAMPLE_VELOCITY 32 /* also sample U_x and U_z (fields 2, 3): the
                                 barycentric velocity of Eq. (10) after the wall
                                 fix, for S_U(q) of Sec. IV.A, Eq. (31) */
+#define FNLB_TWO_STEP 64       /* execution only: advance pairs of steps with the
+                                two-step kernel (FP32_DEV storage and every
+                                Lx <= 512, else FNLB_EINVAL) */
+#define FNLB_ONE_STEP 128      /* execution only: one step per launch, also after
+                                fnlb_autotune */
 #define FNLB_DEFAULT_FLAGS (FNLB_ASTAR | FNLB_WALL_UZ_FIX)
 
 /* ---- fields of the structure factor ---- */
@@ -157,7 +162,10 @@ int fnlb_init_static_work(const fnlb_replica_params* reps, int32_t n_rep,
  * velocity (Eq. (10)), MRT collision with forcing moments and noise (Eq. (14)),
  * then streaming with mid-way bounce-back at the walls and periodic x.
  * Samples according to options->sample_every.  All replicas advance in one
- * kernel launch per step.  Whole sampling periods (sample_every steps, or 16
+ * kernel launch per step, or per pair of steps with the two-step kernel (which
+ * keeps the state of the middle time in LDS; a pair never spans a sample time
+ * other than its first, and results equal those of single steps to FP32
+ * rounding).  Whole sampling periods (sample_every steps, or 16
  * steps without sampling) that start on a period boundary are replayed from a
  * HIP graph captured by fnlb_init or fnlb_autotune (periods longer than 1024
  * steps: on first use; none with FNLB_NO_GRAPH).  In the graph the
@@ -166,16 +174,23 @@ int fnlb_init_static_work(const fnlb_replica_params* reps, int32_t n_rep,
  * way.  Asynchronous: all of it is ordered on the caller's stream. */
 int fnlb_step(fnlb_handle* h, int64_t n);
 
-/* Chooses the number of rows each work item of the step kernel covers by
- * timing steps_per_trial >= 1 launches of each candidate (1 to 128 rows),
- * twice in turn, and keeps the one whose faster round is fastest for this
- * handle and, for the rest of the process, for
- * any handle with the same precision and set of lattice shapes created with
- * options->chunk_rows = 0.  Trial steps read the current state and write the
- * spare copy, so the state and the time are unchanged.  The period graphs are
- * captured again for the chosen work items.  Synchronises the stream;
- * *chunk_rows_out (nullable) receives the choice. */
+/* Chooses the step kernel and the number of rows each of its work items
+ * covers by timing steps_per_trial >= 1 launches of each candidate, twice in
+ * turn: the one-step kernel with 1 to 128 rows and, where it fits (FP32_DEV,
+ * every Lx <= 512), the two-step kernel with 8 to 256 rows (FNLB_ONE_STEP or
+ * FNLB_TWO_STEP restrict the choice to one kernel).  It keeps the candidate
+ * whose faster round takes the least time per step, for this handle and, for
+ * the rest of the process, for any handle with the same precision and set of
+ * lattice shapes created with options->chunk_rows = 0.  Trial launches read
+ * the current state and write the spare copy, so the state and the time are
+ * unchanged.  The period graphs are captured again for the choice.
+ * Synchronises the stream; *chunk_rows_out (nullable) receives the rows. */
 int fnlb_autotune(fnlb_handle* h, int32_t steps_per_trial, int32_t* chunk_rows_out);
+
+/* The launch configuration in use: steps each launch of the state advances
+ * (1, or 2 with the two-step kernel) and rows per work item.  Either pointer
+ * may be NULL. */
+int fnlb_launch_config(const fnlb_handle* h, int32_t* steps_per_launch, int32_t* chunk_rows);
 
 /* Samples the current state f(t) of every replica now: adds |Phi(q)|^2,
  * Re Phi(q), Im Phi(q) of delta c and delta rho (and of U_x, U_z with

@@ -5,12 +5,13 @@ pressure accumulation) runs in the HIP library ``libfnlb.so`` behind the C ABI
 of ``include/fnlb.h``; this package is its thin Python binding.
 """
 from .fnlb import (ASTAR, DEFAULT_FLAGS, FIELD_C, FIELD_RHO, FIELD_UX, FIELD_UZ, FORCE_LITERAL,
-                   FP32_DEV, FP64, NO_GRAPH, NOISE_LOC, SAMPLE_VELOCITY, STATIC_WORK_BYTES,
+                   FP32_DEV, FP64, NO_GRAPH, NOISE_LOC, ONE_STEP, SAMPLE_VELOCITY, STATIC_WORK_BYTES,
+                   TWO_STEP,
                    WALL_UZ_FIX, FnlbError,
                    Lattice, bytes_required, load, p_misfit, sq_misfit)
 
 __all__ = ["ASTAR", "DEFAULT_FLAGS", "FIELD_C", "FIELD_RHO", "FIELD_UX", "FIELD_UZ",
            "FORCE_LITERAL", "FP32_DEV", "FP64", "NO_GRAPH", "NOISE_LOC", "SAMPLE_VELOCITY",
-           "STATIC_WORK_BYTES",
+           "STATIC_WORK_BYTES", "TWO_STEP", "ONE_STEP",
            "WALL_UZ_FIX", "FnlbError", "Lattice", "bytes_required", "load", "p_misfit",
            "sq_misfit"]

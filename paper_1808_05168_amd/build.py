@@ -14,8 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfnlb.so")
-SOURCES = ["k_step.hip", "k_observe.hip", "k_adjoint.hip", "fnlb_api.hip"]
-HEADERS = ["fnlb_device.hpp", "fnlb_fft.hpp", "fnlb_internal.hpp", "fnlb_state.hpp"]
+SOURCES = ["k_step.hip", "k_step2.hip", "k_observe.hip", "k_adjoint.hip", "fnlb_api.hip"]
+HEADERS = ["fnlb_device.hpp", "fnlb_fft.hpp", "fnlb_internal.hpp", "fnlb_node.hpp",
+           "fnlb_state.hpp"]
 ARCH = os.environ.get("FNLB_OFFLOAD_ARCH", "gfx950")
 
 

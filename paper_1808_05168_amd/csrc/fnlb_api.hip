@@ -27,6 +27,8 @@ static __device__ __align__(256) char scratch[FNLB_STATIC_WORK_BYTES];
 namespace {
 
 constexpr size_t kAlign = 256;
+// option bits that choose how the steps are launched, not what they compute
+constexpr int kExecFlags = FNLB_NO_GRAPH | FNLB_TWO_STEP | FNLB_ONE_STEP;
 size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -42,13 +44,33 @@ constexpr int kColTile = 2048;  // complex values per column-transform tile (32 
 constexpr int kRowGroup = 1024;  // complex values per row-transform block (short rows share)
 constexpr int kTransformThreads = 256;  // threads of a transform block (at least one per row)
 
+// The two-step kernel takes FP32-deviation storage and whole rows of at most
+// kTBLanes columns.
+bool two_step_fits(const fnlb_replica_params* reps, int n_rep, int precision) {
+  if (precision != FNLB_FP32_DEV) return false;
+  for (int r = 0; r < n_rep; ++r)
+    if (reps[r].Lx > kTBLanes) return false;
+  return true;
+}
+
+// lanes per two-step work item: the row length rounded up to a power of two, at
+// least one wavefront
+int tb_lwidth(int Lx) {
+  int lw = 6;
+  while ((1 << lw) < Lx) ++lw;
+  return lw;
+}
+
 int validate(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options* opt) {
   if (!reps || !opt || n_rep <= 0) return FNLB_EINVAL;
   if (opt->precision != FNLB_FP64 && opt->precision != FNLB_FP32_DEV) return FNLB_EINVAL;
   if (opt->sample_every < 0 || opt->chunk_rows < 0) return FNLB_EINVAL;
   if (opt->flags &
       ~(FNLB_ASTAR | FNLB_WALL_UZ_FIX | FNLB_NOISE_LOC | FNLB_FORCE_LITERAL | FNLB_NO_GRAPH |
-        FNLB_SAMPLE_VELOCITY))
+        FNLB_SAMPLE_VELOCITY | FNLB_TWO_STEP | FNLB_ONE_STEP))
+    return FNLB_EINVAL;
+  if ((opt->flags & FNLB_TWO_STEP) && (opt->flags & FNLB_ONE_STEP)) return FNLB_EINVAL;
+  if ((opt->flags & FNLB_TWO_STEP) && !two_step_fits(reps, n_rep, opt->precision))
     return FNLB_EINVAL;
   for (int r = 0; r < n_rep; ++r) {
     const fnlb_replica_params& p = reps[r];
@@ -83,6 +105,11 @@ struct Plan {
   size_t item_capacity = 0;  // items the work buffer holds (row ranges of one row)
   int max_lx = 0, max_lz = 0, max_col_lds = 0, max_row_lds = 0, chunk = 0;
   int n_pairs = 1;  // complex row transforms per row: (dc, drho) [, (Ux, Uz)]
+  // the two-step kernel: eligibility, its blocks of work items, their capacity
+  bool tb_ok = false;
+  std::vector<PackItem> pitems;
+  size_t pitem_capacity = 0;
+  size_t o_pitems = 0;
 };
 
 // work items for a row-range length: (replica, row range, segment), with
@@ -103,6 +130,44 @@ void make_items(Plan& P, int chunk) {
   }
 }
 
+// Work items of the two-step kernel for a row-range length: per replica its
+// row ranges (alternating march direction, as for the one-step kernel), packed
+// kTBLanes >> lwidth to a block among replicas of the same lane width.  A
+// block's iteration count is its longest item's: the first-step rows (the
+// range plus two rows on each side, clipped at the walls) and two more.
+void make_pitems(Plan& P, int chunk) {
+  P.pitems.clear();
+  if (!P.tb_ok) return;
+  for (int lw = 6; (1 << lw) <= kTBLanes; ++lw) {
+    const int per_block = kTBLanes >> lw;
+    PackItem cur{};
+    cur.lwidth = lw;
+    for (size_t r = 0; r < P.info.size(); ++r) {
+      const RepInfo& R = P.info[r];
+      if (tb_lwidth(R.Lx) != lw) continue;
+      for (int j0 = 0; j0 < R.Lz; j0 += chunk) {
+        const int j1 = std::min(R.Lz, j0 + chunk);
+        const int dir = ((j0 / chunk) & 1) ? -1 : 1;
+        const int alo = std::max(j0 - 2, 0), ahi = std::min(j1 + 2, R.Lz);
+        const int niter = dir > 0 ? j1 + 2 - alo : ahi - j0 + 2;
+        const int k = cur.nsub++;
+        cur.rep[k] = (int32_t)r;
+        cur.j0[k] = j0;
+        cur.j1[k] = j1;
+        cur.dir[k] = dir;
+        // the kernel runs two iterations per loop trip
+        cur.niter = std::max(cur.niter, (niter + 1) & ~1);
+        if (cur.nsub == per_block) {
+          P.pitems.push_back(cur);
+          cur = PackItem{};
+          cur.lwidth = lw;
+        }
+      }
+    }
+    if (cur.nsub > 0) P.pitems.push_back(cur);
+  }
+}
+
 // Row-range lengths found by fnlb_autotune, per precision and set of lattice
 // shapes, for the life of the process.
 std::mutex g_tune_mu;
@@ -118,6 +183,7 @@ std::string tune_key(const fnlb_replica_params* reps, int n_rep, int precision) 
   return k;
 }
 
+// (a negative value: that many rows with the two-step kernel)
 int cached_chunk(const fnlb_replica_params* reps, int n_rep, int precision) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune_cache.find(tune_key(reps, n_rep, precision));
@@ -163,8 +229,9 @@ void fill_bm_tables(BmTables& T) {
 
 void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* opt, Plan& P) {
   P.store_size = opt->precision == FNLB_FP64 ? 8 : 4;
+  P.tb_ok = two_step_fits(reps, n_rep, opt->precision);
   int chunk = opt->chunk_rows;
-  if (chunk <= 0) chunk = cached_chunk(reps, n_rep, opt->precision);
+  if (chunk <= 0) chunk = std::abs(cached_chunk(reps, n_rep, opt->precision));
   if (chunk <= 0) chunk = auto_chunk(reps, n_rep);
   P.info.assign(n_rep, RepInfo{});
   int64_t state_elems = 0, field_d = 0, spec_c = 0, acc_d = 0, ppart_d = 0, tw_c = 0;
@@ -234,8 +301,13 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
     P.max_lz = std::max(P.max_lz, p.Lz);
   }
   make_items(P, chunk);
+  make_pitems(P, chunk);
   P.item_capacity = 0;
-  for (const RepInfo& R : P.info) P.item_capacity += (size_t)((R.Lx + kSeg - 1) / kSeg) * R.Lz;
+  P.pitem_capacity = 0;
+  for (const RepInfo& R : P.info) {
+    P.item_capacity += (size_t)((R.Lx + kSeg - 1) / kSeg) * R.Lz;
+    if (P.tb_ok) P.pitem_capacity += (size_t)R.Lz;  // at most one block per row
+  }
   // rows and column tiles of the transforms
   P.rows.clear();
   P.cols.clear();
@@ -271,6 +343,8 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
   o = align_up(o + P.info.size() * sizeof(RepInfo));
   P.o_items = o;
   o = align_up(o + P.item_capacity * sizeof(Item));
+  P.o_pitems = o;
+  o = align_up(o + P.pitem_capacity * sizeof(PackItem));
   P.o_rows = o;
   o = align_up(o + P.rows.size() * sizeof(RowRef));
   P.o_cols = o;
@@ -312,6 +386,8 @@ struct fnlb_handle {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int64_t period = 0;
+  int period_launches = 0;  // kernel launches of the state in one captured period
+  bool two_step = false;    // pairs of steps run in the two-step kernel
   int static_dev = -1;   // device whose static workspace this handle holds, or -1
   // the last forward sweep of a misfit, kept for its reverse sweep
   struct {
@@ -325,6 +401,7 @@ struct fnlb_handle {
 
   RepInfo* d_reps() { return (RepInfo*)(work + plan.o_reps); }
   Item* d_items() { return (Item*)(work + plan.o_items); }
+  PackItem* d_pitems() { return (PackItem*)(work + plan.o_pitems); }
   RowRef* d_rows() { return (RowRef*)(work + plan.o_rows); }
   ColRef* d_cols() { return (ColRef*)(work + plan.o_cols); }
   int64_t* d_time() { return (int64_t*)(work + plan.o_misc); }
@@ -358,6 +435,40 @@ StepArgs step_args(fnlb_handle* h, int64_t t_off) {
   a.t_off = t_off;
   a.fields = h->d_fields();
   return a;
+}
+
+Step2Args step2_args(fnlb_handle* h, int64_t t_off) {
+  Step2Args a{};
+  a.reps = h->d_reps();
+  a.items = h->d_pitems();
+  a.n_items = (int)h->plan.pitems.size();
+  a.n_blocks = (a.n_items + 7) / 8 * 8;
+  a.state_in = h->state_copy(h->cur);
+  a.state_out = h->state_copy(1 - h->cur);
+  a.t_base = h->d_time();
+  a.t_off = t_off;
+  a.fields = h->d_fields();
+  return a;
+}
+
+// Whether the launch at time t (n steps still to go) takes two steps: the
+// handle runs the two-step kernel, two steps remain, and t + 1 is not a
+// sample time (a sample of f(t) itself is taken by the two-step kernel).
+bool pair_at(const fnlb_handle* h, int64_t t, int64_t n) {
+  const int every = h->opt.sample_every;
+  return h->two_step && n >= 2 && !(every > 0 && (t + 1) % every == 0);
+}
+
+// One launch of the state from time t: two steps or one, sampling f(t) when t
+// is a sample time; returns the steps taken (0 on error, e set).
+int launch_state(fnlb_handle* h, int64_t t_off, bool pair, bool smp, hipStream_t s,
+                 hipError_t& e) {
+  if (pair) {
+    e = launch_step2(smp ? kStepSample : kStep, step2_args(h, t_off), s);
+    return e == hipSuccess ? 2 : 0;
+  }
+  e = launch_step(h->opt.precision, smp ? kStepSample : kStep, step_args(h, t_off), s);
+  return e == hipSuccess ? 1 : 0;
 }
 
 // Structure-factor transforms and pressure reduction of the sample fields.
@@ -405,10 +516,13 @@ hipError_t capture_period(fnlb_handle* h, int parity) {
   h->cur = parity;
   hipError_t le = hipSuccess;
   bool forked = false;
-  for (int64_t k = 0; k < h->period && le == hipSuccess; ++k) {
+  int launches = 0;
+  for (int64_t k = 0; k < h->period && le == hipSuccess;) {
     const bool smp = sampling && k == 0;
-    StepArgs a = step_args(h, k);
-    le = launch_step(h->opt.precision, smp ? kStepSample : kStep, a, s);
+    // a period starts at a sample time and holds no other
+    const int took = launch_state(h, k, pair_at(h, k, h->period - k), smp, s, le);
+    k += took > 0 ? took : 1;
+    ++launches;
     if (le == hipSuccess && smp) {
       le = hipEventRecord(h->ev_fork, s);
       if (le == hipSuccess) le = hipStreamWaitEvent(h->obs_stream, h->ev_fork, 0);
@@ -422,6 +536,7 @@ hipError_t capture_period(fnlb_handle* h, int parity) {
     }
     h->cur ^= 1;
   }
+  h->period_launches = launches;
   // the branch always joins, so that the capture can end
   if (forked) {
     const hipError_t je = hipStreamWaitEvent(s, h->ev_join, 0);
@@ -462,7 +577,7 @@ int replay_period(fnlb_handle* h) {
   if (e != hipSuccess) return dev_err(h, e);
   h->t += h->period;
   h->t_dev += h->period;
-  if (h->period & 1) h->cur ^= 1;
+  if (h->period_launches & 1) h->cur ^= 1;
   if (h->opt.sample_every > 0) ++h->nsamples;
   return FNLB_OK;
 }
@@ -544,6 +659,12 @@ int init_handle(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_optio
   h->work = (char*)d_work;
   h->stream = (hipStream_t)hip_stream;
   h->period = h->opt.sample_every > 0 ? h->opt.sample_every : 16;
+  // the kernel: as requested, else as tuned for this shape (a negative cached
+  // row count), else one step per launch
+  if (h->opt.flags & FNLB_TWO_STEP)
+    h->two_step = true;
+  else if (!(h->opt.flags & FNLB_ONE_STEP) && options->chunk_rows <= 0)
+    h->two_step = P.tb_ok && cached_chunk(reps, n_rep, options->precision) < 0;
   hipStream_t s = h->stream;
   hipError_t e = hipSuccess;
   auto up = [&](size_t off, const void* src, size_t n) {
@@ -556,6 +677,7 @@ int init_handle(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_optio
   for (RepInfo& R : h->plan.info) R.bm = (const BmTables*)(h->work + P.o_bm);
   up(P.o_reps, P.info.data(), P.info.size() * sizeof(RepInfo));
   up(P.o_items, P.items.data(), P.items.size() * sizeof(Item));
+  up(P.o_pitems, P.pitems.data(), P.pitems.size() * sizeof(PackItem));
   up(P.o_rows, P.rows.data(), P.rows.size() * sizeof(RowRef));
   up(P.o_cols, P.cols.data(), P.cols.size() * sizeof(ColRef));
   if (e == hipSuccess) e = launch_fill_zero(h->work + P.o_misc, 16, s);
@@ -649,14 +771,14 @@ int fnlb_step(fnlb_handle* h, int64_t n) {
       continue;
     }
     const bool smp = every > 0 && t >= 1 && t % every == 0;
-    StepArgs a = step_args(h, t - h->t_dev);
-    hipError_t e = launch_step(h->opt.precision, smp ? kStepSample : kStep, a, h->stream);
+    hipError_t e = hipSuccess;
+    const int took = launch_state(h, t - h->t_dev, pair_at(h, t, n), smp, h->stream, e);
     if (e == hipSuccess && smp) e = observe(h, h->stream);
     if (e != hipSuccess) return dev_err(h, e);
     if (smp) ++h->nsamples;
     h->cur ^= 1;
-    ++h->t;
-    --n;
+    h->t += took;
+    n -= took;
   }
   return FNLB_OK;
 }
@@ -667,62 +789,84 @@ int fnlb_autotune(fnlb_handle* h, int32_t steps_per_trial, int32_t* chunk_rows_o
   Plan& P = h->plan;
   int max_lz = 0;
   for (const RepInfo& R : P.info) max_lz = std::max(max_lz, R.Lz);
-  const int cands[] = {1, 2, 4, 8, 16, 32, 64, 128};
+  // candidates: (two-step kernel?, rows per work item)
+  struct Cand {
+    bool two;
+    int rows;
+    float ms;  // per step, the faster of two rounds
+  };
+  std::vector<Cand> cands;
+  if (!(h->opt.flags & FNLB_TWO_STEP))
+    for (int c : {1, 2, 4, 8, 16, 32, 64, 128})
+      if (c <= 2 * max_lz || c == 4) cands.push_back(Cand{false, c, 1e30f});
+  if (P.tb_ok && !(h->opt.flags & FNLB_ONE_STEP))
+    for (int c : {8, 16, 32, 64, 128, 256})
+      if (c <= 2 * max_lz || c == 8) cands.push_back(Cand{true, c, 1e30f});
+  if (cands.empty()) return FNLB_EINVAL;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   // Two rounds over the candidates, each timed by its faster round, so that
   // neither the order of the trials (clocks still ramping up during the first
   // ones) nor one disturbed trial decides: neighbouring lengths often differ
-  // by only a few percent.
-  constexpr int kCands = (int)(sizeof(cands) / sizeof(cands[0]));
-  float cand_ms[kCands];
-  for (float& m : cand_ms) m = 1e30f;
-  for (int round = 0; round < 2; ++round)
-    for (int ci = 0; ci < kCands; ++ci) {
-      const int c = cands[ci];
-      if (e != hipSuccess) break;
-      if (c > 2 * max_lz && c != 4) continue;
-      make_items(P, c);
-      e = hipMemcpyAsync(h->d_items(), P.items.data(), P.items.size() * sizeof(Item),
+  // by only a few percent.  Trial launches read the current copy and write
+  // the spare one, so the state and the time are unchanged.
+  auto upload = [&]() {
+    hipError_t u = hipMemcpyAsync(h->d_items(), P.items.data(), P.items.size() * sizeof(Item),
+                                  hipMemcpyHostToDevice, h->stream);
+    if (u == hipSuccess && !P.pitems.empty())
+      u = hipMemcpyAsync(h->d_pitems(), P.pitems.data(), P.pitems.size() * sizeof(PackItem),
                          hipMemcpyHostToDevice, h->stream);
-      // trial steps read the current copy and write the spare one: the state
-      // and the time are unchanged
-      StepArgs a = step_args(h, h->t - h->t_dev);
-      for (int w = 0; w < 2 && e == hipSuccess; ++w)
-        e = launch_step(h->opt.precision, kStep, a, h->stream);
+    return u;
+  };
+  for (int round = 0; round < 2; ++round)
+    for (Cand& cd : cands) {
+      if (e != hipSuccess) break;
+      make_items(P, cd.rows);
+      make_pitems(P, cd.rows);
+      e = upload();
+      const int64_t off = h->t - h->t_dev;
+      auto trial = [&]() {
+        return cd.two ? launch_step2(kStep, step2_args(h, off), h->stream)
+                      : launch_step(h->opt.precision, kStep, step_args(h, off), h->stream);
+      };
+      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = trial();
       if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-      for (int k = 0; k < steps_per_trial && e == hipSuccess; ++k)
-        e = launch_step(h->opt.precision, kStep, a, h->stream);
+      for (int k = 0; k < steps_per_trial && e == hipSuccess; ++k) e = trial();
       if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e == hipSuccess) cand_ms[ci] = std::min(cand_ms[ci], ms);
+      if (e == hipSuccess) cd.ms = std::min(cd.ms, ms / (cd.two ? 2.0f : 1.0f));
     }
-  int best = P.chunk;
-  float best_ms = 1e30f;
-  for (int ci = 0; ci < kCands; ++ci)
-    if (cand_ms[ci] < best_ms) {
-      best_ms = cand_ms[ci];
-      best = cands[ci];
-    }
+  Cand best{false, P.chunk, 1e30f};
+  for (const Cand& cd : cands)
+    if (cd.ms < best.ms) best = cd;
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  make_items(P, best);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(h->d_items(), P.items.data(), P.items.size() * sizeof(Item),
-                       hipMemcpyHostToDevice, h->stream);
+  make_items(P, best.rows);
+  make_pitems(P, best.rows);
+  P.chunk = best.rows;
+  if (e == hipSuccess) e = upload();
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return dev_err(h, e);
+  h->two_step = best.two;
   drop_graphs(h);
   e = prepare_graphs(h);
   if (e != hipSuccess) return dev_err(h, e);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[tune_key(h->reps.data(), (int)h->reps.size(), h->opt.precision)] = best;
+    g_tune_cache[tune_key(h->reps.data(), (int)h->reps.size(), h->opt.precision)] =
+        best.two ? -best.rows : best.rows;
   }
-  if (chunk_rows_out) *chunk_rows_out = best;
+  if (chunk_rows_out) *chunk_rows_out = best.rows;
+  return FNLB_OK;
+}
+
+int fnlb_launch_config(const fnlb_handle* h, int32_t* steps_per_launch, int32_t* chunk_rows) {
+  if (!h) return FNLB_EINVAL;
+  if (steps_per_launch) *steps_per_launch = h->two_step ? 2 : 1;
+  if (chunk_rows) *chunk_rows = h->plan.chunk;
   return FNLB_OK;
 }
 
@@ -923,7 +1067,7 @@ uint64_t ckpt_key(const fnlb_handle* h) {
     mix(d, sizeof d);
     mix(&p.seed, 8);
   }
-  const int32_t o[3] = {h->opt.precision, h->opt.flags & ~FNLB_NO_GRAPH, h->opt.sample_every};
+  const int32_t o[3] = {h->opt.precision, h->opt.flags & ~kExecFlags, h->opt.sample_every};
   mix(o, sizeof o);
   return k;
 }
@@ -1004,7 +1148,7 @@ struct AdjPlan {
 
 int adj_plan(const fnlb_handle* h, int64_t horizon, int32_t K, AdjPlan& A) {
   if (h->reps.size() != 1 || h->opt.precision != FNLB_FP64) return FNLB_EINVAL;
-  if ((h->opt.flags & ~FNLB_NO_GRAPH) != (FNLB_ASTAR | FNLB_WALL_UZ_FIX)) return FNLB_EINVAL;
+  if ((h->opt.flags & ~kExecFlags) != (FNLB_ASTAR | FNLB_WALL_UZ_FIX)) return FNLB_EINVAL;
   if (horizon < 1 || K < 1) return FNLB_EINVAL;
   const RepInfo& R = h->plan.info[0];
   const size_t N = (size_t)R.Lx * R.Lz, P = (size_t)R.Lz * (R.Lx / 2 + 1);

@@ -78,6 +78,34 @@ struct ColRef {
 // Kernel modes of the fused step.
 enum StepMode { kStep = 0, kStepSample = 1, kSampleOnly = 2 };
 
+// The two-step kernel (FP32-deviation storage): a block of kTBLanes lanes
+// advances whole rows of up to kTBLanes columns by two time steps in one pass,
+// keeping the intermediate state in LDS.  A block holds up to 8 work items of
+// the same lane width (narrow lattices share a block); each marches through
+// its row range with a halo of two rows on each side for the first step.
+constexpr int kTBLanes = 512;
+constexpr int kTBMaxSub = 8;
+struct PackItem {
+  int32_t nsub;    // work items in this block (1 .. kTBMaxSub)
+  int32_t lwidth;  // log2 of the lanes per work item (6 .. 9)
+  int32_t niter;   // loop iterations of the block (the longest item's, even)
+  int32_t pad;
+  int32_t rep[kTBMaxSub], j0[kTBMaxSub], j1[kTBMaxSub], dir[kTBMaxSub];
+};
+
+struct Step2Args {
+  const RepInfo* reps;
+  const PackItem* items;
+  int32_t n_items;
+  int32_t n_blocks;       // blocks launched (multiple of 8 for the XCD map)
+  const void* state_in;   // state at t
+  void* state_out;        // state at t + 2
+  const int64_t* t_base;  // device time counter
+  int64_t t_off;          // time of the first step = *t_base + t_off
+  void* fields;           // sample inputs of f(t) (sampling mode)
+};
+hipError_t launch_step2(int mode, const Step2Args& a, hipStream_t stream);
+
 struct StepArgs {
   const RepInfo* reps;
   const Item* items;

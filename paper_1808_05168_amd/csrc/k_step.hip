@@ -41,6 +41,7 @@
 #include "fnlb.h"
 #include "fnlb_device.hpp"
 #include "fnlb_internal.hpp"
+#include "fnlb_node.hpp"
 #include "fnlb_state.hpp"
 
 #include <type_traits>
@@ -191,28 +192,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   const int64_t t = *a.t_base + a.t_off;
   const uint32_t k0 = R.seed_lo, k1 = R.seed_hi;
 
-  // physics constants in the compute type
-  const Real G = (Real)R.G;
-  const Real ne = (Real)R.ne_coef;
-  const Real lam_d = (Real)R.lam[1], lam_e = (Real)R.lam[3], lam_s = (Real)R.lam[4];
-  const Real lam_q = (Real)R.lam[6], lam_p = (Real)R.lam[8];
-  const Real fac_d = (Real)R.fac[1], fac_e = (Real)R.fac[3], fac_s = (Real)R.fac[4];
-  const Real w1 = (Real)(1.0 / 9.0), w5 = (Real)(1.0 / 36.0), w0 = (Real)(4.0 / 9.0);
   const double rA0 = R.rA_mid, rAs = R.rA_step, rho0 = R.rho0;
-  // shift of a deviation that moves up one row, species A: w_l (rho_ref^A(j)
-  // - rho_ref^A(j+1)) = -w_l rho_bar grad_c0; species B has the opposite sign
-  const Real shA1 = (Real)(-rAs / 9.0), shA5 = (Real)(-rAs / 36.0);
-
-  // noise amplitudes of the moments 1 and 3..8, read once before the row loop
-  // (reloading them per row cost 5% of the step): those at the reference
-  // densities, or with local noise the factors that multiply the square roots
-  // of the local densities
-  const bool loc = (flags & FNLB_NOISE_LOC) != 0;
-  const double* sgA = loc ? R.sig_base : R.sig[0];
-  const double* sgB = loc ? R.sig_base : R.sig[1];
-  const Real sig0d = (Real)sgA[1];
-  const Real sig0[5] = {(Real)sgA[3], (Real)sgA[4], (Real)sgA[5], (Real)sgA[6], (Real)sgA[8]};
-  const Real sig1[5] = {(Real)sgB[3], (Real)sgB[4], (Real)sgB[5], (Real)sgB[6], (Real)sgB[8]};
+  // physics constants, read once before the row loop (reloading the noise
+  // amplitudes per row cost 5% of the step)
+  NodePhys<Real> P;
+  P.load(R);
 
   const int j0 = it.j0, j1 = it.j1;
   // FP64 Box-Muller tables: gathered by table index, from LDS when the item
@@ -283,12 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     const uint32_t node = (uint32_t)(j * Lx + x);
     Real gA0[4], gA1[4], gB0[4], gB1[4];
     if constexpr (MODE != kSampleOnly) {
-      if (wave_act) {
-        node_normals(node, (uint64_t)t, 2u, k0, k1, gB0, bmt);
-        node_normals(node, (uint64_t)t, 3u, k0, k1, gB1, bmt);
-        node_normals(node, (uint64_t)t, 0u, k0, k1, gA0, bmt);
-        node_normals(node, (uint64_t)t, 1u, k0, k1, gA1, bmt);
-      }
+      if (wave_act) node_noise(node, (uint64_t)t, k0, k1, bmt, gA0, gA1, gB0, gB1);
     }
 
     if (ahead) {
@@ -342,152 +321,14 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
       const DT* bC = ring[j & 3][1];
       const DT* aD = ring[jD & 3][0];
       const DT* bD = ring[jD & 3][1];
-      const DT dAc = aC[c], dBc = bC[c];
-      const DT aWc = aC[c - 1], aEc = aC[c + 1], bWc = bC[c - 1], bEc = bC[c + 1];
-      const DT dAp = aU[c], aWp = aU[c - 1], aEp = aU[c + 1];
-      const DT dBp = bU[c], bWp = bU[c - 1], bEp = bU[c + 1];
-      const DT dAm = aD[c], aWm = aD[c - 1], aEm = aD[c + 1];
-      const DT dBm = bD[c], bWm = bD[c - 1], bEm = bD[c + 1];
       Real dA[9], dB[9];
 #pragma unroll
       for (int l = 0; l < 9; ++l) {
         dA[l] = (Real)cur[l];
         dB[l] = (Real)cur[9 + l];
       }
-      const Real rhoA = (Real)rAj + (Real)dAc;
-      const Real rhoB = (Real)(rho0 - rAj) + (Real)dBc;
-      const Real rho = rhoA + rhoB;
-      // FP32: the hardware reciprocal (1 ulp) instead of a correctly rounded
-      // division sequence
-      Real inv_rho;
-      if constexpr (sizeof(Real) == 4)
-        inv_rho = __builtin_amdgcn_rcpf(rho);
-      else
-        inv_rho = (Real)1 / rho;
-
-      // s^S = sum_l w_l c_l rho^S(r + c_l) (deviation part + reference part)
-      const Real sAx = w1 * (Real)(aEc - aWc) + w5 * (Real)((aEp - aWp) + (aEm - aWm));
-      const Real sBx = w1 * (Real)(bEc - bWc) + w5 * (Real)((bEp - bWp) + (bEm - bWm));
-      const Real sAz =
-          w1 * (Real)(dAp - dAm) + w5 * (Real)((aEp + aWp) - (aEm + aWm)) + (Real)szref;
-      const Real sBz =
-          w1 * (Real)(dBp - dBm) + w5 * (Real)((bEp + bWp) - (bEm + bWm)) - (Real)szref;
-
-      // non-ideal forces (Eq. (11)); with a_* both species share
-      // a_bar = (rho^A a^A_NI + rho^B a^B_NI) / rho
-      Real FAx, FAz, FBx, FBz;
-      if (flags & FNLB_ASTAR) {
-        const Real abx = -G * (rhoA * sBx + rhoB * sAx) * inv_rho;
-        const Real abz = -G * (rhoA * sBz + rhoB * sAz) * inv_rho;
-        FAx = rhoA * abx;
-        FAz = rhoA * abz;
-        FBx = rhoB * abx;
-        FBz = rhoB * abz;
-      } else {
-        FAx = -G * rhoA * sBx;
-        FAz = -G * rhoA * sBz;
-        FBx = -G * rhoB * sAx;
-        FBz = -G * rhoB * sAz;
-      }
-      // non-equilibrium forces (Eq. (12)): rho^A grad_c0/(3c) = rho grad_c0/3
-      FAz += ne * rho;
-      FBz -= ne * rho;
-
-      // species momenta (Eq. (9)) from deviations (the reference carries none)
-      Real jAx = (dA[1] - dA[3]) + (dA[5] - dA[6]) + (dA[8] - dA[7]);
-      Real jAz = (dA[2] - dA[4]) + (dA[5] + dA[6]) - (dA[7] + dA[8]);
-      Real jBx = (dB[1] - dB[3]) + (dB[5] - dB[6]) + (dB[8] - dB[7]);
-      Real jBz = (dB[2] - dB[4]) + (dB[5] + dB[6]) - (dB[7] + dB[8]);
-
-      // U_z = 0 on the wall rows: move the barycentric normal momentum from
-      // the bounced-back normal population into the rest population
-      if ((flags & FNLB_WALL_UZ_FIX) && (bot || top)) {
-        const Real Pi = jAz + jBz + (Real)0.5 * (FAz + FBz);
-        const Real delA = rhoA * inv_rho * Pi, delB = rhoB * inv_rho * Pi;
-        if (bot) {
-          dA[2] -= delA;
-          dA[0] += delA;
-          dB[2] -= delB;
-          dB[0] += delB;
-        } else {
-          dA[4] += delA;
-          dA[0] -= delA;
-          dB[4] += delB;
-          dB[0] -= delB;
-        }
-        jAz -= delA;
-        jBz -= delB;
-      }
-
-      // barycentric velocity (Eq. (10))
-      const Real Ux = (jAx + jBx + (Real)0.5 * (FAx + FBx)) * inv_rho;
-      const Real Uz = (jAz + jBz + (Real)0.5 * (FAz + FBz)) * inv_rho;
-      const Real Uxx = Ux * Ux, Uzz = Uz * Uz, Uxz = Ux * Uz;
-
-      // noise amplitudes: at the reference densities, or with local noise the
-      // base amplitudes times the square roots of the local densities, applied
-      // to the normals (the amplitudes themselves stay loop-invariant)
-      const Real sd = sig0d;
-      const Real sA3 = sig0[0], sA4 = sig0[1], sA5 = sig0[2], sA6 = sig0[3], sA8 = sig0[4];
-      const Real sB3 = sig1[0], sB4 = sig1[1], sB5 = sig1[2], sB6 = sig1[3], sB8 = sig1[4];
-      if (loc) {
-        const Real qa = sqrt(rhoA), qb = sqrt(rhoB), qd = sqrt(rhoA * rhoB * inv_rho);
-        gA0[0] *= qd;
-        gA0[1] *= qd;
-        gA0[2] *= qa;
-        gA0[3] *= qa;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          gA1[k] *= qa;
-          gB0[k] *= qb;
-        }
-        gB1[0] *= qb;
-        gB1[1] *= qb;
-      }
-      const Real xi1 = sd * gA0[0], xi2 = sd * gA0[1];
-
-      // collision of one species in moment space: adds the increments
-      // R_l = w_l sum_a T_al dm_a / N_a to the populations
-      auto collide = [&](Real(&d)[9], Real rs, Real jx, Real jz, Real Fx, Real Fz, Real x1,
-                         Real x2, Real x3, Real x4, Real x5, Real x6, Real x7, Real x8) {
-        const Real s14 = (d[1] + d[2]) + (d[3] + d[4]);
-        const Real s58 = (d[5] + d[6]) + (d[7] + d[8]);
-        const Real m3 = -2 * d[0] + s14 + 4 * s58;
-        const Real m4 = (d[1] - d[2]) + (d[3] - d[4]);
-        const Real m5 = (d[5] - d[6]) + (d[7] - d[8]);
-        const Real m6 = (d[3] - d[1]) + 2 * ((d[5] - d[6]) + (d[8] - d[7]));
-        const Real m7 = (d[4] - d[2]) + 2 * ((d[5] + d[6]) - (d[7] + d[8]));
-        const Real m8 = 2 * d[0] - 4 * s14 + 8 * s58;
-        const Real UF = Ux * Fx + Uz * Fz;
-        const Real dm1 = lam_d * (rs * Ux - jx) + fac_d * Fx + x1;
-        const Real dm2 = lam_d * (rs * Uz - jz) + fac_d * Fz + x2;
-        const Real dm3 = lam_e * (3 * rs * (Uxx + Uzz) - m3) + fac_e * 6 * UF + x3;
-        const Real dm4 = lam_s * (rs * (Uxx - Uzz) - m4) + fac_s * 2 * (Ux * Fx - Uz * Fz) + x4;
-        const Real dm5 = lam_s * (rs * Uxz - m5) + fac_s * (Ux * Fz + Uz * Fx) + x5;
-        const Real dm6 = -lam_q * m6 + x6;
-        const Real dm7 = -lam_q * m7 + x7;
-        const Real dm8 = -lam_p * m8 + x8;
-        // e_a = dm_a / N_a with N = (1, 1/3, 1/3, 4, 4/9, 1/9, 2/3, 2/3, 16)
-        const Real e1 = 3 * dm1, e2 = 3 * dm2, e3 = (Real)0.25 * dm3, e4 = (Real)2.25 * dm4;
-        const Real e5 = 9 * dm5, e6 = (Real)1.5 * dm6, e7 = (Real)1.5 * dm7;
-        const Real e8 = (Real)0.0625 * dm8;
-        d[0] += w0 * (2 * (e8 - e3));
-        const Real a38 = e3 - 4 * e8;
-        d[1] += w1 * (a38 + e1 + e4 - e6);
-        d[3] += w1 * (a38 - e1 + e4 + e6);
-        d[2] += w1 * (a38 + e2 - e4 - e7);
-        d[4] += w1 * (a38 - e2 - e4 + e7);
-        const Real b38 = 4 * e3 + 8 * e8;
-        const Real p1 = e1 + 2 * e6, p2 = e2 + 2 * e7;
-        d[5] += w5 * (b38 + p1 + p2 + e5);
-        d[7] += w5 * (b38 - p1 - p2 + e5);
-        d[6] += w5 * (b38 - p1 + p2 - e5);
-        d[8] += w5 * (b38 + p1 - p2 - e5);
-      };
-      collide(dA, rhoA, jAx, jAz, FAx, FAz, xi1, xi2, sA3 * gA0[2], sA4 * gA0[3],
-              sA5 * gA1[0], sA6 * gA1[1], sA6 * gA1[2], sA8 * gA1[3]);
-      collide(dB, rhoB, jBx, jBz, FBx, FBz, -xi1, -xi2, sB3 * gB0[0], sB4 * gB0[1],
-              sB5 * gB0[2], sB6 * gB0[3], sB6 * gB1[0], sB8 * gB1[1]);
+      node_update<Real, DT>(P, flags, top, bot, rAj, rho0, szref, aU, aC, aD, bU, bC, bD, c, dA,
+                            dB, gA0, gA1, gB0, gB1);
 
       // store the node's post-collision populations, each shifted to the
       // reference of the row it streams to (bounced-back links stay in row)
@@ -506,8 +347,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
           bstore<Store>(out, off, p + 7 * link_b, (Store)(d[7] - dn * sh5));
           bstore<Store>(out, off, p + 8 * link_b, (Store)(d[8] - dn * sh5));
         };
-        emit(0, dA, shA1, shA5);
-        emit(1, dB, -shA1, -shA5);
+        emit(0, dA, P.shA1, P.shA5);
+        emit(1, dB, -P.shA1, -P.shA5);
       }
      }
     }

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfnlb.so")
 FNLB_OK = 0
 FP64, FP32_DEV = 0, 1
 ASTAR, WALL_UZ_FIX, NOISE_LOC, FORCE_LITERAL, NO_GRAPH, SAMPLE_VELOCITY = 1, 2, 4, 8, 16, 32
+TWO_STEP, ONE_STEP = 64, 128
 DEFAULT_FLAGS = ASTAR | WALL_UZ_FIX
 FIELD_C, FIELD_RHO, FIELD_UX, FIELD_UZ = 0, 1, 2, 3
 
@@ -49,7 +50,8 @@ EXPORTS = ["fnlb_bytes_required", "fnlb_init", "fnlb_step", "fnlb_autotune",
            "fnlb_strerror", "fnlb_adjoint_bytes_required", "fnlb_sq_misfit_gradient",
            "fnlb_checkpoint_bytes", "fnlb_save", "fnlb_load", "fnlb_pressure_misfit_gradient",
            "fnlb_build_id", "fnlb_init_static_work", "fnlb_reinit", "fnlb_sq_misfit",
-           "fnlb_pressure_misfit", "fnlb_misfit_backward", "fnlb_step_vjp"]
+           "fnlb_pressure_misfit", "fnlb_misfit_backward", "fnlb_step_vjp",
+           "fnlb_launch_config"]
 STATIC_WORK_BYTES = 128 << 20  # FNLB_STATIC_WORK_BYTES
 
 
@@ -79,6 +81,8 @@ def load(path: str = LIB_PATH):
                                           ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     lib.fnlb_step.argtypes = [vp, ctypes.c_int64]
     lib.fnlb_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.fnlb_launch_config.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]
     lib.fnlb_accumulate_structure_factor.argtypes = [vp]
     lib.fnlb_read_structure_factor.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, dp, dp, dp,
                                                i64p]
@@ -212,8 +216,15 @@ class Lattice:
     def step(self, n: int = 1) -> None:
         _check(self._lib.fnlb_step(self._h, int(n)), "fnlb_step")
 
+    def launch_config(self):
+        """(steps per launch, rows per work item) the handle uses."""
+        k, c = ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.fnlb_launch_config(self._h, ctypes.byref(k), ctypes.byref(c)),
+               "fnlb_launch_config")
+        return int(k.value), int(c.value)
+
     def autotune(self, steps_per_trial: int = 20) -> int:
-        """Picks the fastest row-range length of the step kernel; returns it."""
+        """Picks the fastest step kernel and row-range length; returns the rows."""
         c = ctypes.c_int32()
         _check(self._lib.fnlb_autotune(self._h, int(steps_per_trial), ctypes.byref(c)),
                "fnlb_autotune")

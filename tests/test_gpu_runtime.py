@@ -34,13 +34,16 @@ def _same(a, b):
         np.testing.assert_array_equal(pa[2], pb[2])
 
 
-@pytest.mark.parametrize("every,prec", [(5, 0), (4, 1), (0, 0), (7, 1)])
-def test_graph_replay_matches_direct_launches(F, every, prec):
+@pytest.mark.parametrize("every,prec,two", [(5, 0, 0), (4, 1, 0), (0, 0, 0), (7, 1, 0),
+                                            (4, 1, 1), (7, 1, 1), (0, 1, 1)])
+def test_graph_replay_matches_direct_launches(F, every, prec, two):
     reps = [W.Replica(Lx=96, Lz=20, grad_c0=2e-3, kT=1e-4, G=0.5, seed=51),
             W.Replica(Lx=300, Lz=9, grad_c0=1e-2, kT=1e-4, seed=52)]
-    say(f"case: graph vs direct, every={every} precision={prec}")
-    g = F.Lattice(reps, precision=prec, sample_every=every)
-    d = F.Lattice(reps, precision=prec, sample_every=every, flags=F.DEFAULT_FLAGS | F.NO_GRAPH)
+    say(f"case: graph vs direct, every={every} precision={prec} two-step={two}")
+    kern = F.TWO_STEP if two else F.ONE_STEP
+    g = F.Lattice(reps, precision=prec, sample_every=every, flags=F.DEFAULT_FLAGS | kern)
+    d = F.Lattice(reps, precision=prec, sample_every=every,
+                  flags=F.DEFAULT_FLAGS | F.NO_GRAPH | kern)
     for n in (3, 7, 20, 1, 13, 40, 0, 17):
         g.step(n)
         d.step(n)

@@ -21,6 +21,8 @@ NOISE_LOC = 4        # local instead of reference densities in the noise
 FORCE_LITERAL = 8    # first-order forcing without (1 - lambda_d/2) (tests only)
 NO_GRAPH = 16        # execution only: no graph replay
 SAMPLE_VELOCITY = 32 # also sample U_x, U_z for the velocity structure factors
+TWO_STEP = 64        # execution only: pairs of steps in the two-step kernel
+ONE_STEP = 128       # execution only: one step per launch
 DEFAULT_FLAGS = ASTAR | WALL_UZ_FIX
 
 
