@@ -11,11 +11,12 @@ Printed as one JSON line:
   value        MLUPS over the whole batch (one update = both species at one node)
   value_without_sampling
                the same batch with sampling off
-  roofline     the step kernel alone (sampling off), HBM-bound: algorithmic
-               bytes (18 reads + 18 writes per node) / measured launch time;
-               measured HBM bytes per launch from the committed counter record
-               (ensemble only, while the kernel sources match it); a plain
-               device-copy ceiling measured in the same run
+  roofline     the step kernel alone (sampling off): algorithmic bytes per
+               launch (18 reads + 18 writes per node and step, times the steps
+               one launch advances) / measured launch time; measured HBM bytes
+               per launch from the committed counter record (ensemble only,
+               while the kernel and its sources match it); a plain device-copy
+               ceiling measured in the same run
   compare      plain FP64 storage on the same batch and on the single 512 x 256
                lattice, and the agreement of the two storage forms
   adjoint      one gradient of the S(q) misfit on 256 x 128 (FP64, 2000 steps)
@@ -183,11 +184,16 @@ def adjoint_leg(F, W, reps_done: int = 3) -> dict:
             "grad": [float(x) for x in g], "J": float(J)}
 
 
-STEP_SOURCES = ("k_step.hip", "fnlb_device.hpp", "fnlb_internal.hpp", "fnlb_state.hpp")
+STEP_SOURCES = ("k_step.hip", "k_step2.hip", "fnlb_node.hpp", "fnlb_device.hpp",
+                "fnlb_internal.hpp", "fnlb_state.hpp")
 # SQ counters of the one --pmc pass behind profiles/counters_batched96_fp32dev.md
 PMC_SET = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU",
            "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_BUSY_CYCLES")
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_k_step_batched96_fp32dev.json")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_step_batched96_fp32dev.json")
+# the step kernels as rocprofv3 names them: (plain, sampling) variants and the
+# steps one launch advances
+STEP_KERNELS = {"k_step2": ("k_step2<0>", "k_step2<1>", 2),
+                "k_step": ("k_step<float, float, 0,", "k_step<float, float, 1,", 1)}
 
 
 def _step_source_hash() -> str:
@@ -199,13 +205,14 @@ def _step_source_hash() -> str:
     return h.hexdigest()
 
 
-def _traffic_from_profiles():
-    """HBM bytes per step launch from the committed counter summary, if it was
-    taken on the current kernel sources (else None)."""
+def _traffic_from_profiles(kernel: str):
+    """HBM bytes per launch of the step kernel from the committed counter
+    summary, if it was taken on this kernel and the current kernel sources
+    (else None)."""
     try:
         with open(TRAFFIC_JSON) as fh:
             d = json.load(fh)
-        if d.get("source_sha256") != _step_source_hash():
+        if d.get("source_sha256") != _step_source_hash() or d.get("kernel") != kernel:
             return None
         return d["bytes_per_launch"]
     except (OSError, KeyError, ValueError):
@@ -237,15 +244,18 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, out_md, command):
     runs first."""
     import csv
     from collections import Counter, defaultdict
-    # template arguments: compute type, storage type, mode (0 plain, 1 sampling), ...
-    step_name = "k_step<float, float, 0,"
     stats = list(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_stats.csv"))))
     rows = sorted(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_trace.csv"))),
                   key=lambda r: int(r["Start_Timestamp"]))
+    # the step kernel of the run: the two-step kernel if it ran, else the
+    # one-step kernel (template arguments: compute type, storage type, mode)
+    kernel = "k_step2" if any(STEP_KERNELS["k_step2"][0] in r["Kernel_Name"] for r in rows) \
+        else "k_step"
+    step_name, sample_name, spl = STEP_KERNELS[kernel]
     trace = [r for r in rows if step_name in r["Kernel_Name"]]
     grid = Counter(r["Grid_Size_X"] for r in trace).most_common(1)[0][0]
     last_sample = max((int(r["Start_Timestamp"]) for r in rows
-                       if "k_step<float, float, 1," in r["Kernel_Name"]), default=-1)
+                       if sample_name in r["Kernel_Name"]), default=-1)
     durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace
             if r["Grid_Size_X"] == grid and int(r["Start_Timestamp"]) > last_sample]
     avg_us = sum(durs) / len(durs) / 1e3
@@ -270,8 +280,10 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, out_md, command):
     wr = w_step * w_scale * 1024
     import workloads as W
     nodes = sum(r.Lx * r.Lz for r in W.batched_ensemble(96))
-    alg = 144 * nodes
-    lines = ["# k_step (fused collide-stream), batched 96-replica FP32-deviation workload", "",
+    alg = 144 * nodes * spl
+    title = ("k_step2 (two fused collide-stream steps per pass)" if spl == 2
+             else "k_step (fused collide-stream)")
+    lines = [f"# {title}, batched 96-replica FP32-deviation workload", "",
              "Commands (run from the repository root; <out> is any output directory):", "",
              "```", command, "```", "",
              "## Kernel trace (rocprofv3 --stats)", "",
@@ -281,18 +293,21 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, out_md, command):
                      f"{float(r['Percentage']):.2f} |")
     lines += ["", "In the sampled run the transforms of each sample run beside the plain steps "
               "that follow it, so the averages above include that overlap.", "",
-              f"Step kernel in the roofline leg (plain steps, grid {grid} threads, "
-              f"{len(durs)} dispatches): average {avg_us:.1f} us.", "",
+              f"Step kernel `{kernel}` in the roofline leg ({spl} step(s) per launch; plain "
+              f"launches, grid {grid} threads, {len(durs)} dispatches): average "
+              f"{avg_us:.1f} us per launch, {avg_us / spl:.1f} us per step.", "",
               "## HBM traffic per step launch", "",
               f"FETCH_SIZE and WRITE_SIZE (KiB per dispatch, {nf} and {nw} step dispatches) "
               f"scaled by the 1 GiB copy: FETCH x{f_scale:.4f}, WRITE x{w_scale:.4f}.", "",
               f"- read {rd/1e6:.1f} MB, write {wr/1e6:.1f} MB, total {(rd+wr)/1e6:.1f} MB",
-              f"- algorithmic (144 B/node x {nodes} nodes): {alg/1e6:.1f} MB",
+              f"- algorithmic (144 B/node-step x {nodes} nodes x {spl} step(s)): "
+              f"{alg/1e6:.1f} MB",
               f"- ratio {(rd+wr)/alg:.3f}"]
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     with open(TRAFFIC_JSON, "w") as fh:
-        json.dump({"bytes_per_launch": round(rd + wr), "read_bytes": round(rd),
+        json.dump({"kernel": kernel, "steps_per_launch": spl,
+                   "bytes_per_launch": round(rd + wr), "read_bytes": round(rd),
                    "write_bytes": round(wr), "algorithmic_bytes": alg,
                    "step_avg_us": round(avg_us, 2), "grid": int(grid),
                    "source_sha256": _step_source_hash(), "command": command}, fh, indent=1)
@@ -437,6 +452,9 @@ def main():
                     help="launch every step directly instead of replaying the captured "
                          "sampling period (a kernel trace then times the transforms of a "
                          "sample without the steps running beside them)")
+    ap.add_argument("--kernel", choices=["auto", "one", "two"], default="auto",
+                    help="step kernel: one or two steps per launch (auto: the autotuner's "
+                         "choice)")
     ap.add_argument("--chunk-rows", type=int, default=0,
                     help="fixed rows per work item (skips the autotuner); profiles use it "
                          "so that every pass times the same launch configuration")
@@ -455,7 +473,7 @@ def main():
         summarize_counters(d, os.path.join(ROOT, "profiles", "counters_batched96_fp32dev.md"),
                            f"rocprofv3 --pmc {' '.join(PMC_SET)} --output-format csv -d <out>/pc "
                            f"-o run -- python3 bench.py --steps 20 --warmup 2 --no-cpu-baseline "
-                           f"--no-compare --no-adjoint --chunk-rows 8\n"
+                           f"--no-compare --no-adjoint --kernel two --chunk-rows 32\n"
                            f"python3 bench.py --summarize-counters <out>/pc")
         return
     if args.summarize_trace:
@@ -463,7 +481,7 @@ def main():
         # the run each committed trace summary is taken from
         runs = {"sample_passes_batched96_fp32dev":
                 ("ps", "--steps 300 --warmup 20 --no-cpu-baseline --no-compare --no-adjoint "
-                       "--chunk-rows 8 --no-graph")}
+                       "--kernel two --chunk-rows 32 --no-graph")}
         sub, run_args = runs.get(name, ("pa", "--adjoint-only"))
         cmd = args.profile_command or (
             f"rocprofv3 --kernel-trace --stats --output-format csv -d <out>/{sub} -o run -- "
@@ -473,8 +491,8 @@ def main():
         return
 
     if args.summarize_profile:
-        out = os.path.join(ROOT, "profiles", "k_step_batched96_fp32dev.md")
-        leg = "--no-cpu-baseline --no-compare --no-adjoint --chunk-rows 8"
+        out = os.path.join(ROOT, "profiles", "step_batched96_fp32dev.md")
+        leg = "--no-cpu-baseline --no-compare --no-adjoint --kernel two --chunk-rows 32"
         cmd = args.profile_command or "\n".join([
             "rocprofv3 --kernel-trace --stats --output-format csv -d <out>/pt -o run -- "
             f"python3 bench.py --steps 200 --warmup 20 {leg}",
@@ -528,12 +546,13 @@ def main():
     bytes_per_node = 36 * store_bytes
 
     flags = F.DEFAULT_FLAGS | (F.NO_GRAPH if args.no_graph else 0)
+    flags |= {"auto": 0, "one": F.ONE_STEP, "two": F.TWO_STEP}[args.kernel]
     lat = F.Lattice(reps, precision=prec, sample_every=every, flags=flags,
                     chunk_rows=args.chunk_rows)
-    if args.chunk_rows > 0:
-        chunk = args.chunk_rows
-    else:
-        chunk = lat.autotune(50) if not args.no_autotune else 0
+    if args.chunk_rows <= 0 and not args.no_autotune:
+        lat.autotune(50)
+    # the launch configuration the timed steps use (kernel and row ranges)
+    spl, chunk = lat.launch_config()
     lat.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -543,17 +562,25 @@ def main():
     sec = ms / 1e3
     mlups = nodes * args.steps / sec / 1e6
 
-    # roofline leg: the step kernel alone (no sampling), same batch
-    lat_r = F.Lattice(reps, precision=prec, sample_every=0, flags=flags,
-                      chunk_rows=args.chunk_rows)
+    # roofline leg: the step kernel alone (no sampling), same batch and launch
+    # configuration; one launch advances spl steps, so its algorithmic bytes
+    # are spl x 144 B (FP32) per node
+    kflag = F.TWO_STEP if spl == 2 else F.ONE_STEP
+    lat_r = F.Lattice(reps, precision=prec, sample_every=0,
+                      flags=(flags & ~(F.ONE_STEP | F.TWO_STEP)) | kflag, chunk_rows=chunk)
+    assert lat_r.launch_config() == (spl, chunk)
     lat_r.step(min(args.warmup, 100))
     nr = max(50, min(args.steps, 1000))
+    nr += nr % spl
     ms_r = _events_time(lat_r, nr)
-    t_launch = ms_r / 1e3 / nr
-    achieved = bytes_per_node * nodes / t_launch / 1e9
+    t_step = ms_r / 1e3 / nr
+    t_launch = t_step * spl
+    alg_launch = bytes_per_node * nodes * spl
+    achieved = alg_launch / t_launch / 1e9
     del lat_r
+    kernel = "k_step2" if spl == 2 else "k_step"
     # the counter record is of the ensemble's step kernel
-    traffic = _traffic_from_profiles() if args.workload == "batched96" else None
+    traffic = _traffic_from_profiles(kernel) if args.workload == "batched96" else None
     copy_gbs = copy_ceiling_gbs()
 
     out = {
@@ -571,17 +598,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "nodes": nodes,
                    "storage": "fp32-deviation" if prec == F.FP32_DEV else "fp64",
-                   "sample_every": every, "chunk_rows": chunk, "parallelism": "single GPU"},
+                   "sample_every": every, "kernel": kernel, "steps_per_launch": spl,
+                   "chunk_rows": chunk, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_step (fused collide-stream)",
+                     "traffic": traffic,
+                     "kernel": ("k_step2 (two fused collide-stream steps per pass)" if spl == 2
+                                else "k_step (fused collide-stream)"),
+                     "steps_per_launch": spl,
                      "launch_ms": round(t_launch * 1e3, 5),
-                     "algorithmic_bytes_per_launch": bytes_per_node * nodes,
+                     "algorithmic_bytes_per_launch": alg_launch,
                      "copy_ceiling_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
         "wall_s": round(wall, 3),
         # the same batch with sampling off (the roofline leg)
-        "value_without_sampling": round(nodes / t_launch / 1e6, 1),
+        "value_without_sampling": round(nodes / t_step / 1e6, 1),
     }
 
     if not args.no_compare and prec == F.FP32_DEV:

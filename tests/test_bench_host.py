@@ -72,15 +72,48 @@ def test_summarize_profile_scales_counters_and_picks_the_roofline_leg(
     assert d["bytes_per_launch"] == d["read_bytes"] + d["write_bytes"]
     assert d["algorithmic_bytes"] == 144 * sum(r.Lx * r.Lz for r in W.batched_ensemble(96))
     assert d["source_sha256"] == bench._step_source_hash()
+    assert d["kernel"] == "k_step" and d["steps_per_launch"] == 1
     text = md.read_text()
     assert "the commands" in text and "FETCH x2.0000, WRITE x1.0000" in text
-    # the record is reported while the kernel sources match it, and not after
-    assert bench._traffic_from_profiles() == d["bytes_per_launch"]
+    # the record is reported for its kernel while the kernel sources match it,
+    # and not after
+    assert bench._traffic_from_profiles("k_step") == d["bytes_per_launch"]
+    assert bench._traffic_from_profiles("k_step2") is None
     d["source_sha256"] = "0" * 64
     traffic.write_text(json.dumps(d))
-    assert bench._traffic_from_profiles() is None
+    assert bench._traffic_from_profiles("k_step") is None
     monkeypatch.setattr(bench, "TRAFFIC_JSON", str(tmp_path / "missing.json"))
-    assert bench._traffic_from_profiles() is None
+    assert bench._traffic_from_profiles("k_step") is None
+
+
+def test_summarize_profile_of_the_two_step_kernel(tmp_path, monkeypatch):
+    """A run of the two-step kernel: its launches are the step kernel, and the
+    algorithmic bytes of a launch count its two steps."""
+    traffic = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_JSON", str(traffic))
+    pt, pf, pw = (tmp_path / d for d in ("pt", "pf", "pw"))
+    for d in (pt, pf, pw):
+        d.mkdir()
+    plain = "void fnlb::(anonymous namespace)::k_step2<0>(fnlb::Step2Args)"
+    sampled = "void fnlb::(anonymous namespace)::k_step2<1>(fnlb::Step2Args)"
+    _write_csv(pt / "run_kernel_stats.csv", [
+        dict(Name=plain, Calls=3, AverageNs=2000.0, Percentage=90.0)])
+    _write_csv(pt / "run_kernel_trace.csv", [
+        dict(Kernel_Name=sampled, Start_Timestamp=0, End_Timestamp=5000, Grid_Size_X=512),
+        dict(Kernel_Name=plain, Start_Timestamp=6000, End_Timestamp=8000, Grid_Size_X=512),
+        dict(Kernel_Name=plain, Start_Timestamp=9000, End_Timestamp=13000, Grid_Size_X=512)])
+    _write_csv(pf / "run_counter_collection.csv", [
+        dict(Kernel_Name=COPY, Counter_Name="FETCH_SIZE", Counter_Value=524288.0, Grid_Size=0),
+        dict(Kernel_Name=plain, Counter_Name="FETCH_SIZE", Counter_Value=10.0, Grid_Size=512)])
+    _write_csv(pw / "run_counter_collection.csv", [
+        dict(Kernel_Name=COPY, Counter_Name="WRITE_SIZE", Counter_Value=1048576.0, Grid_Size=0),
+        dict(Kernel_Name=plain, Counter_Name="WRITE_SIZE", Counter_Value=20.0, Grid_Size=512)])
+    bench.summarize_profile(str(pt), str(pf), str(pw), str(tmp_path / "s.md"), "cmd")
+    d = json.loads(traffic.read_text())
+    assert d["kernel"] == "k_step2" and d["steps_per_launch"] == 2
+    assert d["step_avg_us"] == pytest.approx(3.0)
+    assert d["algorithmic_bytes"] == 2 * 144 * sum(r.Lx * r.Lz for r in W.batched_ensemble(96))
+    assert bench._traffic_from_profiles("k_step2") == d["bytes_per_launch"]
 
 
 def test_summarize_trace_writes_the_command_and_table(profiler_dirs, tmp_path):

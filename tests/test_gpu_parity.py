@@ -329,18 +329,27 @@ def test_parity_maximum_sizes(F, shape, prec):
     assert err <= tol
     qs = [(0, 1), (1, 0), (1, 1), (3, 7), (Lz // 2, Lx // 2), (Lz - 1, Lx // 2), (Lz // 3, 5),
           (2, Lx // 2 - 1)]
+    # FP64, k_x = 0: each side forms delta c = c - c_0(z) and delta rho =
+    # rho - rho_bar from O(1) quantities, with an FP64 rounding of about
+    # eps |phi_0| that is the same along a row (the reference profile); a
+    # k_x = 0 entry adds it over the Lx columns of every row, about
+    # eps sqrt(Lx) / (field scale ~ 3e-3) relative to rms |Phi| = a few 1e-12 at
+    # 4096 columns, for the oracle as for the library.  Those entries get 1e-11.
+    tol0 = tol if prec == "fp32" else max(tol, 1e-11 * np.sqrt(Lx / 4096.0))
     for fld in range(2):
         a2, re, im, n = lat.read_structure_factor(0, fld)
         assert n == 1
         ref = phi_entries(dphi[fld], qs)
         got = np.array([re[kz, kx] + 1j * im[kz, kx] for kz, kx in qs])
         scale = np.sqrt(a2.mean())
-        rel = np.abs(got - ref).max() / scale
-        say(f"  field {fld}: max |dPhi| / rms |Phi| = {rel:.3e}")
-        assert rel <= tol
+        dev = np.abs(got - ref) / scale
+        kx0 = np.array([kx == 0 for kz, kx in qs])
+        say(f"  field {fld}: max |dPhi| / rms |Phi| = {dev[~kx0].max():.3e} (k_x > 0), "
+            f"{dev[kx0].max():.3e} (k_x = 0)")
+        assert dev[~kx0].max() <= tol and dev[kx0].max() <= tol0
         # |Phi|^2 of one sample: an error dPhi <= tol * scale in Phi moves it by
         # at most 2 |Phi| dPhi + dPhi^2
-        dphi_max = tol * scale
+        dphi_max = np.where(kx0, tol0, tol) * scale
         got2 = np.array([a2[kz, kx] for kz, kx in qs])
         assert np.all(np.abs(got2 - np.abs(ref) ** 2)
                       <= 2 * dphi_max * np.abs(ref) + dphi_max ** 2), (got2, np.abs(ref) ** 2)
