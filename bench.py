@@ -333,7 +333,8 @@ def summarize_counters(pmc_dir, out_md, command):
              "Command (run from the repository root; <out> is any output directory):", "",
              "```", command.strip(), "```", "",
              "Averages per dispatch of the library's kernels. VALU/node = SQ_INSTS_VALU x 64 "
-             "/ 4,177,920 nodes. The next two columns are raw ratios of counters to "
+             "/ 4,177,920 nodes, per step (the two-step kernel's dispatches are divided by "
+             "their two steps). The next two columns are raw ratios of counters to "
              "SQ_WAVE_CYCLES (SQ_ACTIVE_INST_VALU, SQ_WAIT_ANY), summed over the wavefronts "
              "of a dispatch; their cycle units need not match. The last column is "
              "SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS.", "",
@@ -345,8 +346,9 @@ def summarize_counters(pmc_dir, out_md, command):
         if not any(k in name for k in ("k_step", "transform", "pressure")):
             continue
         wc = max(m.get("SQ_WAVE_CYCLES", 1.0), 1.0)
+        per = 2 if "k_step2" in name else 1
         lines.append(
-            f"| {name} | {m['SQ_WAVES']:.0f} | {m['SQ_INSTS_VALU'] * 64 / nodes:.0f} | "
+            f"| {name} | {m['SQ_WAVES']:.0f} | {m['SQ_INSTS_VALU'] * 64 / nodes / per:.0f} | "
             f"{m['SQ_ACTIVE_INST_VALU'] / wc:.2f} | {m['SQ_WAIT_ANY'] / wc:.2f} | "
             f"{m['SQ_INSTS_LDS']:.3g} | "
             f"{m['SQ_LDS_BANK_CONFLICT'] / max(m['SQ_INSTS_LDS'], 1.0):.2f} |")
