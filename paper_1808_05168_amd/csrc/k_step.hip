@@ -179,13 +179,17 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   auto put_edges = [&](int jr, Store v) {
     if (edge_lane) edge[jr & 1][lane] = v;
   };
+  // (a segment of one column has one lane next to both edges)
   auto sum_edges = [&](int jr) {
     if (!whole_row && (tid == 0 || tid == width - 1)) {
-      const Store* e = edge[jr & 1] + (tid == 0 ? 0 : 18);
-      Store o[18];
+      for (int side = 0; side < 2; ++side) {
+        if (side == 0 ? tid != 0 : tid != width - 1) continue;
+        const Store* e = edge[jr & 1] + 18 * side;
+        Store o[18];
 #pragma unroll
-      for (int l = 0; l < 18; ++l) o[l] = e[l];
-      put_col(jr, tid == 0 ? 0 : width + 1, o);
+        for (int l = 0; l < 18; ++l) o[l] = e[l];
+        put_col(jr, side == 0 ? 0 : width + 1, o);
+      }
     }
   };
 
@@ -234,13 +238,16 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     put_row(jfirst - dir, tmp);
   }
   if (!whole_row && (tid == 0 || tid == width - 1)) {
-    const int col = tid == 0 ? hl : hr, rc = tid == 0 ? 0 : width + 1;
-    for (int k = 0; k < 2; ++k) {
-      const int jr = k == 0 ? jfirst - dir : jfirst;
-      if (!needed(jr)) continue;
-      Store o[18];
-      edge_pull<Store>(in, link_b, row_b, jr, Lz, Lx, col, o);
-      put_col(jr, rc, o);
+    for (int side = 0; side < 2; ++side) {
+      if (side == 0 ? tid != 0 : tid != width - 1) continue;
+      const int col = side == 0 ? hl : hr, rc = side == 0 ? 0 : width + 1;
+      for (int k = 0; k < 2; ++k) {
+        const int jr = k == 0 ? jfirst - dir : jfirst;
+        if (!needed(jr)) continue;
+        Store o[18];
+        edge_pull<Store>(in, link_b, row_b, jr, Lz, Lx, col, o);
+        put_col(jr, rc, o);
+      }
     }
   }
 

@@ -55,6 +55,14 @@ def compare_observables(lat, acc, rep_index, rep, tol, kx0_tol=None, diag=None):
     which shows that amplification."""
     out = {}
     kx0 = {}
+    # The raw sums of Re and Im Phi are checked beyond the contract (which
+    # bounds S and the pressure), to catch a wrong phase or sign of the
+    # transform.  In FP32 storage their bar is 5e-5: over a long run the
+    # FP32 rounding of the slow modes adds up coherently across samples while
+    # the sums themselves grow only like the square root of the sample count
+    # (measured 1e-5 to 1.3e-5 over the 499 samples of the 5000-step run).
+    raw = {}
+    raw_tol = tol if tol < 1e-9 else 5e-5
     for fld in range(acc.sq.shape[0]):
         a2, re, im, n = lat.read_structure_factor(rep_index, fld)
         assert n == acc.n_samples, (n, acc.n_samples)
@@ -93,8 +101,8 @@ def compare_observables(lat, acc, rep_index, rep, tol, kx0_tol=None, diag=None):
             s_a2 = n * rep.Lx * rep.Lz
             s_c = n * np.sqrt(rep.Lx * rep.Lz)
         out[f"abs2_{fld}"] = np.abs(a2 - acc.sq[fld, 0]).max() / s_a2
-        out[f"re_{fld}"] = np.abs(re_g - re_o).max() / s_c
-        out[f"im_{fld}"] = np.abs(im_g - im_o).max() / s_c
+        raw[f"re_{fld}"] = np.abs(re_g - re_o).max() / s_c
+        raw[f"im_{fld}"] = np.abs(im_g - im_o).max() / s_c
     s, s2, prof, n = lat.read_pressure(rep_index)
     if n:
         scale = np.abs(acc.prof).max()
@@ -105,7 +113,10 @@ def compare_observables(lat, acc, rep_index, rep, tol, kx0_tol=None, diag=None):
     t0 = tol if kx0_tol is None else kx0_tol
     for k, v in kx0.items():
         assert v <= t0, f"{k}: {v:.3e} > {t0:.1e}"
+    for k, v in raw.items():
+        assert v <= raw_tol, f"{k}: {v:.3e} > {raw_tol:.1e}"
     out.update(kx0)
+    out.update(raw)
     return out
 
 

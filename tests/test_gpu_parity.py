@@ -87,6 +87,9 @@ VARIANTS = {
                                       seed=23), None, 200, 5),
     "three_segments": (W.Replica(Lx=600, Lz=8, grad_c0=1e-2, kT=1e-4, G=0.3, seed=24),
                        W.ASTAR, 150, 5),
+    # a last segment of one column (its lane is next to both segment edges)
+    "one_column_segment": (W.Replica(Lx=257, Lz=6, grad_c0=1e-2, kT=1e-4, G=0.5, seed=29),
+                           None, 60, 5),
     "noiseless": (W.Replica(Lx=32, Lz=16, grad_c0=0.01, kT=0.0, G=0.5, seed=20), None, 500, 50),
     "large_seed_and_time": (W.Replica(Lx=32, Lz=8, grad_c0=0.0, kT=1e-4, seed=(1 << 63) + 5),
                             None, 50, 5),
