@@ -184,8 +184,10 @@ def adjoint_leg(F, W, reps_done: int = 3) -> dict:
             "grad": [float(x) for x in g], "J": float(J)}
 
 
-STEP_SOURCES = ("k_step.hip", "k_step2.hip", "fnlb_node.hpp", "fnlb_device.hpp",
-                "fnlb_internal.hpp", "fnlb_state.hpp")
+# the sources each step kernel is compiled from
+_STEP_HEADERS = ("fnlb_node.hpp", "fnlb_device.hpp", "fnlb_internal.hpp", "fnlb_state.hpp")
+STEP_SOURCES = {"k_step": ("k_step.hip",) + _STEP_HEADERS,
+                "k_step2": ("k_step2.hip",) + _STEP_HEADERS}
 # SQ counters of the one --pmc pass behind profiles/counters_batched96_fp32dev.md
 PMC_SET = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU",
            "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_BUSY_CYCLES")
@@ -196,10 +198,10 @@ STEP_KERNELS = {"k_step2": ("k_step2<0>", "k_step2<1>", 2),
                 "k_step": ("k_step<float, float, 0,", "k_step<float, float, 1,", 1)}
 
 
-def _step_source_hash() -> str:
+def _step_source_hash(kernel: str) -> str:
     import hashlib
     h = hashlib.sha256()
-    for n in STEP_SOURCES:
+    for n in STEP_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1808_05168_amd", "csrc", n), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -212,7 +214,7 @@ def _traffic_from_profiles(kernel: str):
     try:
         with open(TRAFFIC_JSON) as fh:
             d = json.load(fh)
-        if d.get("source_sha256") != _step_source_hash() or d.get("kernel") != kernel:
+        if d.get("kernel") != kernel or d.get("source_sha256") != _step_source_hash(kernel):
             return None
         return d["bytes_per_launch"]
     except (OSError, KeyError, ValueError):
@@ -310,7 +312,7 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, out_md, command):
                    "bytes_per_launch": round(rd + wr), "read_bytes": round(rd),
                    "write_bytes": round(wr), "algorithmic_bytes": alg,
                    "step_avg_us": round(avg_us, 2), "grid": int(grid),
-                   "source_sha256": _step_source_hash(), "command": command}, fh, indent=1)
+                   "source_sha256": _step_source_hash(kernel), "command": command}, fh, indent=1)
     print("\n".join(lines))
 
 
@@ -454,6 +456,10 @@ def main():
                     help="launch every step directly instead of replaying the captured "
                          "sampling period (a kernel trace then times the transforms of a "
                          "sample without the steps running beside them)")
+    ap.add_argument("--tune-cache", default="",
+                    help="tuning file: load the stored choices first, save them after "
+                         "tuning; the line reports whether the new pick reproduces the "
+                         "stored one")
     ap.add_argument("--kernel", choices=["auto", "one", "two"], default="auto",
                     help="step kernel: one or two steps per launch (auto: the autotuner's "
                          "choice)")
@@ -549,12 +555,42 @@ def main():
 
     flags = F.DEFAULT_FLAGS | (F.NO_GRAPH if args.no_graph else 0)
     flags |= {"auto": 0, "one": F.ONE_STEP, "two": F.TWO_STEP}[args.kernel]
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        F.tune_cache_load(args.tune_cache)
+    stored = F.tune_lookup(reps, prec)
     lat = F.Lattice(reps, precision=prec, sample_every=every, flags=flags,
                     chunk_rows=args.chunk_rows)
-    if args.chunk_rows <= 0 and not args.no_autotune:
+    tuned = args.chunk_rows <= 0 and not args.no_autotune
+    if tuned:
         lat.autotune(50)
+        if args.tune_cache:
+            F.tune_cache_save(args.tune_cache)
     # the launch configuration the timed steps use (kernel and row ranges)
     spl, chunk = lat.launch_config()
+    tuning = {"autotuned": tuned, "stored": list(stored) if stored else None,
+              "reproduces_stored": (tuple(stored) == (spl, chunk)) if (stored and tuned)
+              else None}
+    # roofline leg: the step kernel alone (no sampling), same batch and launch
+    # configuration; one launch advances spl steps, so its algorithmic bytes
+    # are spl x 144 B (FP32) per node.  It runs first, for about 0.3 s: the
+    # GPU lowers its clocks within milliseconds of idling and takes about
+    # 0.2 s of load to raise them again, so the timed steps that follow it
+    # (after their own warm-up steps) see the clocks a long run sees.
+    kflag = F.TWO_STEP if spl == 2 else F.ONE_STEP
+    lat_r = F.Lattice(reps, precision=prec, sample_every=0,
+                      flags=(flags & ~(F.ONE_STEP | F.TWO_STEP)) | kflag, chunk_rows=chunk)
+    assert lat_r.launch_config() == (spl, chunk)
+    lat_r.step(100)
+    ms_probe = _events_time(lat_r, 20)
+    nr = max(50, int(300.0 / max(ms_probe / 20, 1e-3)))
+    nr += nr % spl
+    ms_r = _events_time(lat_r, nr)
+    t_step = ms_r / 1e3 / nr
+    t_launch = t_step * spl
+    alg_launch = bytes_per_node * nodes * spl
+    achieved = alg_launch / t_launch / 1e9
+    kernel = "k_step2" if spl == 2 else "k_step"
+
     lat.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -563,24 +599,8 @@ def main():
     wall = time.perf_counter() - t0
     sec = ms / 1e3
     mlups = nodes * args.steps / sec / 1e6
+    del lat_r       # freed after the timed steps: its teardown would idle the GPU
 
-    # roofline leg: the step kernel alone (no sampling), same batch and launch
-    # configuration; one launch advances spl steps, so its algorithmic bytes
-    # are spl x 144 B (FP32) per node
-    kflag = F.TWO_STEP if spl == 2 else F.ONE_STEP
-    lat_r = F.Lattice(reps, precision=prec, sample_every=0,
-                      flags=(flags & ~(F.ONE_STEP | F.TWO_STEP)) | kflag, chunk_rows=chunk)
-    assert lat_r.launch_config() == (spl, chunk)
-    lat_r.step(min(args.warmup, 100))
-    nr = max(50, min(args.steps, 1000))
-    nr += nr % spl
-    ms_r = _events_time(lat_r, nr)
-    t_step = ms_r / 1e3 / nr
-    t_launch = t_step * spl
-    alg_launch = bytes_per_node * nodes * spl
-    achieved = alg_launch / t_launch / 1e9
-    del lat_r
-    kernel = "k_step2" if spl == 2 else "k_step"
     # the counter record is of the ensemble's step kernel
     traffic = _traffic_from_profiles(kernel) if args.workload == "batched96" else None
     copy_gbs = copy_ceiling_gbs()
@@ -601,7 +621,7 @@ def main():
         "config": {"workload": args.workload, "description": desc, "nodes": nodes,
                    "storage": "fp32-deviation" if prec == F.FP32_DEV else "fp64",
                    "sample_every": every, "kernel": kernel, "steps_per_launch": spl,
-                   "chunk_rows": chunk, "parallelism": "single GPU"},
+                   "chunk_rows": chunk, "tuning": tuning, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,

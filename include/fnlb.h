@@ -187,6 +187,23 @@ int fnlb_step(fnlb_handle* h, int64_t n);
  * Synchronises the stream; *chunk_rows_out (nullable) receives the rows. */
 int fnlb_autotune(fnlb_handle* h, int32_t steps_per_trial, int32_t* chunk_rows_out);
 
+/* The autotuner's choices, per precision and multiset of lattice shapes, are
+ * kept for the life of the process and may be saved to and loaded from a
+ * text file keyed also by the GPU architecture (entries of other
+ * architectures in the file are kept by save and ignored by load).
+ * fnlb_tune_lookup: *found = 1 and the stored choice if there is one for
+ * these replicas and precision, else *found = 0.
+ * fnlb_tune_cache_save: writes every choice of this process for the current
+ * device's architecture to path (replaced atomically).  FNLB_EINVAL if the
+ * file cannot be written.
+ * fnlb_tune_cache_load: adds the file's entries for the current device's
+ * architecture to the process's choices.  FNLB_EINVAL if the file cannot be
+ * read or is not a tuning file. */
+int fnlb_tune_lookup(const fnlb_replica_params* reps, int32_t n_rep, int32_t precision,
+                     int32_t* found, int32_t* steps_per_launch, int32_t* chunk_rows);
+int fnlb_tune_cache_save(const char* path);
+int fnlb_tune_cache_load(const char* path);
+
 /* The launch configuration in use: steps each launch of the state advances
  * (1, or 2 with the two-step kernel) and rows per work item.  Either pointer
  * may be NULL. */

@@ -8,10 +8,11 @@ from .fnlb import (ASTAR, DEFAULT_FLAGS, FIELD_C, FIELD_RHO, FIELD_UX, FIELD_UZ,
                    FP32_DEV, FP64, NO_GRAPH, NOISE_LOC, ONE_STEP, SAMPLE_VELOCITY, STATIC_WORK_BYTES,
                    TWO_STEP,
                    WALL_UZ_FIX, FnlbError,
-                   Lattice, bytes_required, load, p_misfit, sq_misfit)
+                   Lattice, bytes_required, load, p_misfit, sq_misfit, tune_cache_load,
+                   tune_cache_save, tune_lookup)
 
 __all__ = ["ASTAR", "DEFAULT_FLAGS", "FIELD_C", "FIELD_RHO", "FIELD_UX", "FIELD_UZ",
            "FORCE_LITERAL", "FP32_DEV", "FP64", "NO_GRAPH", "NOISE_LOC", "SAMPLE_VELOCITY",
            "STATIC_WORK_BYTES", "TWO_STEP", "ONE_STEP",
            "WALL_UZ_FIX", "FnlbError", "Lattice", "bytes_required", "load", "p_misfit",
-           "sq_misfit"]
+           "sq_misfit", "tune_cache_load", "tune_cache_save", "tune_lookup"]

@@ -8,6 +8,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -184,6 +186,20 @@ std::string tune_key(const fnlb_replica_params* reps, int n_rep, int precision) 
 }
 
 // (a negative value: that many rows with the two-step kernel)
+// The tuning file: a header line, comment lines starting with '#', and one
+// line per entry,
+// "<device architecture>\t<precision|shapes>\t<rows, negative for two steps>".
+constexpr char kTuneMagic[] = "fnlb-tune 1";
+
+// the current device's architecture name (e.g. gfx950:sramecc+:xnack-)
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "unknown";
+  return std::string(prop.gcnArchName);
+}
+
 int cached_chunk(const fnlb_replica_params* reps, int n_rep, int precision) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune_cache.find(tune_key(reps, n_rep, precision));
@@ -549,6 +565,9 @@ hipError_t capture_period(fnlb_handle* h, int parity) {
   if (le != hipSuccess) e = le;
   if (e == hipSuccess) e = hipGraphInstantiate(&h->graph[parity], g, nullptr, nullptr, 0);
   if (g) (void)hipGraphDestroy(g);
+  // upload it now, so that its first launch costs what every launch costs
+  if (e == hipSuccess) e = hipGraphUpload(h->graph[parity], h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   return e;
 }
 
@@ -860,6 +879,87 @@ int fnlb_autotune(fnlb_handle* h, int32_t steps_per_trial, int32_t* chunk_rows_o
         best.two ? -best.rows : best.rows;
   }
   if (chunk_rows_out) *chunk_rows_out = best.rows;
+  return FNLB_OK;
+}
+
+int fnlb_tune_lookup(const fnlb_replica_params* reps, int32_t n_rep, int32_t precision,
+                     int32_t* found, int32_t* steps_per_launch, int32_t* chunk_rows) {
+  if (!reps || n_rep <= 0 || !found) return FNLB_EINVAL;
+  const int v = cached_chunk(reps, n_rep, precision);
+  *found = v != 0;
+  if (steps_per_launch) *steps_per_launch = v < 0 ? 2 : 1;
+  if (chunk_rows) *chunk_rows = std::abs(v);
+  return FNLB_OK;
+}
+
+int fnlb_tune_cache_save(const char* path) {
+  if (!path) return FNLB_EINVAL;
+  const std::string arch = device_arch();
+  // entries of other architectures already in the file are kept
+  std::vector<std::string> keep;
+  if (FILE* f = std::fopen(path, "r")) {
+    char line[4096];
+    while (std::fgets(line, sizeof line, f)) {
+      std::string l(line);
+      if (l.rfind(kTuneMagic, 0) == 0 || l.rfind("#", 0) == 0) continue;
+      if (l.compare(0, arch.size() + 1, arch + "\t") != 0) keep.push_back(l);
+    }
+    std::fclose(f);
+  }
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return FNLB_EINVAL;
+  bool ok = std::fprintf(f, "%s\n# device %s\n", kTuneMagic, arch.c_str()) > 0;
+  for (const std::string& l : keep) ok = ok && std::fputs(l.c_str(), f) >= 0;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& e : g_tune_cache)
+      ok = ok && std::fprintf(f, "%s\t%s\t%d\n", arch.c_str(), e.first.c_str(), e.second) > 0;
+  }
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return FNLB_EINVAL;
+  }
+  return FNLB_OK;
+}
+
+int fnlb_tune_cache_load(const char* path) {
+  if (!path) return FNLB_EINVAL;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return FNLB_EINVAL;
+  const std::string arch = device_arch();
+  char line[4096];
+  bool first = true, ok = true;
+  std::map<std::string, int> entries;
+  while (std::fgets(line, sizeof line, f)) {
+    std::string l(line);
+    while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+    if (first) {
+      ok = l == kTuneMagic;
+      first = false;
+      if (!ok) break;
+      continue;
+    }
+    if (l.empty() || l[0] == '#') continue;  // comments
+    const size_t a = l.find('\t'), b = l.rfind('\t');
+    if (a == std::string::npos || b == a) {
+      ok = false;
+      break;
+    }
+    if (l.compare(0, a, arch) != 0) continue;  // tuned on another architecture
+    char* end = nullptr;
+    const long v = std::strtol(l.c_str() + b + 1, &end, 10);
+    if (!end || *end != 0 || v == 0) {
+      ok = false;
+      break;
+    }
+    entries[l.substr(a + 1, b - a - 1)] = (int)v;
+  }
+  std::fclose(f);
+  if (!ok || first) return FNLB_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& e : entries) g_tune_cache[e.first] = e.second;
   return FNLB_OK;
 }
 

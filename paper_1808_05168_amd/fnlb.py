@@ -51,7 +51,8 @@ EXPORTS = ["fnlb_bytes_required", "fnlb_init", "fnlb_step", "fnlb_autotune",
            "fnlb_checkpoint_bytes", "fnlb_save", "fnlb_load", "fnlb_pressure_misfit_gradient",
            "fnlb_build_id", "fnlb_init_static_work", "fnlb_reinit", "fnlb_sq_misfit",
            "fnlb_pressure_misfit", "fnlb_misfit_backward", "fnlb_step_vjp",
-           "fnlb_launch_config"]
+           "fnlb_launch_config", "fnlb_tune_lookup", "fnlb_tune_cache_save",
+           "fnlb_tune_cache_load"]
 STATIC_WORK_BYTES = 128 << 20  # FNLB_STATIC_WORK_BYTES
 
 
@@ -63,6 +64,9 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise FnlbError(f"{path} not found: build it with `python -m paper_1808_05168_amd.build`")
+    # torch brings its own HIP runtime; it must be the one in the process
+    # before the library's first HIP call, or torch later finds no GPU
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     lib.fnlb_build_id.restype = ctypes.c_char_p
     from . import build as _build
@@ -83,6 +87,10 @@ def load(path: str = LIB_PATH):
     lib.fnlb_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.fnlb_launch_config.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32)]
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.fnlb_tune_lookup.argtypes = [rp, ctypes.c_int32, ctypes.c_int32, i32p, i32p, i32p]
+    lib.fnlb_tune_cache_save.argtypes = [ctypes.c_char_p]
+    lib.fnlb_tune_cache_load.argtypes = [ctypes.c_char_p]
     lib.fnlb_accumulate_structure_factor.argtypes = [vp]
     lib.fnlb_read_structure_factor.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, dp, dp, dp,
                                                i64p]
@@ -145,6 +153,25 @@ def bytes_required(reps: Sequence, precision: int = FP64, sample_every: int = 0,
     _check(lib.fnlb_bytes_required(p, len(reps), ctypes.byref(o), ctypes.byref(s),
                                    ctypes.byref(a), ctypes.byref(w)), "fnlb_bytes_required")
     return s.value, a.value, w.value
+
+
+def tune_lookup(reps: Sequence, precision: int):
+    """The autotuner's stored (steps per launch, rows per work item) for these
+    replicas and precision, or None."""
+    f, k, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().fnlb_tune_lookup(replica_params(reps), len(reps), precision, ctypes.byref(f),
+                                   ctypes.byref(k), ctypes.byref(c)), "fnlb_tune_lookup")
+    return (int(k.value), int(c.value)) if f.value else None
+
+
+def tune_cache_save(path: str) -> None:
+    """Writes the autotuner's choices of this process to a text file."""
+    _check(load().fnlb_tune_cache_save(os.fsencode(path)), "fnlb_tune_cache_save")
+
+
+def tune_cache_load(path: str) -> None:
+    """Adds a tuning file's choices for the current GPU architecture."""
+    _check(load().fnlb_tune_cache_load(os.fsencode(path)), "fnlb_tune_cache_load")
 
 
 class Lattice:

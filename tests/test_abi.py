@@ -81,3 +81,34 @@ def test_init_rejects_null_and_small_buffers(lib):
     assert rc == -1 and not h.value
     assert lib.fnlb_step(None, 1) == -1
     assert lib.fnlb_destroy(None) == 0
+
+
+def test_tune_cache_file_round_trip(lib, tmp_path):
+    """The autotuner's choices go to a text file keyed by GPU architecture,
+    precision and the multiset of lattice shapes, and come back from it; entries
+    of another architecture are kept but not used; other files are refused."""
+    import paper_1808_05168_amd as F
+    a = tmp_path / "a.txt"
+    F.tune_cache_save(str(a))
+    lines = a.read_text().splitlines()
+    assert lines[0] == "fnlb-tune 1" and lines[1].startswith("# device ")
+    arch = lines[1][len("# device "):]
+    ens = W.batched_ensemble(96)
+    key = "1|64x32*24|128x64*24|256x128*24|512x256*24"
+    b = tmp_path / "b.txt"
+    b.write_text(f"fnlb-tune 1\n{arch}\t{key}\t-32\nsome-other-gpu\t1|64x32*1\t7\n")
+    F.tune_cache_load(str(b))
+    assert F.tune_lookup(ens, F.FP32_DEV) == (2, 32)
+    assert F.tune_lookup(ens, F.FP64) is None
+    assert F.tune_lookup([W.parity_small()], F.FP32_DEV) is None
+    c = tmp_path / "c.txt"
+    c.write_text(f"fnlb-tune 1\nsome-other-gpu\t{key}\t5\n")
+    F.tune_cache_save(str(c))
+    text = c.read_text()
+    assert f"{arch}\t{key}\t-32" in text and "some-other-gpu" in text
+    bad = tmp_path / "bad.txt"
+    bad.write_text("not a tuning file\n")
+    with pytest.raises(F.FnlbError):
+        F.tune_cache_load(str(bad))
+    with pytest.raises(F.FnlbError):
+        F.tune_cache_load(str(tmp_path / "missing.txt"))

@@ -71,7 +71,7 @@ def test_summarize_profile_scales_counters_and_picks_the_roofline_leg(
     assert d["write_bytes"] == round(50.0 * 1024)
     assert d["bytes_per_launch"] == d["read_bytes"] + d["write_bytes"]
     assert d["algorithmic_bytes"] == 144 * sum(r.Lx * r.Lz for r in W.batched_ensemble(96))
-    assert d["source_sha256"] == bench._step_source_hash()
+    assert d["source_sha256"] == bench._step_source_hash("k_step")
     assert d["kernel"] == "k_step" and d["steps_per_launch"] == 1
     text = md.read_text()
     assert "the commands" in text and "FETCH x2.0000, WRITE x1.0000" in text
@@ -114,6 +114,11 @@ def test_summarize_profile_of_the_two_step_kernel(tmp_path, monkeypatch):
     assert d["step_avg_us"] == pytest.approx(3.0)
     assert d["algorithmic_bytes"] == 2 * 144 * sum(r.Lx * r.Lz for r in W.batched_ensemble(96))
     assert bench._traffic_from_profiles("k_step2") == d["bytes_per_launch"]
+    # the record is hashed over the two-step kernel's own sources only: an
+    # edit of the one-step kernel leaves it current
+    assert "k_step.hip" not in bench.STEP_SOURCES["k_step2"]
+    assert d["source_sha256"] == bench._step_source_hash("k_step2") \
+        != bench._step_source_hash("k_step")
 
 
 def test_summarize_trace_writes_the_command_and_table(profiler_dirs, tmp_path):

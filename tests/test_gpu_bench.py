@@ -40,7 +40,9 @@ def test_bench_line():
     assert rf["achieved"] == pytest.approx(
         rf["algorithmic_bytes_per_launch"] / (rf["launch_ms"] * 1e-3) / 1e9, rel=1e-3)
     assert rf["frac"] == pytest.approx(rf["achieved"] / rf["peak"], abs=1e-4)
-    assert 0 < rf["frac"] < 1 and 0 < rf["frac_of_copy"] < 1.2
+    # a two-step launch moves about half its algorithmic bytes, so its
+    # algorithmic rate may pass the plain copy's up to about twice over
+    assert 0 < rf["frac"] < 1 and 0 < rf["frac_of_copy"] < 1.2 * spl
     # steady state even at 20 steps after 5: the graphs the timed steps replay
     # were captured before the timing began, so a step costs the step kernel
     # plus the sampling's share (about 8% at one sample in 10), not a capture

@@ -2,6 +2,8 @@
 sampling periods is bit-identical to direct launches (checked after every
 chunk of steps, with host reads in between), and the autotuner leaves state
 and time untouched."""
+import os
+
 import numpy as np
 import pytest
 
@@ -137,3 +139,36 @@ def test_sampling_leaves_fp32_trajectory_unchanged(F, flags):
     b.step(37)
     for i in range(len(reps)):
         np.testing.assert_array_equal(a.read_populations(i), b.read_populations(i))
+
+
+def test_autotune_pick_reproduces_across_processes(F, tmp_path):
+    """The benchmark ensemble's autotuned choice (kernel, rows per work item),
+    saved to a tuning file, is what a fresh process finds stored and picks
+    again when it tunes; a handle created there without a row-range length
+    uses the stored choice."""
+    import json
+    import subprocess
+    import sys
+    reps = W.batched_ensemble(96)
+    say("case: autotune, save, and tune again in a fresh process")
+    lat = F.Lattice(reps, precision=F.FP32_DEV, sample_every=10)
+    lat.autotune(20)
+    pick = lat.launch_config()
+    path = tmp_path / "tune.txt"
+    F.tune_cache_save(str(path))
+    code = (
+        "import json, sys; sys.path.insert(0, %r)\n"
+        "import paper_1808_05168_amd as F, workloads as W\n"
+        "F.tune_cache_load(%r)\n"
+        "reps = W.batched_ensemble(96)\n"
+        "stored = F.tune_lookup(reps, F.FP32_DEV)\n"
+        "lat = F.Lattice(reps, precision=F.FP32_DEV, sample_every=10)\n"
+        "used = lat.launch_config()\n"
+        "lat.autotune(20)\n"
+        "print(json.dumps([stored, used, lat.launch_config()]))\n"
+    ) % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))), str(path))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    stored, used, repick = json.loads(r.stdout.strip().splitlines()[-1])
+    say(f"  pick {pick}, stored {stored}, used {used}, picked again {repick}")
+    assert tuple(stored) == pick and tuple(used) == pick and tuple(repick) == pick
