@@ -329,6 +329,8 @@ def summarize_counters(pmc_dir, out_md, command):
     agg = defaultdict(lambda: defaultdict(list))
     for r in csv.DictReader(open(os.path.join(pmc_dir, "run_counter_collection.csv"))):
         name = r["Kernel_Name"].replace("fnlb::(anonymous namespace)::", "")
+        name = name.replace("HIP_vector_type<float, 2u>", "float2")
+        name = name.replace("HIP_vector_type<double, 2u>", "double2")
         name = name.split("(")[0] if "k_step" not in name else name.split("(fnlb")[0]
         agg[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
     lines = ["# SQ counters, batched 96-replica FP32-deviation workload", "",
@@ -336,7 +338,8 @@ def summarize_counters(pmc_dir, out_md, command):
              "```", command.strip(), "```", "",
              "Averages per dispatch of the library's kernels. VALU/node = SQ_INSTS_VALU x 64 "
              "/ 4,177,920 nodes, per step (the two-step kernel's dispatches are divided by "
-             "their two steps). The next two columns are raw ratios of counters to "
+             "their two steps; a column-pass dispatch adds every sample kept in the "
+             "spectrum slots, up to 16). The next two columns are raw ratios of counters to "
              "SQ_WAVE_CYCLES (SQ_ACTIVE_INST_VALU, SQ_WAIT_ANY), summed over the wavefronts "
              "of a dispatch; their cycle units need not match. The last column is "
              "SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS.", "",
@@ -345,7 +348,7 @@ def summarize_counters(pmc_dir, out_md, command):
              "|---|---|---|---|---|---|---|"]
     for name, c in sorted(agg.items()):
         m = {k: sum(v) / len(v) for k, v in c.items()}
-        if not any(k in name for k in ("k_step", "transform", "pressure")):
+        if not any(k in name for k in ("k_step", "transform", "_fft", "pressure")):
             continue
         wc = max(m.get("SQ_WAVE_CYCLES", 1.0), 1.0)
         per = 2 if "k_step2" in name else 1

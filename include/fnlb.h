@@ -166,12 +166,17 @@ int fnlb_init_static_work(const fnlb_replica_params* reps, int32_t n_rep,
  * keeps the state of the middle time in LDS; a pair never spans a sample time
  * other than its first, and results equal those of single steps to FP32
  * rounding).  Whole sampling periods (sample_every steps, or 16
- * steps without sampling) that start on a period boundary are replayed from a
- * HIP graph captured by fnlb_init or fnlb_autotune (periods longer than 1024
- * steps: on first use; none with FNLB_NO_GRAPH).  In the graph the
- * transforms of a sample run on a branch of their own beside the steps that
- * follow it, joined before the period ends; results are identical either
- * way.  Asynchronous: all of it is ordered on the caller's stream. */
+ * steps without sampling) that start on a period boundary are replayed from
+ * HIP graphs captured by fnlb_init or fnlb_autotune (periods longer than 1024
+ * steps: on first use; none with FNLB_NO_GRAPH): one of up to 16 periods while
+ * that many remain (within 1024 steps), else one of a single period.  In a
+ * graph the transforms of each sample run on a branch of their own beside the
+ * steps that follow it, joined before the next sample.  The row transforms of
+ * up to 16 samples are kept and their column transforms done in one pass,
+ * adding the samples in time order; every sample of a call is in the
+ * accumulators when the call's work completes, and results are identical
+ * with or without graphs.  Asynchronous: all of it is ordered on the caller's
+ * stream. */
 int fnlb_step(fnlb_handle* h, int64_t n);
 
 /* Chooses the step kernel and the number of rows each of its work items

@@ -3,6 +3,7 @@
 // synchronous read/write calls of the C ABI (include/fnlb.h).
 #include "fnlb.h"
 #include "fnlb_device.hpp"
+#include "fnlb_fft.hpp"
 #include "fnlb_internal.hpp"
 #include "fnlb_state.hpp"
 
@@ -44,7 +45,13 @@ constexpr int kMaxDirect = 2048;
 // Complex entries of the column-pass LDS tile.
 constexpr int kColTile = 2048;  // complex values per column-transform tile (32 KiB)
 constexpr int kRowGroup = 1024;  // complex values per row-transform block (short rows share)
+// samples per column pass: the row passes of up to this many samples keep
+// their spectra, and one column pass adds them all, reading and writing the
+// FP64 sums once instead of once per sample
+constexpr int kSpecSlots = 16;
 constexpr int kTransformThreads = 256;  // threads of a transform block (at least one per row)
+// lengths the wavefront transforms take
+constexpr bool wave_fft_len(int n) { return n >= kFftMin && n <= kFftMax && (n & (n - 1)) == 0; }
 
 // The two-step kernel takes FP32-deviation storage and whole rows of at most
 // kTBLanes columns.
@@ -95,18 +102,27 @@ int validate(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options*
 struct Plan {
   std::vector<RepInfo> info;
   std::vector<Item> items;
-  std::vector<RowRef> rows;
+  std::vector<RowRef> rows;  // rows and column tiles of the block transforms
   std::vector<ColRef> cols;
+  std::vector<RowTask> frows;  // and of the wavefront transforms (8 to 512 points)
+  std::vector<ColTask> fcols;
   size_t store_size = 0;
   size_t state_half = 0;  // bytes of one state copy
   size_t state_bytes = 0, accum_bytes = 0, work_bytes = 0;
   // work-buffer offsets (bytes)
   size_t o_bm = 0;  // FP64 Box-Muller tables
-  size_t o_reps = 0, o_items = 0, o_rows = 0, o_cols = 0, o_misc = 0, o_tw = 0, o_fields = 0,
-         o_spec = 0, o_ppart = 0;
+  size_t o_rowc = 0;                 // per-row sample constants of every replica
+  std::vector<size_t> rowc_at;       // byte offset of each replica's rows there
+  size_t o_reps = 0, o_items = 0, o_rows = 0, o_cols = 0, o_frows = 0, o_fcols = 0, o_misc = 0,
+         o_tw = 0, o_fields = 0, o_spec = 0, o_ppart = 0;
   size_t item_capacity = 0;  // items the work buffer holds (row ranges of one row)
   int max_lx = 0, max_lz = 0, max_col_lds = 0, max_row_lds = 0, chunk = 0;
   int n_pairs = 1;  // complex row transforms per row: (dc, drho) [, (Ux, Uz)]
+  // samples whose row spectra and pressure row sums are kept before one column
+  // pass adds them all (slots of spec_slot complex pairs of the storage type
+  // and ppart_slot doubles)
+  int spec_slots = 1;
+  size_t spec_slot = 0, ppart_slot = 0;
   // the two-step kernel: eligibility, its blocks of work items, their capacity
   bool tb_ok = false;
   std::vector<PackItem> pitems;
@@ -243,14 +259,18 @@ void fill_bm_tables(BmTables& T) {
   T.ln2 = make_double2(hi, (double)(ln2 - (long double)hi));
 }
 
-void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* opt, Plan& P) {
+void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* opt, Plan& P,
+               int spec_slots) {
   P.store_size = opt->precision == FNLB_FP64 ? 8 : 4;
+  P.spec_slots = spec_slots;
   P.tb_ok = two_step_fits(reps, n_rep, opt->precision);
   int chunk = opt->chunk_rows;
   if (chunk <= 0) chunk = std::abs(cached_chunk(reps, n_rep, opt->precision));
   if (chunk <= 0) chunk = auto_chunk(reps, n_rep);
   P.info.assign(n_rep, RepInfo{});
-  int64_t state_elems = 0, field_d = 0, spec_c = 0, acc_d = 0, ppart_d = 0, tw_c = 0;
+  int64_t state_elems = 0, field_d = 0, spec_c = 0, acc_d = 0, ppart_d = 0, tw_c = 0,
+          rowc_c = 0;
+  P.rowc_at.assign(n_rep, 0);
   // sampled fields: (delta c, delta rho) and, on request, (U_x, U_z)
   const int nf = n_fields(opt->flags);
   P.n_pairs = nf / 2;
@@ -268,17 +288,24 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
     // 256-byte aligned (paired loads of the row pass)
     field_d = (field_d + 256 / P.store_size - 1) / (256 / P.store_size) * (256 / P.store_size);
     R.field_off = field_d;
-    field_d += (int64_t)nf * p.Lz * p.Lx;
+    field_d += (int64_t)nf * p.Lz * p.Lx;  // the pairs
+    // row spectra (complex pairs of the storage type) in whole 128-byte lines
+    // per row, so that the column pass reads each tile row as aligned lines
+    const int line = 128 / (2 * (int)P.store_size);
+    R.spitch = (nkx + line - 1) / line * line;
+    spec_c = (spec_c + line - 1) / line * line;
     R.spec_off = spec_c;
-    spec_c += (int64_t)nf * p.Lz * nkx;
+    spec_c += (int64_t)nf * p.Lz * R.spitch;
     R.acc_off = acc_d;
     acc_d += 3LL * nf * p.Lz * nkx;
     R.pacc_off = acc_d;
     acc_d += 2 + p.Lz;
     R.ppart_off = ppart_d;
-    ppart_d += p.Lz;
+    ppart_d += (int64_t)p.Lz * pressure_parts(p.Lx);
     R.tw_off = tw_c;
     tw_c += p.Lx + p.Lz;
+    P.rowc_at[r] = (size_t)rowc_c * P.store_size;
+    rowc_c += (int64_t)kRowConsts * p.Lz;
     R.flags = opt->flags;
     R.pow2 = is_pow2(p.Lx) && is_pow2(p.Lz);
     R.seed_lo = (uint32_t)p.seed;
@@ -324,22 +351,39 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
     P.item_capacity += (size_t)((R.Lx + kSeg - 1) / kSeg) * R.Lz;
     if (P.tb_ok) P.pitem_capacity += (size_t)R.Lz;  // at most one block per row
   }
-  // rows and column tiles of the transforms
+  // rows and column tiles of the transforms: the wavefront transforms for
+  // lengths of 8 to 512 points (powers of two), the block transforms (longer
+  // rows or columns, or direct sums for other lengths) otherwise
   P.rows.clear();
   P.cols.clear();
+  P.frows.clear();
+  P.fcols.clear();
   P.max_col_lds = 0;
   P.max_row_lds = 0;
   for (int r = 0; r < n_rep; ++r) {
     const RepInfo& R = P.info[r];
-    // short power-of-two rows are transformed several to a block
-    const int per = R.pow2 ? std::min(kTransformThreads, std::max(1, kRowGroup / R.Lx)) : 1;
-    for (int j = 0; j < R.Lz; j += per) {
-      const int nr = std::min(per, R.Lz - j);
-      P.rows.push_back(RowRef{r, j, nr, 0});
-      // the rows, plus N/2 twiddles for the power-of-two FFT
-      P.max_row_lds = std::max(P.max_row_lds, nr * R.Lx + (R.pow2 ? R.Lx / 2 : 0));
-    }
     const int nkx = R.Lx / 2 + 1;
+    if (wave_fft_len(R.Lx)) {
+      const int per = kFftMax / R.Lx;  // rows per wavefront
+      for (int j = 0; j < R.Lz; j += per)
+        P.frows.push_back(RowTask{r, j, std::min(per, R.Lz - j), 0});
+    } else {
+      // short power-of-two rows are transformed several to a block
+      const int per = R.pow2 ? std::min(kTransformThreads, std::max(1, kRowGroup / R.Lx)) : 1;
+      for (int j = 0; j < R.Lz; j += per) {
+        const int nr = std::min(per, R.Lz - j);
+        P.rows.push_back(RowRef{r, j, nr, 0});
+        // the rows, plus N/2 twiddles for the power-of-two FFT
+        P.max_row_lds = std::max(P.max_row_lds, nr * R.Lx + (R.pow2 ? R.Lx / 2 : 0));
+      }
+    }
+    if (wave_fft_len(R.Lz)) {
+      const int tile = 4 * kFftMax / R.Lz;  // columns per block
+      for (int f = 0; f < nf; ++f)
+        for (int k0 = 0; k0 < nkx; k0 += tile)
+          P.fcols.push_back(ColTask{r, f, k0, std::min(tile, nkx - k0)});
+      continue;
+    }
     int lt = 0;  // tile of 2^lt columns: at most 16 and at most kColTile values
     while (lt < 4 && (2 << lt) * R.Lz <= kColTile) ++lt;
     const int tile = 1 << lt;
@@ -365,19 +409,36 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
   o = align_up(o + P.rows.size() * sizeof(RowRef));
   P.o_cols = o;
   o = align_up(o + P.cols.size() * sizeof(ColRef));
+  P.o_frows = o;
+  o = align_up(o + P.frows.size() * sizeof(RowTask));
+  P.o_fcols = o;
+  o = align_up(o + P.fcols.size() * sizeof(ColTask));
   P.o_misc = o;  // int64 time base + int32 watchdog
   o = align_up(o + 16);
   P.o_bm = o;
   o = align_up(o + sizeof(BmTables));
+  P.o_rowc = o;
+  o = align_up(o + (size_t)rowc_c * P.store_size);
   P.o_tw = o;
   o = align_up(o + (size_t)tw_c * 16);
   P.o_fields = o;
   o = align_up(o + (size_t)field_d * P.store_size);
+  P.spec_slot = (size_t)spec_c;  // whole 128-byte lines
+  P.ppart_slot = (size_t)ppart_d;
   P.o_spec = o;
-  o = align_up(o + (size_t)spec_c * 16);
+  o = align_up(o + P.spec_slots * P.spec_slot * 2 * P.store_size);
   P.o_ppart = o;
-  o = align_up(o + (size_t)ppart_d * 8);
+  o = align_up(o + P.spec_slots * P.ppart_slot * 8);
   P.work_bytes = o;
+}
+
+// Device addresses of the tables the replicas share (Box-Muller) or own (row
+// constants) in the work buffer at `work`.
+void set_table_pointers(Plan& P, char* work) {
+  for (size_t r = 0; r < P.info.size(); ++r) {
+    P.info[r].bm = (const BmTables*)(work + P.o_bm);
+    P.info[r].rowc = work + P.o_rowc + P.rowc_at[r];
+  }
 }
 
 }  // namespace
@@ -395,14 +456,18 @@ struct fnlb_handle {
   int64_t t_dev = 0;     // value held by the device time base
   int64_t nsamples = 0;
   int error = FNLB_OK;   // sticky error
-  // one sampling period captured as a graph, per parity of the starting copy;
-  // in it the transforms of the sample run on a branch of their own (captured
-  // from obs_stream) beside the plain steps that follow
+  // sampling periods captured as graphs, per parity of the starting copy:
+  // graph[0] holds one period; graph[1], when sampling, kgraph periods whose
+  // samples fill the spectrum slots in turn and share one column pass at the
+  // end.  In them the transforms of each sample run on a branch of their own
+  // (captured from obs_stream) beside the plain steps that follow.
   hipStream_t cap_stream = nullptr, obs_stream = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork[kSpecSlots] = {}, ev_join[kSpecSlots] = {};
+  hipGraphExec_t graph[2][2] = {};  // [kind][parity]
+  int graph_launches[2] = {};       // kernel launches of the state in each kind
+  int kgraph = 0;                   // periods of graph[1] (0: no such graph)
+  int pending = 0;  // samples in the spectrum slots that no column pass has added yet
   int64_t period = 0;
-  int period_launches = 0;  // kernel launches of the state in one captured period
   bool two_step = false;    // pairs of steps run in the two-step kernel
   int static_dev = -1;   // device whose static workspace this handle holds, or -1
   // the last forward sweep of a misfit, kept for its reverse sweep
@@ -420,12 +485,18 @@ struct fnlb_handle {
   PackItem* d_pitems() { return (PackItem*)(work + plan.o_pitems); }
   RowRef* d_rows() { return (RowRef*)(work + plan.o_rows); }
   ColRef* d_cols() { return (ColRef*)(work + plan.o_cols); }
+  RowTask* d_frows() { return (RowTask*)(work + plan.o_frows); }
+  ColTask* d_fcols() { return (ColTask*)(work + plan.o_fcols); }
   int64_t* d_time() { return (int64_t*)(work + plan.o_misc); }
   int32_t* d_watchdog() { return (int32_t*)(work + plan.o_misc + 8); }
   double2* d_tw() { return (double2*)(work + plan.o_tw); }
   void* d_fields() { return (void*)(work + plan.o_fields); }
-  double2* d_spec() { return (double2*)(work + plan.o_spec); }
-  double* d_ppart() { return (double*)(work + plan.o_ppart); }
+  void* d_spec(int slot = 0) {
+    return work + plan.o_spec + (size_t)slot * plan.spec_slot * 2 * plan.store_size;
+  }
+  double* d_ppart(int slot = 0) {
+    return (double*)(work + plan.o_ppart) + (size_t)slot * plan.ppart_slot;
+  }
   char* state_copy(int k) { return state + (size_t)k * plan.state_half; }
 };
 
@@ -437,7 +508,7 @@ int dev_err(fnlb_handle* h, hipError_t e) {
   return FNLB_EDEVICE;
 }
 
-StepArgs step_args(fnlb_handle* h, int64_t t_off) {
+StepArgs step_args(fnlb_handle* h, int64_t t_off, int slot = 0) {
   StepArgs a{};
   a.reps = h->d_reps();
   a.items = h->d_items();
@@ -450,10 +521,12 @@ StepArgs step_args(fnlb_handle* h, int64_t t_off) {
   a.t_base = h->d_time();
   a.t_off = t_off;
   a.fields = h->d_fields();
+  a.ppart = h->d_ppart(slot);
+  a.watchdog = h->d_watchdog();
   return a;
 }
 
-Step2Args step2_args(fnlb_handle* h, int64_t t_off) {
+Step2Args step2_args(fnlb_handle* h, int64_t t_off, int slot = 0) {
   Step2Args a{};
   a.reps = h->d_reps();
   a.items = h->d_pitems();
@@ -464,6 +537,8 @@ Step2Args step2_args(fnlb_handle* h, int64_t t_off) {
   a.t_base = h->d_time();
   a.t_off = t_off;
   a.fields = h->d_fields();
+  a.ppart = h->d_ppart(slot);
+  a.watchdog = h->d_watchdog();
   return a;
 }
 
@@ -476,102 +551,155 @@ bool pair_at(const fnlb_handle* h, int64_t t, int64_t n) {
 }
 
 // One launch of the state from time t: two steps or one, sampling f(t) when t
-// is a sample time; returns the steps taken (0 on error, e set).
-int launch_state(fnlb_handle* h, int64_t t_off, bool pair, bool smp, hipStream_t s,
+// is a sample time (its pressure sums into spectrum slot `slot`); returns the
+// steps taken (0 on error, e set).
+int launch_state(fnlb_handle* h, int64_t t_off, bool pair, bool smp, int slot, hipStream_t s,
                  hipError_t& e) {
   if (pair) {
-    e = launch_step2(smp ? kStepSample : kStep, step2_args(h, t_off), s);
+    e = launch_step2(smp ? kStepSample : kStep, step2_args(h, t_off, slot), s);
     return e == hipSuccess ? 2 : 0;
   }
-  e = launch_step(h->opt.precision, smp ? kStepSample : kStep, step_args(h, t_off), s);
+  e = launch_step(h->opt.precision, smp ? kStepSample : kStep, step_args(h, t_off, slot), s);
   return e == hipSuccess ? 1 : 0;
 }
 
-// Structure-factor transforms and pressure reduction of the sample fields.
-hipError_t observe(fnlb_handle* h, hipStream_t s, double* acc = nullptr) {
+// Row passes of one sample into spectrum slot `slot`: the sampled pairs the
+// step stored are transformed along x (the step has put the sample's pressure
+// sums in the slot).
+hipError_t observe_rows(fnlb_handle* h, hipStream_t s, int slot) {
+  const Plan& P = h->plan;
+  hipError_t e = launch_row_fft(h->d_reps(), h->d_frows(), (int)P.frows.size(), P.n_pairs,
+                                h->opt.precision, h->d_fields(), h->d_spec(slot), h->d_tw(), s);
+  if (e == hipSuccess)
+    e = launch_row_transform(h->d_reps(), h->d_rows(), (int)P.rows.size(), P.n_pairs,
+                             P.max_row_lds, h->opt.precision, h->d_fields(), h->d_spec(slot),
+                             h->d_tw(), s);
+  return e;
+}
+
+// Column passes over the samples in slots 0 .. nslots - 1, added to the
+// accumulators (or to acc) in slot order.
+hipError_t observe_cols(fnlb_handle* h, hipStream_t s, int nslots, double* acc = nullptr) {
   const Plan& P = h->plan;
   if (!acc) acc = (double*)h->accum;
-  hipError_t e = launch_row_transform(h->d_reps(), h->d_rows(), (int)P.rows.size(), P.n_pairs,
-                                      P.max_row_lds, h->opt.precision, h->d_fields(),
-                                      h->d_spec(), h->d_tw(),
-                                      h->d_ppart(), h->d_watchdog(), s);
-  if (e != hipSuccess) return e;
-  return launch_col_transform(h->d_reps(), h->d_cols(), (int)P.cols.size(), P.max_col_lds,
-                              h->d_spec(), acc, h->d_tw(), h->d_ppart(), s);
+  hipError_t e = launch_col_fft(h->d_reps(), h->d_fcols(), (int)P.fcols.size(),
+                                h->opt.precision, h->d_spec(), nslots, P.spec_slot, acc,
+                                h->d_tw(), h->d_ppart(), P.ppart_slot, s);
+  if (e == hipSuccess)
+    e = launch_col_transform(h->d_reps(), h->d_cols(), (int)P.cols.size(), P.max_col_lds,
+                             h->opt.precision, h->d_spec(), nslots, P.spec_slot, acc,
+                             h->d_tw(), h->d_ppart(), P.ppart_slot, s);
+  return e;
+}
+
+// Structure-factor transforms and pressure reduction of one sample at once.
+hipError_t observe(fnlb_handle* h, hipStream_t s, double* acc = nullptr) {
+  hipError_t e = observe_rows(h, s, 0);
+  if (e == hipSuccess) e = observe_cols(h, s, 1, acc);
+  return e;
+}
+
+// The column pass of the samples still kept in the slots (fnlb_step leaves
+// none behind, and a graph replay starts from the first slot).
+hipError_t flush_samples(fnlb_handle* h) {
+  hipError_t e = hipSuccess;
+  if (h->pending > 0) e = observe_cols(h, h->stream, h->pending);
+  h->pending = 0;
+  return e;
 }
 
 void drop_graphs(fnlb_handle* h) {
-  for (auto& g : h->graph)
-    if (g) {
-      (void)hipGraphExecDestroy(g);
-      g = nullptr;
-    }
+  for (auto& gp : h->graph)
+    for (auto& g : gp)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
 }
 
-// Captures one period of `period` steps starting at a period start, from
-// state copy `parity`: the first step samples when sampling is on, and the
-// last node advances the device time counter by the period.  Kernels read
-// their time as counter + offset, so one graph serves every period.  The
-// transforms of the sample form a branch that forks after the sampling step
-// and joins before the last node: they read only the sample buffer and write
-// only the spectra, pressure sums and accumulators, which no step touches, and
-// the next sample is taken by the next period.
-hipError_t capture_period(fnlb_handle* h, int parity) {
+// periods in a graph of kind `which` (0: one, 1: kgraph)
+int graph_periods(const fnlb_handle* h, int which) { return which ? h->kgraph : 1; }
+
+// Captures `graph_periods(which)` periods of `period` steps starting at a
+// period start, from state copy `parity`: the first step of each period
+// samples when sampling is on, and the last node advances the device time
+// counter by the steps of the graph.  Kernels read their time as counter +
+// offset, so one graph serves every start.  The transforms of each sample form
+// a branch that forks after the sampling step and joins before the next
+// sampling step (which overwrites the sample buffer) or the last node: they
+// read only the sample buffer and write only the spectra, pressure sums and
+// accumulators, which no step touches.  The sample of period p keeps its row
+// spectra in slot p, and the branch of the last sample runs the column pass
+// over every slot of the graph.
+hipError_t capture_periods(fnlb_handle* h, int which, int parity) {
   hipError_t e = hipSuccess;
   if (!h->cap_stream) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
   if (e == hipSuccess && !h->obs_stream)
     e = hipStreamCreateWithFlags(&h->obs_stream, hipStreamNonBlocking);
-  if (e == hipSuccess && !h->ev_fork) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
-  if (e == hipSuccess && !h->ev_join) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
+  for (int k = 0; k < kSpecSlots && e == hipSuccess; ++k) {
+    if (!h->ev_fork[k]) e = hipEventCreateWithFlags(&h->ev_fork[k], hipEventDisableTiming);
+    if (e == hipSuccess && !h->ev_join[k])
+      e = hipEventCreateWithFlags(&h->ev_join[k], hipEventDisableTiming);
+  }
   if (e != hipSuccess) return e;
   hipStream_t s = h->cap_stream;
   e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
   const bool sampling = h->opt.sample_every > 0;
+  const int nper = graph_periods(h, which);
+  const int64_t len = nper * h->period;
   const int saved = h->cur;
   h->cur = parity;
   hipError_t le = hipSuccess;
-  bool forked = false;
+  int joins = -1;  // the branch that has yet to join (-1: none)
   int launches = 0;
-  for (int64_t k = 0; k < h->period && le == hipSuccess;) {
-    const bool smp = sampling && k == 0;
-    // a period starts at a sample time and holds no other
-    const int took = launch_state(h, k, pair_at(h, k, h->period - k), smp, s, le);
+  for (int64_t k = 0; k < len && le == hipSuccess;) {
+    const int per = (int)(k / h->period);
+    // each period starts at a sample time and holds no other
+    const bool smp = sampling && k % h->period == 0;
+    if (smp && joins >= 0) {
+      le = hipStreamWaitEvent(s, h->ev_join[joins], 0);
+      joins = -1;
+      if (le != hipSuccess) break;
+    }
+    const int took = launch_state(h, k, pair_at(h, k, len - k), smp, per, s, le);
     k += took > 0 ? took : 1;
     ++launches;
     if (le == hipSuccess && smp) {
-      le = hipEventRecord(h->ev_fork, s);
-      if (le == hipSuccess) le = hipStreamWaitEvent(h->obs_stream, h->ev_fork, 0);
+      le = hipEventRecord(h->ev_fork[per], s);
+      if (le == hipSuccess) le = hipStreamWaitEvent(h->obs_stream, h->ev_fork[per], 0);
       if (le == hipSuccess) {
-        forked = true;
-        le = observe(h, h->obs_stream);
+        joins = per;
+        le = observe_rows(h, h->obs_stream, per);
+        if (le == hipSuccess && per == nper - 1) le = observe_cols(h, h->obs_stream, nper);
         // recorded even after a failed launch, so that the branch can join
-        const hipError_t re = hipEventRecord(h->ev_join, h->obs_stream);
+        const hipError_t re = hipEventRecord(h->ev_join[per], h->obs_stream);
         if (le == hipSuccess) le = re;
       }
     }
     h->cur ^= 1;
   }
-  h->period_launches = launches;
+  h->graph_launches[which] = launches;
   // the branch always joins, so that the capture can end
-  if (forked) {
-    const hipError_t je = hipStreamWaitEvent(s, h->ev_join, 0);
+  if (joins >= 0) {
+    const hipError_t je = hipStreamWaitEvent(s, h->ev_join[joins], 0);
     if (le == hipSuccess) le = je;
   }
-  if (le == hipSuccess) le = launch_advance_time(h->d_time(), h->period, s);
+  if (le == hipSuccess) le = launch_advance_time(h->d_time(), len, s);
   h->cur = saved;
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(s, &g);
   if (le != hipSuccess) e = le;
-  if (e == hipSuccess) e = hipGraphInstantiate(&h->graph[parity], g, nullptr, nullptr, 0);
+  hipGraphExec_t& x = h->graph[which][parity];
+  if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
   if (g) (void)hipGraphDestroy(g);
   // upload it now, so that its first launch costs what every launch costs
-  if (e == hipSuccess) e = hipGraphUpload(h->graph[parity], h->stream);
+  if (e == hipSuccess) e = hipGraphUpload(x, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   return e;
 }
 
-// Periods up to this many steps are captured when the handle is created (and
+// Graphs of up to this many steps are captured when the handle is created (and
 // again after fnlb_autotune changes the work items), so that fnlb_step never
 // captures or instantiates a graph; longer periods are captured on first use.
 constexpr int64_t kPrecapturePeriod = 1024;
@@ -579,25 +707,28 @@ constexpr int64_t kPrecapturePeriod = 1024;
 hipError_t prepare_graphs(fnlb_handle* h) {
   if ((h->opt.flags & FNLB_NO_GRAPH) || h->period > kPrecapturePeriod) return hipSuccess;
   hipError_t e = hipSuccess;
-  for (int parity = 0; parity < 2 && e == hipSuccess; ++parity)
-    if (!h->graph[parity]) e = capture_period(h, parity);
+  for (int which = 0; which < (h->kgraph > 1 ? 2 : 1); ++which)
+    for (int parity = 0; parity < 2 && e == hipSuccess; ++parity)
+      if (!h->graph[which][parity]) e = capture_periods(h, which, parity);
   return e;
 }
 
-// Runs one captured period on the caller's stream.
-int replay_period(fnlb_handle* h) {
+// Runs one captured graph of kind `which` on the caller's stream.
+int replay_periods(fnlb_handle* h, int which) {
   hipError_t e = hipSuccess;
   if (h->t_dev != h->t) {  // bring the device time counter to the period start
     e = launch_advance_time(h->d_time(), h->t - h->t_dev, h->stream);
     h->t_dev = h->t;
   }
-  if (e == hipSuccess && !h->graph[h->cur]) e = capture_period(h, h->cur);
-  if (e == hipSuccess) e = hipGraphLaunch(h->graph[h->cur], h->stream);
+  hipGraphExec_t& x = h->graph[which][h->cur];
+  if (e == hipSuccess && !x) e = capture_periods(h, which, h->cur);
+  if (e == hipSuccess) e = hipGraphLaunch(x, h->stream);
   if (e != hipSuccess) return dev_err(h, e);
-  h->t += h->period;
-  h->t_dev += h->period;
-  if (h->period_launches & 1) h->cur ^= 1;
-  if (h->opt.sample_every > 0) ++h->nsamples;
+  const int nper = graph_periods(h, which);
+  h->t += nper * h->period;
+  h->t_dev += nper * h->period;
+  if (h->graph_launches[which] & 1) h->cur ^= 1;
+  if (h->opt.sample_every > 0) h->nsamples += nper;
   return FNLB_OK;
 }
 
@@ -639,7 +770,7 @@ int fnlb_bytes_required(const fnlb_replica_params* reps, int32_t n_rep,
   const int rc = validate(reps, n_rep, options);
   if (rc) return rc;
   Plan P;
-  make_plan(reps, n_rep, options, P);
+  make_plan(reps, n_rep, options, P, kSpecSlots);
   if (state_bytes) *state_bytes = P.state_bytes;
   if (accum_bytes) *accum_bytes = P.accum_bytes;
   if (work_bytes) *work_bytes = P.work_bytes;
@@ -655,7 +786,7 @@ namespace {
 int init_handle(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options* options,
                 void* d_state, size_t state_bytes, void* d_accum, size_t accum_bytes,
                 void* d_work, size_t work_bytes, void* hip_stream, int static_dev,
-                fnlb_handle** out) {
+                int spec_slots, fnlb_handle** out) {
   if (!out) return FNLB_EINVAL;
   *out = nullptr;
   int rc = validate(reps, n_rep, options);
@@ -666,7 +797,7 @@ int init_handle(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_optio
   if (!h) return FNLB_ENOMEM;
   h->reps.assign(reps, reps + n_rep);
   h->opt = *options;
-  make_plan(reps, n_rep, options, h->plan);
+  make_plan(reps, n_rep, options, h->plan, spec_slots);
   const Plan& P = h->plan;
   if (state_bytes < P.state_bytes || accum_bytes < P.accum_bytes || work_bytes < P.work_bytes) {
     delete h;
@@ -678,6 +809,11 @@ int init_handle(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_optio
   h->work = (char*)d_work;
   h->stream = (hipStream_t)hip_stream;
   h->period = h->opt.sample_every > 0 ? h->opt.sample_every : 16;
+  // the long graph: as many sampling periods as there are slots, within the
+  // steps captured in advance
+  if (h->opt.sample_every > 0)
+    h->kgraph = (int)std::min<int64_t>(P.spec_slots, kPrecapturePeriod / h->period);
+  if (h->kgraph < 2) h->kgraph = 0;
   // the kernel: as requested, else as tuned for this shape (a negative cached
   // row count), else one step per launch
   if (h->opt.flags & FNLB_TWO_STEP)
@@ -693,15 +829,19 @@ int init_handle(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_optio
   BmTables bm;
   fill_bm_tables(bm);
   up(P.o_bm, &bm, sizeof(BmTables));
-  for (RepInfo& R : h->plan.info) R.bm = (const BmTables*)(h->work + P.o_bm);
+  set_table_pointers(h->plan, h->work);
   up(P.o_reps, P.info.data(), P.info.size() * sizeof(RepInfo));
   up(P.o_items, P.items.data(), P.items.size() * sizeof(Item));
   up(P.o_pitems, P.pitems.data(), P.pitems.size() * sizeof(PackItem));
   up(P.o_rows, P.rows.data(), P.rows.size() * sizeof(RowRef));
   up(P.o_cols, P.cols.data(), P.cols.size() * sizeof(ColRef));
+  up(P.o_frows, P.frows.data(), P.frows.size() * sizeof(RowTask));
+  up(P.o_fcols, P.fcols.data(), P.fcols.size() * sizeof(ColTask));
   if (e == hipSuccess) e = launch_fill_zero(h->work + P.o_misc, 16, s);
   if (e == hipSuccess) e = launch_fill_zero(h->work + P.o_ppart, P.work_bytes - P.o_ppart, s);
   if (e == hipSuccess) e = launch_twiddles(h->d_reps(), P.info.data(), n_rep, h->d_tw(), s);
+  if (e == hipSuccess)
+    e = launch_row_consts(h->d_reps(), P.info.data(), n_rep, h->opt.precision, s);
   // state of rest on the imposed profile: all deviations zero
   if (e == hipSuccess) e = launch_fill_zero(h->state, P.state_bytes, s);
   if (e == hipSuccess) e = launch_fill_zero(h->accum, P.accum_bytes, s);
@@ -730,7 +870,7 @@ int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep, const fnlb_options
               void* d_state, size_t state_bytes, void* d_accum, size_t accum_bytes,
               void* d_work, size_t work_bytes, void* hip_stream, fnlb_handle** out) {
   return init_handle(reps, n_rep, options, d_state, state_bytes, d_accum, accum_bytes, d_work,
-                     work_bytes, hip_stream, -1, out);
+                     work_bytes, hip_stream, -1, kSpecSlots, out);
 }
 
 int fnlb_init_static_work(const fnlb_replica_params* reps, int32_t n_rep,
@@ -745,10 +885,13 @@ int fnlb_init_static_work(const fnlb_replica_params* reps, int32_t n_rep,
   // stream or event of its own
   fnlb_options opt = *options;
   opt.flags |= FNLB_NO_GRAPH;
-  {
+  // as many spectrum slots as the array holds (at least one)
+  int slots = kSpecSlots;
+  for (;; slots /= 2) {
     Plan P;
-    make_plan(reps, n_rep, &opt, P);
-    if (P.work_bytes > kStaticWorkBytes) return FNLB_ENOMEM;
+    make_plan(reps, n_rep, &opt, P, slots);
+    if (P.work_bytes <= kStaticWorkBytes) break;
+    if (slots == 1) return FNLB_ENOMEM;
   }
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return FNLB_EDEVICE;
@@ -767,7 +910,7 @@ int fnlb_init_static_work(const fnlb_replica_params* reps, int32_t n_rep,
     g_static_busy[dev] = true;
   }
   const int r = init_handle(reps, n_rep, &opt, d_state, state_bytes, d_accum, accum_bytes, work,
-                            kStaticWorkBytes, hip_stream, dev, out);
+                            kStaticWorkBytes, hip_stream, dev, slots, out);
   if (r != FNLB_OK) {
     std::lock_guard<std::mutex> lk(g_static_mu);
     g_static_busy[dev] = false;
@@ -782,23 +925,35 @@ int fnlb_step(fnlb_handle* h, int64_t n) {
   const bool use_graph = !(h->opt.flags & FNLB_NO_GRAPH);
   while (n > 0) {
     const int64_t t = h->t;
-    // whole sampling periods from a period start replay the captured graph
+    // whole sampling periods from a period start replay a captured graph:
+    // kgraph periods at once while that many remain, else one
     if (use_graph && n >= h->period && t % h->period == 0 && (every == 0 || t >= 1)) {
-      const int rc = replay_period(h);
+      const int which = h->kgraph > 1 && n >= h->kgraph * h->period ? 1 : 0;
+      // the graphs fill the slots from the first
+      const hipError_t fe = flush_samples(h);
+      if (fe != hipSuccess) return dev_err(h, fe);
+      const int rc = replay_periods(h, which);
       if (rc) return rc;
-      n -= h->period;
+      n -= graph_periods(h, which) * h->period;
       continue;
     }
     const bool smp = every > 0 && t >= 1 && t % every == 0;
     hipError_t e = hipSuccess;
-    const int took = launch_state(h, t - h->t_dev, pair_at(h, t, n), smp, h->stream, e);
-    if (e == hipSuccess && smp) e = observe(h, h->stream);
+    const int took =
+        launch_state(h, t - h->t_dev, pair_at(h, t, n), smp, h->pending, h->stream, e);
+    if (e == hipSuccess && smp) {
+      e = observe_rows(h, h->stream, h->pending++);
+      if (e == hipSuccess && h->pending == h->plan.spec_slots) e = flush_samples(h);
+    }
     if (e != hipSuccess) return dev_err(h, e);
     if (smp) ++h->nsamples;
     h->cur ^= 1;
     h->t += took;
     n -= took;
   }
+  // every sample of the call is in the accumulators when it returns
+  const hipError_t e = flush_samples(h);
+  if (e != hipSuccess) return dev_err(h, e);
   return FNLB_OK;
 }
 
@@ -1102,15 +1257,17 @@ int fnlb_reinit(fnlb_handle* h, const fnlb_replica_params* reps, int32_t n_rep) 
   fnlb_options o = h->opt;
   o.chunk_rows = h->plan.chunk;
   Plan P;
-  make_plan(reps, n_rep, &o, P);
-  for (RepInfo& R : P.info) R.bm = (const BmTables*)(h->work + h->plan.o_bm);
+  make_plan(reps, n_rep, &o, P, h->plan.spec_slots);
   h->reps.assign(reps, reps + n_rep);
   h->plan.info = P.info;
+  set_table_pointers(h->plan, h->work);
   h->adj.valid = false;
   const Plan& Q = h->plan;
   hipStream_t s = h->stream;
   hipError_t e = hipMemcpyAsync(h->work + Q.o_reps, Q.info.data(), Q.info.size() * sizeof(RepInfo),
                                 hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = launch_row_consts(h->d_reps(), Q.info.data(), n_rep, h->opt.precision, s);
   if (e == hipSuccess) e = launch_fill_zero(h->work + Q.o_misc, 16, s);
   if (e == hipSuccess) e = launch_fill_zero(h->work + Q.o_ppart, Q.work_bytes - Q.o_ppart, s);
   if (e == hipSuccess) e = launch_fill_zero(h->state, Q.state_bytes, s);
@@ -1585,8 +1742,10 @@ int fnlb_destroy(fnlb_handle* h) {
   drop_graphs(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->obs_stream) (void)hipStreamDestroy(h->obs_stream);
-  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  for (int k = 0; k < kSpecSlots; ++k) {
+    if (h->ev_fork[k]) (void)hipEventDestroy(h->ev_fork[k]);
+    if (h->ev_join[k]) (void)hipEventDestroy(h->ev_join[k]);
+  }
   delete h;
   return FNLB_OK;
 }

@@ -23,10 +23,13 @@ constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kSeg = kBlock;
 constexpr int kRowAlign = 64;
 
-// sampled real fields: delta c, delta rho, and U_x, U_z on request (the step
-// leaves as many per-node inputs: the two density deviations, and the two
-// momenta)
-inline int n_fields(int flags) { return (flags & FNLB_SAMPLE_VELOCITY) ? 4 : 2; }
+// sampled real fields: delta c, delta rho, and U_x, U_z on request; the
+// sampling step stores them per node as complex pairs (delta c, delta rho)
+// [, (U_x, U_z)], the sequences the row transform takes, and sums the
+// pressure deviations of each row in parts of 64 columns
+__host__ __device__ inline int n_fields(int flags) { return (flags & FNLB_SAMPLE_VELOCITY) ? 4 : 2; }
+// Parts of a row's pressure sum in a sample: one per 64 columns.
+__host__ __device__ inline int pressure_parts(int Lx) { return (Lx + 63) >> 6; }
 
 // Everything a kernel needs about one replica.  Filled on the host, copied to
 // the work buffer once at init, read by the kernels with scalar loads.
@@ -35,14 +38,15 @@ struct alignas(256) RepInfo {
   int32_t pitch;          // row length rounded up to whole 64-column tiles (>= Lx)
   int64_t plane;          // elements per (species, link) plane
   int64_t state_off;      // element offset of this replica in one state copy
-  int64_t field_off;      // element offset of the sample inputs [2 or 4][Lz][Lx] (storage type)
-  int64_t spec_off;       // double2 offset of the row spectra [2][Lz][Lx/2+1]
+  int64_t field_off;      // element offset of the sample: pairs [1 or 2][Lz][Lx][2] (storage type)
+  int64_t spec_off;       // element offset of the row spectra [2][Lz][spitch], 128-byte aligned
   int64_t acc_off;        // double offset of [2][3][Lz][Lx/2+1] sums
   int64_t pacc_off;       // double offset of {sum, sum2, profile[Lz]}
-  int64_t ppart_off;      // double offset of the pressure row sums [Lz]
+  int64_t ppart_off;      // double offset of the pressure sums [Lz][pressure_parts(Lx)]
   int64_t tw_off;         // double2 offset of twiddles: Lx entries then Lz
   int32_t flags;          // FNLB_* option bits
   int32_t pow2;           // both Lx and Lz are powers of two (FFT path)
+  int32_t spitch;         // elements per row of the row spectra: Lx/2+1 rounded up to 128 B
   uint32_t seed_lo, seed_hi;
   double rho0;            // reference density rho_bar
   double grad;            // grad_c0
@@ -57,7 +61,14 @@ struct alignas(256) RepInfo {
   double p_ref;           // rho_bar/3 + G rho_bar^2 / 12
   double inv_norm;        // 1 / sqrt(Lx Lz)
   const BmTables* bm;     // FP64 Box-Muller tables in the work buffer (shared)
+  const void* rowc;       // per row, kRowConsts constants of a sample in the compute type
 };
+
+// Constants of row j that the sample of a node needs (formed in FP64 by
+// k_row_consts, rounded once to the compute type): rho_ref^A, rho_ref^B, c_0,
+// the reference parts of sum_l w_l rho^S(r + c_l) for A and B, the reference
+// part of the z component of sum_l w_l c_l rho^A(r + c_l), and G/4.
+constexpr int kRowConsts = 8;
 
 // One block's work: replica, 256-column segment and a range of rows.
 struct Item {
@@ -73,6 +84,16 @@ struct RowRef {
 // A tile of k_x columns of one field of one replica (column transform).
 struct ColRef {
   int32_t rep, field, kx0, ncols, ltile;  // ncols <= 2^ltile columns from kx0
+};
+
+// Wavefront transforms (sequences of 8 to 512 points): a wavefront's rows
+// j0 .. j0 + nrows - 1 of one replica (nrows <= 512 / Lx), and a block's tile
+// of ncols <= 2048 / Lz k_x columns of one field.
+struct RowTask {
+  int32_t rep, j0, nrows, pad;
+};
+struct ColTask {
+  int32_t rep, field, kx0, ncols;
 };
 
 // Kernel modes of the fused step.
@@ -102,7 +123,9 @@ struct Step2Args {
   void* state_out;        // state at t + 2
   const int64_t* t_base;  // device time counter
   int64_t t_off;          // time of the first step = *t_base + t_off
-  void* fields;           // sample inputs of f(t) (sampling mode)
+  void* fields;           // sample of f(t) (sampling mode)
+  double* ppart;          // its pressure sums, [Lz][pressure_parts(Lx)] per replica
+  int32_t* watchdog;      // set non-zero when a sample sees a bad state
 };
 hipError_t launch_step2(int mode, const Step2Args& a, hipStream_t stream);
 
@@ -116,7 +139,9 @@ struct StepArgs {
   void* state_out;        // next state copy
   const int64_t* t_base;  // device time counter (graph replays advance it)
   int64_t t_off;          // time = *t_base + t_off
-  void* fields;           // sample inputs base (float for FP32-deviation storage, else double)
+  void* fields;           // sample (float for FP32-deviation storage, else double)
+  double* ppart;          // its pressure sums, [Lz][pressure_parts(Lx)] per replica
+  int32_t* watchdog;      // set non-zero when a sample sees a bad state
 };
 
 // Launchers (asynchronous on `stream`).
@@ -124,16 +149,32 @@ hipError_t launch_step(int precision, int mode, const StepArgs& a, hipStream_t s
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t stream);
 hipError_t launch_twiddles(const RepInfo* d_reps, const RepInfo* h_reps, int n_rep,
                            double2* tw_base, hipStream_t stream);
-// watchdog: set non-zero when a sample sees a bad state
+// the per-row sample constants of every replica (into each RepInfo::rowc)
+hipError_t launch_row_consts(const RepInfo* d_reps, const RepInfo* h_reps, int n_rep,
+                             int precision, hipStream_t stream);
+// Row passes of one sample into the spectrum slot spec.  The row spectra hold
+// complex pairs of the storage type: double2 for FP64, float2 for
+// FP32-deviation storage; spec_off, spitch and slot strides count such
+// elements.
 hipError_t launch_row_transform(const RepInfo* reps, const RowRef* rows, int n_rows,
                                 int n_pairs, int max_row_lds, int precision, const void* fields,
-                                double2* spec,
-                                const double2* tw, double* ppart, int32_t* watchdog,
-                                hipStream_t stream);
-// (also reduces each replica's pressure row sums in ppart)
+                                void* spec, const double2* tw, hipStream_t stream);
+// Column passes of nslots samples, slot s of the spectra and of the pressure
+// sums the sampling step formed at s spec_slot and s ppart_slot elements from
+// spec and ppart, added to the sums in slot order (also adds each replica's
+// pressure of every sample).
 hipError_t launch_col_transform(const RepInfo* reps, const ColRef* cols, int n_cols,
-                                int max_lds_cols, const double2* spec, double* acc,
-                                const double2* tw, const double* ppart, hipStream_t stream);
+                                int max_lds_cols, int precision, const void* spec, int nslots,
+                                size_t spec_slot, double* acc, const double2* tw,
+                                const double* ppart, size_t ppart_slot, hipStream_t stream);
+// the same passes for rows and columns of 8 to 512 points (powers of two)
+hipError_t launch_row_fft(const RepInfo* reps, const RowTask* tasks, int n_tasks, int n_pairs,
+                          int precision, const void* fields, void* spec, const double2* tw,
+                          hipStream_t stream);
+hipError_t launch_col_fft(const RepInfo* reps, const ColTask* tasks, int n_tasks,
+                          int precision, const void* spec, int nslots, size_t spec_slot,
+                          double* acc, const double2* tw, const double* ppart,
+                          size_t ppart_slot, hipStream_t stream);
 hipError_t launch_advance_time(int64_t* t_base, int64_t dt, hipStream_t stream);
 
 // Adjoint of the step (single replica, FP64 storage); see k_adjoint.hip.

@@ -70,27 +70,302 @@ __device__ __forceinline__ void node_noise(uint32_t node, uint64_t t, uint32_t k
   node_normals(node, t, 1u, k0, k1, gA1, bmt);
 }
 
+// ---- The sample of one node, formed by the sampling step from the values
+// its collision reads.
+//
+// From f(t) as pulled: (delta c, delta rho), the pressure deviation and, with
+// velocity sampling, (U_x, U_z), the barycentric velocity of Eq. (10) with the
+// total non-ideal force (the a_* and non-equilibrium parts cancel between the
+// species) and U_z = 0 on the wall rows when the wall rule is on.  The
+// pressure (reading R11: P = rho/3 + (G/4) sum_l w_l |c_l|^2 [rho^A rho^B(r +
+// c_l) + rho^B rho^A(r + c_l)], the ghost rows repeating the wall row) is
+// split into a part that is constant along a row, G/4 (rho_ref^A s_ref^B +
+// rho_ref^B s_ref^A) - P_ref, which the row pass adds in FP64, and the
+// deviation formed here,
+//   dp = delta rho / 3 + G/4 [rho_ref^A ds^B + rho_ref^B ds^A
+//                            + d^A s_ref^B + d^B s_ref^A + d^A ds^B + d^B ds^A],
+// with s^S = s_ref^S + ds^S = sum_l w_l |c_l|^2 rho^S(r + c_l) and d^S the
+// density deviations: every term is of the size of the fluctuations, so the
+// compute type (FP32 with FP32-deviation storage) carries its relative
+// rounding, not that of the O(1) reference terms.
+
+// the 3 x 3 density stencil of both species (deviations; W, C, E of the rows
+// below, at and above the node)
+template <typename DT>
+struct Stencil {
+  DT aC, aW, aE, aU, aUW, aUE, aD, aDW, aDE;
+  DT bC, bW, bE, bU, bUW, bUE, bD, bDW, bDE;
+};
+
+template <typename DT>
+__device__ __forceinline__ Stencil<DT> load_stencil(const DT* aU, const DT* aC, const DT* aD,
+                                                    const DT* bU, const DT* bC, const DT* bD,
+                                                    int c) {
+  return Stencil<DT>{aC[c], aC[c - 1], aC[c + 1], aU[c], aU[c - 1], aU[c + 1],
+                     aD[c], aD[c - 1], aD[c + 1], bC[c], bC[c - 1], bC[c + 1],
+                     bU[c], bU[c - 1], bU[c + 1], bD[c], bD[c - 1], bD[c + 1]};
+}
+
+// the reference values of one row the sample needs, in the compute type
+template <typename Real>
+struct SampleRow {
+  Real rAj, rBj, c0, sAref, sBref, G4, szref;
+  bool wall;  // U_z = 0 on this row
+};
+
+// (formed in FP64 and rounded once to the compute type; the kernels read them
+// from the replica's row table, which k_row_consts fills with this function)
+template <typename Real>
+__device__ __forceinline__ SampleRow<Real> sample_row_calc(const RepInfo& R, int j, int jU,
+                                                           int jD) {
+  const double rho0 = R.rho0;
+  const double rAj = R.rA_mid + R.rA_step * j, rBj = rho0 - rAj;
+  const double rAu = R.rA_mid + R.rA_step * jU, rAd = R.rA_mid + R.rA_step * jD;
+  const double rBu = rho0 - rAu, rBd = rho0 - rAd;
+  SampleRow<Real> r;
+  r.rAj = (Real)rAj;
+  r.rBj = (Real)rBj;
+  r.c0 = (Real)(rAj * (1.0 / rho0));
+  r.sAref = (Real)((1.0 / 9.0) * (2.0 * rAj + rAu + rAd) + (1.0 / 9.0) * (rAu + rAd));
+  r.sBref = (Real)((1.0 / 9.0) * (2.0 * rBj + rBu + rBd) + (1.0 / 9.0) * (rBu + rBd));
+  r.G4 = (Real)(0.25 * R.G);
+  r.szref = (Real)(R.rA_step * (double)(jU - jD) * (1.0 / 6.0));
+  r.wall = (R.flags & FNLB_WALL_UZ_FIX) && (j == 0 || j == R.Lz - 1);
+  return r;
+}
+
+// Where the sample of one replica goes and the row table it reads: the
+// RepInfo fields the sampling code needs, read once at the start of a launch.
+// (A kernel that stores to global memory would otherwise read them again
+// after its stores, and the wait for such a load also waits for every load
+// issued before it, the prefetched rows included.)
+template <typename Store, typename Real>
+struct SampleDest {
+  Store* fld;        // the replica's pairs
+  double* ppart;     // the replica's pressure parts
+  const Real* rowc;  // the replica's row constants
+  int64_t plane;     // Lz Lx
+  int Lx, Lz, nparts;
+  bool wall_fix;
+};
+template <typename Store, typename Real>
+__device__ __forceinline__ SampleDest<Store, Real> sample_dest(const RepInfo& R, void* fields,
+                                                               double* ppart) {
+  SampleDest<Store, Real> d;
+  d.fld = (Store*)fields + R.field_off;
+  d.ppart = ppart + R.ppart_off;
+  d.rowc = (const Real*)R.rowc;
+  d.plane = (int64_t)R.Lz * R.Lx;
+  d.Lx = R.Lx;
+  d.Lz = R.Lz;
+  d.nparts = pressure_parts(R.Lx);
+  d.wall_fix = (R.flags & FNLB_WALL_UZ_FIX) != 0;
+  return d;
+}
+
+// The sample constants of row j from the replica's row table (read through
+// the constant address space: the table does not change during a launch, so
+// a wavefront-uniform row is read with scalar loads).
+template <typename Store, typename Real>
+__device__ __forceinline__ SampleRow<Real> sample_row(const SampleDest<Store, Real>& D, int j) {
+  typedef const __attribute__((address_space(4))) Real ConstReal;
+  ConstReal* t = (ConstReal*)(D.rowc + (size_t)kRowConsts * j);
+  SampleRow<Real> r;
+  r.rAj = t[0];
+  r.rBj = t[1];
+  r.c0 = t[2];
+  r.sAref = t[3];
+  r.sBref = t[4];
+  r.szref = t[5];
+  r.G4 = t[6];
+  r.wall = D.wall_fix && (j == 0 || j == D.Lz - 1);
+  return r;
+}
+
+// the part of the pressure deviation that is constant along row j (FP64)
+__device__ __forceinline__ double pressure_row_ref(const RepInfo& R, int j) {
+  const int Lz = R.Lz, jU = min(j + 1, Lz - 1), jD = max(j - 1, 0);
+  const double rho0 = R.rho0;
+  const double rAj = R.rA_mid + R.rA_step * j, rBj = rho0 - rAj;
+  const double rAu = R.rA_mid + R.rA_step * jU, rAd = R.rA_mid + R.rA_step * jD;
+  const double rBu = rho0 - rAu, rBd = rho0 - rAd;
+  const double sAref = (1.0 / 9.0) * (2.0 * rAj + rAu + rAd) + (1.0 / 9.0) * (rAu + rAd);
+  const double sBref = (1.0 / 9.0) * (2.0 * rBj + rBu + rBd) + (1.0 / 9.0) * (rBu + rBd);
+  return 0.25 * R.G * (rAj * sBref + rBj * sAref) - (R.p_ref - rho0 / 3.0);
+}
+
+template <typename Real>
+struct NodeSample {
+  Real dc, drho, dp, ux, uz;
+  bool bad;  // a density not positive, c outside (0, 1), or a pressure not finite
+};
+
+// jx, jz: total momentum of the pulled populations (before the wall rule);
+// G: the coupling
+template <typename Real, typename DT>
+__device__ __forceinline__ NodeSample<Real> node_sample(const Stencil<DT>& s,
+                                                        const SampleRow<Real>& r, Real G, Real jx,
+                                                        Real jz, bool velocity) {
+  const Real w1 = (Real)(1.0 / 9.0), w2 = (Real)(1.0 / 18.0), w5 = (Real)(1.0 / 36.0);
+  const Real aC = (Real)s.aC, bC = (Real)s.bC;
+  const Real rhoA = r.rAj + aC, rhoB = r.rBj + bC;
+  const Real rho = rhoA + rhoB;
+  Real inv_rho;
+  if constexpr (sizeof(Real) == 4)
+    inv_rho = __builtin_amdgcn_rcpf(rho);
+  else
+    inv_rho = (Real)1 / rho;
+  NodeSample<Real> o;
+  o.drho = aC + bC;
+  o.dc = (aC - r.c0 * o.drho) * inv_rho;
+  const Real sdA = w1 * ((Real)(s.aE + s.aW) + (Real)(s.aU + s.aD)) +
+                   w2 * ((Real)(s.aUE + s.aUW) + (Real)(s.aDE + s.aDW));
+  const Real sdB = w1 * ((Real)(s.bE + s.bW) + (Real)(s.bU + s.bD)) +
+                   w2 * ((Real)(s.bUE + s.bUW) + (Real)(s.bDE + s.bDW));
+  o.dp = o.drho * (Real)(1.0 / 3.0) +
+         r.G4 * ((r.rAj * sdB + r.rBj * sdA) + (aC * r.sBref + bC * r.sAref) +
+                 (aC * sdB + bC * sdA));
+  o.bad = !(rhoA > (Real)0) || !(rhoB > (Real)0) || !(o.dc + r.c0 > (Real)0) ||
+          !(o.dc + r.c0 < (Real)1) || !isfinite(o.dp);
+  o.ux = o.uz = (Real)0;
+  if (velocity) {
+    // total force -G (rho^A s^B + rho^B s^A), s^S = sum_l w_l c_l rho^S(r + c_l)
+    const Real sAx = w1 * (Real)(s.aE - s.aW) + w5 * (Real)((s.aUE - s.aUW) + (s.aDE - s.aDW));
+    const Real sBx = w1 * (Real)(s.bE - s.bW) + w5 * (Real)((s.bUE - s.bUW) + (s.bDE - s.bDW));
+    const Real sAz =
+        w1 * (Real)(s.aU - s.aD) + w5 * (Real)((s.aUE + s.aUW) - (s.aDE + s.aDW)) + r.szref;
+    const Real sBz =
+        w1 * (Real)(s.bU - s.bD) + w5 * (Real)((s.bUE + s.bUW) - (s.bDE + s.bDW)) - r.szref;
+    const Real Fx = -G * (rhoA * sBx + rhoB * sAx);
+    const Real Fz = -G * (rhoA * sBz + rhoB * sAz);
+    o.ux = (jx + (Real)0.5 * Fx) * inv_rho;
+    o.uz = r.wall ? (Real)0 : (jz + (Real)0.5 * Fz) * inv_rho;
+  }
+  return o;
+}
+
+// A copy of v that the compiler cannot tie to v's other uses (an empty asm
+// statement; no instruction).  The sample is formed from such copies, so it
+// shares no floating-point operation with the collision, whose FP32
+// contractions then stay those of the step that does not sample: a sampled
+// trajectory stays bit-identical to an unsampled one.
+template <typename T>
+__device__ __forceinline__ T opaque(T v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
+// The sample of a node with stencil s0 (pulled populations f, for the
+// momentum), formed from opaque copies.
+template <typename Real, typename DT, typename Store>
+__device__ __forceinline__ NodeSample<Real> sample_of(const Stencil<DT>& s0,
+                                                      const Store (&f)[18],
+                                                      const SampleRow<Real>& r, Real G,
+                                                      bool velocity) {
+  Stencil<DT> st = s0;
+  st = Stencil<DT>{opaque(st.aC), opaque(st.aW), opaque(st.aE), opaque(st.aU), opaque(st.aUW),
+                   opaque(st.aUE), opaque(st.aD), opaque(st.aDW), opaque(st.aDE),
+                   opaque(st.bC), opaque(st.bW), opaque(st.bE), opaque(st.bU), opaque(st.bUW),
+                   opaque(st.bUE), opaque(st.bD), opaque(st.bDW), opaque(st.bDE)};
+  Real jx = (Real)0, jz = (Real)0;
+  if (velocity) {
+    Real d[9];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) d[l] = opaque((Real)f[l]) + opaque((Real)f[9 + l]);
+    jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+    jz = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+  }
+  return node_sample<Real, DT>(st, r, opaque(G), jx, jz, velocity);
+}
+
+// Stores a node's sample at node n = j Lx + x: the pairs (delta c, delta rho)
+// [, (U_x, U_z)] in the storage type ([1 or 2][Lz][Lx][2]).
+template <typename Store, typename Real>
+__device__ __forceinline__ void store_sample(const SampleDest<Store, Real>& D, int32_t* watchdog,
+                                             int j, int x, const NodeSample<Real>& o,
+                                             bool velocity) {
+  Store* fld = D.fld;
+  const int64_t n = (int64_t)j * D.Lx + x, plane = D.plane;
+  if constexpr (sizeof(Store) == 4) {
+    *(float2*)(fld + 2 * n) = make_float2((float)o.dc, (float)o.drho);
+    if (velocity) *(float2*)(fld + 2 * plane + 2 * n) = make_float2((float)o.ux, (float)o.uz);
+  } else {
+    *(double2*)(fld + 2 * n) = make_double2((double)o.dc, (double)o.drho);
+    if (velocity) *(double2*)(fld + 2 * plane + 2 * n) = make_double2((double)o.ux, (double)o.uz);
+  }
+  if (o.bad) atomicOr(watchdog, 1);
+}
+
+// x from the lane the DPP pattern CTRL selects (patterns within rows of 16
+// lanes, every lane of the wavefront active).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(
+      (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo));
+}
+__device__ __forceinline__ double readlane_as_f64(float x, int lane) {
+  return (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+__device__ __forceinline__ double readlane_as_f64(double x, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Part `part` of row j's sum of pressure deviations (columns 64 part ..
+// 64 part + 63): every lane of a wavefront passes its node's deviation (0 for
+// a lane past the row).  In the compute type, within each row of 16 lanes:
+// pairs, then quads (lane moves by quad permutation), then the quad sums
+// rotated by 4 and by 8 lanes, after which lane 0 of the row holds the row's
+// sum; the four row sums are added in FP64 as (r0 + r1) + (r2 + r3) and
+// stored by the first lane.  The order is fixed, so the part does not depend
+// on how the lanes run.  Called by whole wavefronts with every lane active.
+template <typename Store, typename Real>
+__device__ __forceinline__ void store_pressure_part(const SampleDest<Store, Real>& D, int j,
+                                                    int part, Real v) {
+  if constexpr (sizeof(Real) == 4) {
+    v += dpp_f32<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f32<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f32<0x124>(v);  // row_ror 4
+    v += dpp_f32<0x128>(v);  // row_ror 8
+  } else {
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x124>(v);
+    v += dpp_f64<0x128>(v);
+  }
+  const double s = (readlane_as_f64(v, 0) + readlane_as_f64(v, 16)) +
+                   (readlane_as_f64(v, 32) + readlane_as_f64(v, 48));
+  if ((threadIdx.x & 63) == 0) D.ppart[(int64_t)j * D.nparts + part] = s;
+}
+
 // Update of one node.  dA, dB: on entry the pulled populations of the node as
 // deviations from w_l rho_ref^S of its row, on exit the post-collision values
-// (before the streaming shift).  aU/aC/aD, bU/bC/bD: density deviations of
-// species A and B in the rows above, at and below the node (ghost rows beyond
-// the walls repeat the wall row), read at c - 1, c, c + 1.  rAj: rho_ref^A of
-// the node's row; szref: the reference part of the z component of
-// sum_l w_l c_l rho^A(r + c_l).
+// (before the streaming shift).  st: the 3 x 3 density deviations of species
+// A and B in the rows above, at and below the node (ghost rows beyond the
+// walls repeat the wall row; load_stencil).  rAj: rho_ref^A of the node's row;
+// szref: the reference part of the z component of sum_l w_l c_l rho^A(r + c_l).
 template <typename Real, typename DT>
 __device__ __forceinline__ void node_update(const NodePhys<Real>& P, int flags, bool top,
                                             bool bot, double rAj, double rho0, double szref,
-                                            const DT* aU, const DT* aC, const DT* aD,
-                                            const DT* bU, const DT* bC, const DT* bD, int c,
-                                            Real (&dA)[9], Real (&dB)[9], Real (&gA0)[4],
-                                            Real (&gA1)[4], Real (&gB0)[4], Real (&gB1)[4]) {
+                                            const Stencil<DT>& st, Real (&dA)[9], Real (&dB)[9],
+                                            Real (&gA0)[4], Real (&gA1)[4], Real (&gB0)[4],
+                                            Real (&gB1)[4]) {
   const Real w1 = (Real)(1.0 / 9.0), w5 = (Real)(1.0 / 36.0), w0 = (Real)(4.0 / 9.0);
-  const DT dAc = aC[c], dBc = bC[c];
-  const DT aWc = aC[c - 1], aEc = aC[c + 1], bWc = bC[c - 1], bEc = bC[c + 1];
-  const DT aWp = aU[c - 1], aEp = aU[c + 1];
-  const DT dAp = aU[c], dBp = bU[c], bWp = bU[c - 1], bEp = bU[c + 1];
-  const DT dAm = aD[c], aWm = aD[c - 1], aEm = aD[c + 1];
-  const DT dBm = bD[c], bWm = bD[c - 1], bEm = bD[c + 1];
+  const DT dAc = st.aC, dBc = st.bC;
+  const DT aWc = st.aW, aEc = st.aE, bWc = st.bW, bEc = st.bE;
+  const DT aWp = st.aUW, aEp = st.aUE;
+  const DT dAp = st.aU, dBp = st.bU, bWp = st.bUW, bEp = st.bUE;
+  const DT dAm = st.aD, aWm = st.aDW, aEm = st.aDE;
+  const DT dBm = st.bD, bWm = st.bDW, bEm = st.bDE;
   const Real rhoA = (Real)rAj + (Real)dAc;
   const Real rhoB = (Real)(rho0 - rAj) + (Real)dBc;
   const Real rho = rhoA + rhoB;

@@ -3,21 +3,47 @@
 // sum_{x,j} dphi e^{-i q.r}, S(q) = <|Phi(q)|^2> on the lattice; Sec. IV.A for
 // S_U) and the mean pressure (Sec. IV.C).
 //
-// The step kernel writes the density deviations (and momenta) of a sample in
-// the storage type (FP32 with FP32-deviation storage, else FP64).  A row pass forms the real fields and the pressure from them,
-// transforms two fields of a row at once as one complex sequence (z = delta c
-// + i delta rho, and z = U_x + i U_z) and splits the result by Hermitian
-// symmetry into the half spectra k_x = 0..Lx/2; a column pass transforms each
-// k_x column over the Lz rows and adds |Phi|^2, Re Phi and Im Phi to the FP64
-// accumulators.  Power-of-two lengths use the in-LDS FFT; other lengths a
-// direct sum with exactly reduced twiddle indices.  Pressure row sums are
-// formed and reduced in a fixed order, so every accumulator is deterministic.
+// The sampling step forms the fields of a sample and stores them per node as
+// complex pairs (z = delta c + i delta rho, and z = U_x + i U_z) in the
+// storage type, and sums the nodes' pressure deviations from the row's
+// constant part in FP64, per row and 64 columns.  A row pass transforms each
+// row's pairs as one complex sequence and splits the result by Hermitian
+// symmetry into the half spectra k_x = 0..Lx/2 of the two fields; a column
+// pass transforms each k_x column over the Lz rows and adds |Phi|^2, Re Phi
+// and Im Phi to the FP64 accumulators, and adds the sample's mean pressure
+// and row profile.  Both transforms compute in FP64; the row spectra between
+// them are kept in the storage type (complex float pairs for FP32-deviation
+// storage, whose fields are float values).  Rows and columns of 8 to 512 points (powers
+// of two) use the wavefront transforms; longer power-of-two lengths the
+// in-LDS FFT of a block; other lengths a direct sum with exactly reduced
+// twiddle indices.  Every sum is formed in a fixed order, so every
+// accumulator is deterministic.
 #include "fnlb.h"
 #include "fnlb_fft.hpp"
 #include "fnlb_internal.hpp"
+#include "fnlb_node.hpp"
 
 namespace fnlb {
 namespace {
+
+// The element of the row spectra: the storage type's complex pair.
+template <typename FT>
+struct SpecOf {
+  using type = double2;
+};
+template <>
+struct SpecOf<float> {
+  using type = float2;
+};
+__device__ __forceinline__ double2 widen(double2 v) { return v; }
+__device__ __forceinline__ double2 widen(float2 v) { return make_double2(v.x, v.y); }
+template <typename ST>
+__device__ __forceinline__ ST narrow(double x, double y) {
+  if constexpr (sizeof(ST) == 8)
+    return make_float2((float)x, (float)y);
+  else
+    return make_double2(x, y);
+}
 
 __global__ void k_fill_zero(uint32_t* p, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -31,6 +57,26 @@ __global__ void k_advance_time(int64_t* t, int64_t dt) {
 
 // twiddles of one replica: tw[m] = exp(-2 pi i m / N) for the Lx table then
 // the Lz table.
+// The per-row sample constants (sample_row_calc), one thread per row; ghost
+// rows beyond the walls repeat the wall row, as in the step.
+template <typename Real>
+__global__ void k_row_consts(const RepInfo* reps) {
+  const RepInfo& R = reps[blockIdx.y];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= R.Lz) return;
+  const int jU = j == R.Lz - 1 ? j : j + 1, jD = j == 0 ? j : j - 1;
+  const SampleRow<Real> r = sample_row_calc<Real>(R, j, jU, jD);
+  Real* t = (Real*)R.rowc + (size_t)kRowConsts * j;
+  t[0] = r.rAj;
+  t[1] = r.rBj;
+  t[2] = r.c0;
+  t[3] = r.sAref;
+  t[4] = r.sBref;
+  t[5] = r.szref;
+  t[6] = r.G4;
+  t[7] = (Real)0;
+}
+
 __global__ void k_twiddles(const RepInfo* reps, double2* tw_base) {
   const RepInfo& R = reps[blockIdx.y];
   double2* tw = tw_base + R.tw_off;
@@ -48,39 +94,26 @@ __global__ void k_twiddles(const RepInfo* reps, double2* tw_base) {
 // that their latencies overlap.
 constexpr int kBatch = 8;
 
-// Row pass of a sample: one block per group of consecutive rows of one
-// replica (several short rows share a block) and field pair (blockIdx.y).
-// The step kernel leaves, per node, the deviations of the two species
-// densities from the row references (and, with velocity sampling, the total
-// momenta), of type FT; this pass works in FP64.  It forms the sampled fields from them: pair 0 is
-// delta c + i delta rho, together with the pressure of every node (reading
-// R11: P = rho/3 + (G/4) sum_l w_l |c_l|^2 [rho^A rho^B(r + c_l) + rho^B
-// rho^A(r + c_l)], ghost rows repeating the wall row) summed per row in a
-// fixed order, and the check of the state; pair 1 is U_x + i U_z, the
-// barycentric velocity of Eq. (10) after the wall fix.  Neighbour densities
-// are read from global memory (L2) with 32-bit offsets shared by both species.
-// Each row is then transformed and split into the two half spectra.  LDS: the
-// rows, then (power-of-two rows) the N/2 twiddles the FFT uses.
+// Row pass of a sample (block transforms): one block per group of
+// consecutive rows of one replica (several short rows share a block) and field
+// pair (blockIdx.y).  The rows' pairs, of type FT, are read into LDS (bit
+// reversed for the FFT), transformed and split into the two half spectra.
+// LDS: the rows, then (power-of-two rows) the N/2 twiddles the FFT uses.
 template <typename FT>
 __global__ __launch_bounds__(256) void k_row_transform(const RepInfo* reps, const RowRef* rows,
-                                                       const void* fields, double2* spec,
-                                                       const double2* tw_base, double* ppart,
-                                                       int32_t* watchdog) {
+                                                       const void* fields, void* spec,
+                                                       const double2* tw_base) {
+  using ST = typename SpecOf<FT>::type;
   extern __shared__ double2 lds[];
-  __shared__ double red[256 / kWave];
   const RowRef rr = rows[blockIdx.x];
   const RepInfo& R = reps[rr.rep];
   const int N = R.Lx, Lz = R.Lz, nkx = N / 2 + 1, nr = rr.nrows;
   const int pair = blockIdx.y;
-  const size_t plane = (size_t)Lz * N;
-  const FT* dA = (const FT*)fields + R.field_off;  // density deviations [Lz][Lx]
-  const FT* dB = dA + plane;
-  const FT* mX = dB + plane;  // total momenta (velocity sampling)
-  const FT* mZ = mX + plane;
+  const FT* z = (const FT*)fields + R.field_off + (size_t)pair * 2 * Lz * N;
   const double2* tw = tw_base + R.tw_off;
   const size_t orow = (size_t)(2 * pair) * Lz + rr.j0;  // first field of the pair
-  double2* out_c = spec + R.spec_off + orow * nkx;
-  double2* out_r = out_c + (size_t)Lz * nkx;
+  ST* out_c = (ST*)spec + R.spec_off + orow * R.spitch;
+  ST* out_r = out_c + (size_t)Lz * R.spitch;
   const int total = nr * N;
   const int bits = R.pow2 ? __ffs(N) - 1 : 0;
   // the block's threads split into one group per row
@@ -88,125 +121,12 @@ __global__ __launch_bounds__(256) void k_row_transform(const RepInfo* reps, cons
   const int r = threadIdx.x / gsz, t2 = threadIdx.x - r * gsz;
   const bool live = r < nr;
   const int j = rr.j0 + (live ? r : 0);
-  const int jU = min(j + 1, Lz - 1), jD = max(j - 1, 0);
-  const double rho0 = R.rho0, G = R.G;
-  const double rAj = R.rA_mid + R.rA_step * j, rBj = rho0 - rAj;
-  const double rAu = R.rA_mid + R.rA_step * jU, rAd = R.rA_mid + R.rA_step * jD;
-  const double rBu = rho0 - rAu, rBd = rho0 - rAd;
-  const double szref = R.rA_step * (double)(jU - jD) * (1.0 / 6.0);  // species A
-  // reference parts of the weighted neighbour sums s^S of the pressure
-  const double sAref = (1.0 / 9.0) * (2.0 * rAj + rAu + rAd) + (1.0 / 9.0) * (rAu + rAd);
-  const double sBref = (1.0 / 9.0) * (2.0 * rBj + rBu + rBd) + (1.0 / 9.0) * (rBu + rBd);
-  const double c0 = rAj / rho0, dPref = R.p_ref - rho0 / 3.0;
-  const bool wall = (R.flags & FNLB_WALL_UZ_FIX) && (j == 0 || j == Lz - 1);
-  // byte offsets of the three rows (Lx, Lz <= 4096, so 8 Lx Lz < 2^32: the
-  // planes are read through 32-bit offsets from a uniform base); FS bytes per
-  // value
-  constexpr uint32_t FS = sizeof(FT);
-  const uint32_t oC = (uint32_t)j * N * FS, oU = (uint32_t)jU * N * FS, oD = (uint32_t)jD * N * FS;
-  auto ld = [](const FT* base, uint32_t off) {
-    return (double)*(const FT*)((const char*)base + off);
-  };
-  double psum = 0.0;
-  bool bad = false;
-  // The sampled field(s) of node x from its 3 x 3 stencil of density
-  // deviations (W, C, E of the rows below, at and above) of both species; c is
-  // the node's byte offset (for the momenta).
-  struct Stencil {
-    double D, DW, DE, C, W, E, U, UW, UE;
-  };
-  auto eval = [&](int x, uint32_t c, const Stencil& A, const Stencil& B) {
-    const double rhoA = rAj + A.C, rhoB = rBj + B.C;
-    const double rho = rhoA + rhoB;
-    double2 v;
-    if (pair == 0) {
-      const double drho = A.C + B.C;
-      const double dc = (A.C - c0 * drho) / rho;
-      const double sA = sAref + (1.0 / 9.0) * ((A.E + A.W) + (A.U + A.D)) +
-                        (1.0 / 18.0) * ((A.UE + A.UW) + (A.DE + A.DW));
-      const double sB = sBref + (1.0 / 9.0) * ((B.E + B.W) + (B.U + B.D)) +
-                        (1.0 / 18.0) * ((B.UE + B.UW) + (B.DE + B.DW));
-      const double dP = drho * (1.0 / 3.0) + G * 0.25 * (rhoA * sB + rhoB * sA) - dPref;
-      psum += dP;
-      bad = bad || !(rhoA > 0.0) || !(rhoB > 0.0) || !(dc + c0 > 0.0) || !(dc + c0 < 1.0) ||
-            !isfinite(dP);
-      v = make_double2(dc, drho);
-    } else {
-      // total force -G (rho^A s^B + rho^B s^A) with s^S = sum_l w_l c_l rho^S(r + c_l)
-      // (the a_* and non-equilibrium parts cancel between the species)
-      const double vAx = (1.0 / 9.0) * (A.E - A.W) + (1.0 / 36.0) * ((A.UE - A.UW) + (A.DE - A.DW));
-      const double vBx = (1.0 / 9.0) * (B.E - B.W) + (1.0 / 36.0) * ((B.UE - B.UW) + (B.DE - B.DW));
-      const double vAz =
-          (1.0 / 9.0) * (A.U - A.D) + (1.0 / 36.0) * ((A.UE + A.UW) - (A.DE + A.DW)) + szref;
-      const double vBz =
-          (1.0 / 9.0) * (B.U - B.D) + (1.0 / 36.0) * ((B.UE + B.UW) - (B.DE + B.DW)) - szref;
-      const double Fx = -G * (rhoA * vBx + rhoB * vAx);
-      const double Fz = -G * (rhoA * vBz + rhoB * vAz);
-      v = make_double2((ld(mX, c) + 0.5 * Fx) / rho, wall ? 0.0 : (ld(mZ, c) + 0.5 * Fz) / rho);
-    }
-    lds[(size_t)r * N + (R.pow2 ? bitrev(x, bits) : x)] = v;
-  };
-  if (live && (N & 1) == 0) {
-    // even rows: a thread takes two neighbouring nodes, reading each row of
-    // each species as one aligned pair (x and the row length are even) and
-    // the pair's two outer neighbours
-    auto ld2 = [](const FT* base, uint32_t off) {
-      if constexpr (sizeof(FT) == 8) {
-        return *(const double2*)((const char*)base + off);
-      } else {
-        const float2 v = *(const float2*)((const char*)base + off);
-        return make_double2((double)v.x, (double)v.y);
-      }
-    };
-    for (int x = 2 * t2; x < N; x += 2 * gsz) {
-      const uint32_t x8 = FS * x, xm8 = x == 0 ? FS * (N - 1) : x8 - FS,
-                     xq8 = x + 2 == N ? 0u : x8 + 2 * FS;
-      Stencil A0, A1, B0, B1;
-      auto rows = [&](const FT* base, Stencil& S0, Stencil& S1) {
-        const double2 mD = ld2(base, oD + x8), mC = ld2(base, oC + x8), mU = ld2(base, oU + x8);
-        const double lD = ld(base, oD + xm8), lC = ld(base, oC + xm8), lU = ld(base, oU + xm8);
-        const double rD = ld(base, oD + xq8), rC = ld(base, oC + xq8), rU = ld(base, oU + xq8);
-        S0 = Stencil{mD.x, lD, mD.y, mC.x, lC, mC.y, mU.x, lU, mU.y};
-        S1 = Stencil{mD.y, mD.x, rD, mC.y, mC.x, rC, mU.y, mU.x, rU};
-      };
-      rows(dA, A0, A1);
-      rows(dB, B0, B1);
-      eval(x, oC + x8, A0, B0);
-      eval(x + 1, oC + x8 + FS, A1, B1);
-    }
-  } else if (live) {
+  if (live)
     for (int x = t2; x < N; x += gsz) {
-      const uint32_t x8 = FS * x, xm8 = x == 0 ? FS * (N - 1) : x8 - FS,
-                     xp8 = x == N - 1 ? 0u : x8 + FS;
-      auto row3 = [&](const FT* base) {
-        return Stencil{ld(base, oD + x8), ld(base, oD + xm8), ld(base, oD + xp8),
-                       ld(base, oC + x8), ld(base, oC + xm8), ld(base, oC + xp8),
-                       ld(base, oU + x8), ld(base, oU + xm8), ld(base, oU + xp8)};
-      };
-      eval(x, oC + x8, row3(dA), row3(dB));
+      const size_t n = (size_t)j * N + x;
+      lds[(size_t)r * N + (R.pow2 ? bitrev(x, bits) : x)] =
+          make_double2((double)z[2 * n], (double)z[2 * n + 1]);
     }
-  }
-  if (pair == 0) {
-    // row sums of P - P_ref: a butterfly over the row's lanes within each
-    // wavefront (fixed order, every lane receives the sum), then the row's
-    // wavefronts in order.  gsz is a power of two: rows are grouped only on
-    // power-of-two lattices, where every group holds the same power of two.
-    const int w = gsz < kWave ? gsz : kWave;
-    double v = psum;
-    for (int m = w >> 1; m >= 1; m >>= 1) v += __shfl_xor(v, m, w);
-    if (gsz > kWave) {
-      if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
-      __syncthreads();
-      if (live && t2 == 0) {
-        double sum = 0.0;
-        for (int k = 0; k < gsz / kWave; ++k) sum += red[threadIdx.x / kWave + k];
-        ppart[R.ppart_off + j] = sum;
-      }
-    } else if (live && t2 == 0) {
-      ppart[R.ppart_off + j] = v;
-    }
-    if (bad) atomicOr(watchdog, 1);
-  }
   if (R.pow2) {
     double2* tws = lds + total;
     for (int m = threadIdx.x; m < N / 2; m += blockDim.x) tws[m] = tw[m];
@@ -242,27 +162,31 @@ __global__ __launch_bounds__(256) void k_row_transform(const RepInfo* reps, cons
       Zm = make_double2(mr, mi);
     }
     // C(k) = (Z(k) + conj Z(N-k)) / 2, Rho(k) = (Z(k) - conj Z(N-k)) / (2i)
-    const size_t o = (size_t)r * nkx + k;
-    out_c[o] = make_double2(0.5 * (Z.x + Zm.x), 0.5 * (Z.y - Zm.y));
-    out_r[o] = make_double2(0.5 * (Z.y + Zm.y), 0.5 * (Zm.x - Z.x));
+    const size_t o = (size_t)r * R.spitch + k;
+    out_c[o] = narrow<ST>(0.5 * (Z.x + Zm.x), 0.5 * (Z.y - Zm.y));
+    out_r[o] = narrow<ST>(0.5 * (Z.y + Zm.y), 0.5 * (Zm.x - Z.x));
   }
 }
 
-// Pressure of a sample for one replica, by one block: the row sums go into the
-// profile (row means), then a fixed-shape tree over the rows gives the spatial
-// mean.  Layout of the replica's block: {sum, sum2, profile[Lz]}.  rows: LDS
-// scratch of at least the next power of two >= Lz doubles.
+// Pressure of a sample for one replica, by one block: each row's sum is its
+// parts in order plus Lx times the row's constant part; the row sums go into
+// the profile (row means), then a fixed-shape tree over the rows gives the
+// spatial mean.  Layout of the replica's block: {sum, sum2, profile[Lz]}.
+// rows: LDS scratch of at least the next power of two >= Lz doubles.
 __device__ void pressure_reduce(const RepInfo& R, const double* ppart, double* acc,
                                 double* rows) {
-  const int Lz = R.Lz;
-  const double* pp = ppart + R.ppart_off;  // row sums of P - P_ref
+  const int Lz = R.Lz, np = pressure_parts(R.Lx);
+  const double* pp = ppart + R.ppart_off;  // parts of the row sums of P - P_ref
   double* pa = acc + R.pacc_off;
   int P2 = 1;
   while (P2 < Lz) P2 <<= 1;
   for (int j = threadIdx.x; j < P2; j += blockDim.x) {
     double s = 0.0;
     if (j < Lz) {
-      s = pp[j];
+      const double* part = pp + (size_t)j * np;
+      double d = part[0];
+      for (int k = 1; k < np; ++k) d += part[k];
+      s = d + R.Lx * pressure_row_ref(R, j);
       pa[2 + j] += s / (double)R.Lx;
     }
     rows[j] = s;
@@ -283,117 +207,340 @@ __device__ void pressure_reduce(const RepInfo& R, const double* ppart, double* a
 // The block of the first tile of the first field also reduces the replica's
 // pressure (the row pass has written all row sums).
 // LDS: the tile's columns, then (power-of-two columns) the M/2 twiddles.
+template <typename ST>
 __global__ __launch_bounds__(256) void k_col_transform(const RepInfo* reps, const ColRef* cols,
-                                                       const double2* spec, double* acc,
+                                                       const ST* spec0, double* acc,
                                                        const double2* tw_base,
-                                                       const double* ppart) {
+                                                       const double* ppart0, int nslots,
+                                                       size_t spec_slot, size_t ppart_slot) {
   extern __shared__ double2 lds[];
   const ColRef cr = cols[blockIdx.x];
-  const RepInfo& R = reps[cr.rep];
-  const int Lx = R.Lx, M = R.Lz, nkx = Lx / 2 + 1;
-  const int nc = cr.ncols, lt = cr.ltile, tmask = (1 << lt) - 1;
-  const double2* in = spec + R.spec_off + (size_t)cr.field * M * nkx + cr.kx0;
-  const double2* tw = tw_base + R.tw_off + Lx;
-  const size_t plane = (size_t)M * nkx;
-  // accumulators are stored column-major, [k_x][k_z], so a tile's sums are one
-  // contiguous run per kind
-  double* a2 = acc + R.acc_off + (size_t)cr.field * 3 * plane + (size_t)cr.kx0 * M;
-  double* are = a2 + plane;
-  double* aim = a2 + 2 * plane;
-  const double norm = R.inv_norm;
-  const int bits = __ffs(M) - 1;
-  const int total = M << lt;
-  // load: row-major reads of the tile's consecutive k_x of each row
-  for (int base = threadIdx.x; base < total; base += kBatch * blockDim.x) {
-    // (two plain arrays: an array of double2 assigned under a condition is
-    // kept in scratch memory)
-    double vr[kBatch], vi[kBatch];
+  for (int sl = 0; sl < nslots; ++sl) {
+    // samples in slot order, each a full pass over the tile
+    const ST* spec = spec0 + sl * spec_slot;
+    const double* ppart = ppart0 + sl * ppart_slot;
+    if (sl > 0) __syncthreads();  // the last sample's tile and sums are done with
+    const RepInfo& R = reps[cr.rep];
+    const int Lx = R.Lx, M = R.Lz, nkx = Lx / 2 + 1;
+    const int nc = cr.ncols, lt = cr.ltile, tmask = (1 << lt) - 1;
+    const ST* in = spec + R.spec_off + (size_t)cr.field * M * R.spitch + cr.kx0;
+    const double2* tw = tw_base + R.tw_off + Lx;
+    const size_t plane = (size_t)M * nkx;
+    // accumulators are stored column-major, [k_x][k_z], so a tile's sums are one
+    // contiguous run per kind
+    double* a2 = acc + R.acc_off + (size_t)cr.field * 3 * plane + (size_t)cr.kx0 * M;
+    double* are = a2 + plane;
+    double* aim = a2 + 2 * plane;
+    const double norm = R.inv_norm;
+    const int bits = __ffs(M) - 1;
+    const int total = M << lt;
+    // load: row-major reads of the tile's consecutive k_x of each row
+    for (int base = threadIdx.x; base < total; base += kBatch * blockDim.x) {
+      // (two plain arrays: an array of double2 assigned under a condition is
+      // kept in scratch memory)
+      double vr[kBatch], vi[kBatch];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int q = base + u * blockDim.x;
-      if (q < total && (q & tmask) < nc) {
-        const double2 t = in[(size_t)(q >> lt) * nkx + (q & tmask)];
-        vr[u] = t.x;
-        vi[u] = t.y;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int q = base + u * blockDim.x;
-      const int j = q >> lt, c = q & tmask;
-      if (q < total && c < nc)
-        lds[(size_t)c * M + (R.pow2 ? bitrev(j, bits) : j)] = make_double2(vr[u], vi[u]);
-    }
-  }
-  if (R.pow2) {
-    // The sums of the first batch of entries are loaded before the transform,
-    // so that their latency overlaps it (entry q of the tile is column
-    // q >> bits, k_z = q & (M - 1), at offset q of each accumulator run).
-    const int valid = min(total, nc * M);
-    double s2[kBatch], sr[kBatch], si[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int q = threadIdx.x + u * blockDim.x;
-      if (q < valid) {
-        s2[u] = a2[q];
-        sr[u] = are[q];
-        si[u] = aim[q];
-      }
-    }
-    double2* tws = lds + ((size_t)M << lt);
-    for (int m = threadIdx.x; m < M / 2; m += blockDim.x) tws[m] = tw[m];
-    lds_fft(lds, bits, nc, tws);
-    for (int base = threadIdx.x; base < valid; base += kBatch * blockDim.x) {
-      if (base != (int)threadIdx.x) {
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-          const int q = base + u * blockDim.x;
-          if (q < valid) {
-            s2[u] = a2[q];
-            sr[u] = are[q];
-            si[u] = aim[q];
-          }
+      for (int u = 0; u < kBatch; ++u) {
+        const int q = base + u * blockDim.x;
+        if (q < total && (q & tmask) < nc) {
+          const double2 t = widen(in[(size_t)(q >> lt) * R.spitch + (q & tmask)]);
+          vr[u] = t.x;
+          vi[u] = t.y;
         }
       }
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
         const int q = base + u * blockDim.x;
+        const int j = q >> lt, c = q & tmask;
+        if (q < total && c < nc)
+          lds[(size_t)c * M + (R.pow2 ? bitrev(j, bits) : j)] = make_double2(vr[u], vi[u]);
+      }
+    }
+    if (R.pow2) {
+      // The sums of the first batch of entries are loaded before the transform,
+      // so that their latency overlaps it (entry q of the tile is column
+      // q >> bits, k_z = q & (M - 1), at offset q of each accumulator run).
+      const int valid = min(total, nc * M);
+      double s2[kBatch], sr[kBatch], si[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int q = threadIdx.x + u * blockDim.x;
         if (q < valid) {
-          const double2 P = lds[q];
-          const double re = P.x * norm, im = P.y * norm;
-          a2[q] = s2[u] + (re * re + im * im);
-          are[q] = sr[u] + re;
-          aim[q] = si[u] + im;
+          s2[u] = a2[q];
+          sr[u] = are[q];
+          si[u] = aim[q];
         }
       }
+      double2* tws = lds + ((size_t)M << lt);
+      for (int m = threadIdx.x; m < M / 2; m += blockDim.x) tws[m] = tw[m];
+      lds_fft(lds, bits, nc, tws);
+      for (int base = threadIdx.x; base < valid; base += kBatch * blockDim.x) {
+        if (base != (int)threadIdx.x) {
+#pragma unroll
+          for (int u = 0; u < kBatch; ++u) {
+            const int q = base + u * blockDim.x;
+            if (q < valid) {
+              s2[u] = a2[q];
+              sr[u] = are[q];
+              si[u] = aim[q];
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+          const int q = base + u * blockDim.x;
+          if (q < valid) {
+            const double2 P = lds[q];
+            const double re = P.x * norm, im = P.y * norm;
+            a2[q] = s2[u] + (re * re + im * im);
+            are[q] = sr[u] + re;
+            aim[q] = si[u] + im;
+          }
+        }
+      }
+    } else {
+      __syncthreads();
+      for (int q = threadIdx.x; q < total; q += blockDim.x) {
+        const int c = q / M, kz = q - c * M;
+        if (c >= nc) continue;
+        const double2* col = lds + (size_t)c * M;
+        double re = 0, im = 0;
+        int ik = 0;
+        for (int j = 0; j < M; ++j) {
+          const double2 a = col[j], w = tw[ik];
+          re += a.x * w.x - a.y * w.y;
+          im += a.x * w.y + a.y * w.x;
+          ik += kz;
+          if (ik >= M) ik -= M;
+        }
+        re *= norm;
+        im *= norm;
+        const size_t o = (size_t)c * M + kz;
+        a2[o] += re * re + im * im;
+        are[o] += re;
+        aim[o] += im;
+      }
+    }
+    if (cr.field == 0 && cr.kx0 == 0) {
+      __syncthreads();  // the tile's LDS is free again (it holds >= Lz double2)
+      pressure_reduce(R, ppart, acc, (double*)lds);
+    }
+  }
+}
+
+// ---- Wavefront transforms (rows and columns of 8 to 512 points, powers of
+// two): one sequence per group of N / 8 lanes, eight points per lane, the
+// Stockham passes of wave_fft.
+
+// Row pass of a sample on rows of N = 8 to 512 points (a power of two): each
+// wavefront takes one task of up to 512 / N consecutive rows of one replica,
+// one row per group of S = N / 8 lanes, and one field pair.  Lane t of a
+// group loads the pairs of the nodes 8t .. 8t + 7 of its row; the row is
+// transformed (wave_fft) and split by Hermitian symmetry into the half
+// spectra k_x = 0 .. N/2 of the two fields.
+template <typename FT, int N>
+__device__ __forceinline__ void row_fft(const RepInfo& R, const RowTask& T, int pair, int lane,
+                                        const void* fields, void* spec,
+                                        const double2* tw_base, double2* wlds) {
+  using ST = typename SpecOf<FT>::type;
+  constexpr int S = N / 8, G = 64 / S;
+  static_assert(G * seq_pitch(N) <= kWaveFftLds, "wavefront LDS");
+  const int Lz = R.Lz;
+  const int g = lane / S, t = lane % S;
+  const bool live = g < T.nrows;
+  const int j = T.j0 + (live ? g : 0);
+  double2* buf = wlds + g * seq_pitch(N);
+  // the row's pairs, eight consecutive nodes per lane, loaded together
+  const FT* z = (const FT*)fields + R.field_off + (size_t)pair * 2 * Lz * N +
+                2 * ((size_t)j * N + 8 * t);
+  double2 u[8];
+  if constexpr (sizeof(FT) == 4) {
+    float4 q[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = *(const float4*)(z + 4 * k);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      u[2 * k] = make_double2(q[k].x, q[k].y);
+      u[2 * k + 1] = make_double2(q[k].z, q[k].w);
     }
   } else {
-    __syncthreads();
-    for (int q = threadIdx.x; q < total; q += blockDim.x) {
-      const int c = q / M, kz = q - c * M;
-      if (c >= nc) continue;
-      const double2* col = lds + (size_t)c * M;
-      double re = 0, im = 0;
-      int ik = 0;
-      for (int j = 0; j < M; ++j) {
-        const double2 a = col[j], w = tw[ik];
-        re += a.x * w.x - a.y * w.y;
-        im += a.x * w.y + a.y * w.x;
-        ik += kz;
-        if (ik >= M) ik -= M;
-      }
-      re *= norm;
-      im *= norm;
-      const size_t o = (size_t)c * M + kz;
-      a2[o] += re * re + im * im;
-      are[o] += re;
-      aim[o] += im;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) u[k] = *(const double2*)(z + 2 * k);
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) buf[pidx(8 * t + k)] = u[k];
+  wave_sync();
+  double2 v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = buf[pidx(t + S * q)];
+  wave_fft<N>(v, buf, t, tw_base + R.tw_off);
+  // C(k) = (Z(k) + conj Z(N-k)) / 2, Rho(k) = (Z(k) - conj Z(N-k)) / (2i), k <= N/2
+  wave_sync();
+#pragma unroll
+  for (int p = 0; p < 8; ++p) buf[pidx(t + S * p)] = v[p];
+  wave_sync();
+  if (!live) return;
+  ST* out_c = (ST*)spec + R.spec_off + ((size_t)(2 * pair) * Lz + j) * R.spitch;
+  ST* out_r = out_c + (size_t)Lz * R.spitch;
+#pragma unroll
+  for (int p = 0; p < 5; ++p) {
+    const int k = t + S * p;
+    if (k <= N / 2) {
+      const double2 Z = v[p], Zm = buf[pidx((N - k) & (N - 1))];
+      out_c[k] = narrow<ST>(0.5 * (Z.x + Zm.x), 0.5 * (Z.y - Zm.y));
+      out_r[k] = narrow<ST>(0.5 * (Z.y + Zm.y), 0.5 * (Zm.x - Z.x));
     }
   }
-  if (cr.field == 0 && cr.kx0 == 0) {
-    __syncthreads();  // the tile's LDS is free again (it holds >= Lz double2)
-    pressure_reduce(R, ppart, acc, (double*)lds);
+}
+
+template <typename FT>
+__global__ __launch_bounds__(256) void k_row_fft(const RepInfo* reps, const RowTask* tasks,
+                                                 int n_tasks, const void* fields, void* spec,
+                                                 const double2* tw_base) {
+  __shared__ double2 lds[4 * kWaveFftLds];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+  const int task = blockIdx.x * 4 + wv;
+  if (task >= n_tasks) return;  // the whole wavefront: nothing below waits on others
+  const RowTask T = tasks[task];
+  const RepInfo& R = reps[__builtin_amdgcn_readfirstlane(T.rep)];
+  const int pair = blockIdx.y;
+  double2* w = lds + wv * kWaveFftLds;
+#define FNLB_ROW(n) row_fft<FT, n>(R, T, pair, lane, fields, spec, tw_base, w)
+  switch (R.Lx) {
+    case 8: FNLB_ROW(8); break;
+    case 16: FNLB_ROW(16); break;
+    case 32: FNLB_ROW(32); break;
+    case 64: FNLB_ROW(64); break;
+    case 128: FNLB_ROW(128); break;
+    case 256: FNLB_ROW(256); break;
+    default: FNLB_ROW(512); break;
   }
+#undef FNLB_ROW
+}
+
+// Column pass on columns of M = 8 to 512 points (Lz a power of two), over the
+// spectra of nslots samples (slot s at spec + s spec_slot): a block takes a
+// tile of C = 2048 / M consecutive k_x columns of one field's row spectra
+// (every row of the tile one run of whole 128-byte lines) per sample, each
+// wavefront transforms C / 4 of them (wave_fft, one per group of M / 8 lanes)
+// and adds |Phi|^2, Re Phi and Im Phi of entries k_z = t + S p to running FP64
+// sums, sample after sample, which it loads before the first and stores after
+// the last; the sums therefore round exactly as one pass per sample would.
+// The next sample's tile is loaded while the current one is transformed.  The
+// block of the first tile of the first field also adds the replica's pressure
+// of each sample, in order.
+template <typename ST, int M>
+__device__ __forceinline__ void col_fft(const RepInfo& R, const ColTask& T, const ST* spec,
+                                        int nslots, size_t spec_slot, double* acc,
+                                        const double2* tw_base, const double* ppart,
+                                        size_t ppart_slot, double2* lds) {
+  constexpr int S = M / 8, G = 64 / S, C = 4 * G, pitch = seq_pitch(M);
+  constexpr int rp = 256 / C;  // tile rows one load instruction covers
+  static_assert(C * pitch <= 4 * kWaveFftLds, "tile");
+  const int Lx = R.Lx, nkx = Lx / 2 + 1, spitch = R.spitch;
+  const double norm = R.inv_norm;
+  const int ncols = T.ncols;
+  const size_t plane = (size_t)M * nkx;
+  const double2* tw = tw_base + R.tw_off + Lx;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+  const int g = lane / S, t = lane % S;
+  const int c = wv * G + g;
+  const bool live = c < ncols;
+  // accumulators are stored column-major, [k_x][k_z]; a dead group reads the
+  // tile's first column, so that the sums stay in registers
+  double* a2 = acc + R.acc_off + (size_t)T.field * 3 * plane + (size_t)T.kx0 * M +
+               (size_t)(live ? c : 0) * M;
+  double s2[8], sr[8], si[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const int kz = t + S * p;
+    s2[p] = a2[kz];
+    sr[p] = a2[plane + kz];
+    si[p] = a2[2 * plane + kz];
+  }
+  // the tile: thread i loads column i % C (a column past the tile, whose group
+  // is dead, loads a copy of the first column) of rows i / C + rp u, as named
+  // values (an array kept across a barrier would be placed in scratch memory)
+  const int lc = threadIdx.x % C, lr = threadIdx.x / C;
+  const ST* in = spec + R.spec_off + (size_t)T.field * M * spitch + T.kx0 +
+                 (size_t)lr * spitch + (lc < ncols ? lc : 0);
+  const size_t rs = (size_t)rp * spitch;
+  ST l0 = in[0], l1 = in[rs], l2 = in[2 * rs], l3 = in[3 * rs], l4 = in[4 * rs],
+     l5 = in[5 * rs], l6 = in[6 * rs], l7 = in[7 * rs];
+  double2* tile = lds + lc * pitch;
+  double2* col = lds + c * pitch;
+  for (int sl = 0; sl < nslots; ++sl) {
+    lds_barrier();  // every wavefront is done with the last tile
+    tile[pidx(lr)] = widen(l0);
+    tile[pidx(lr + rp)] = widen(l1);
+    tile[pidx(lr + 2 * rp)] = widen(l2);
+    tile[pidx(lr + 3 * rp)] = widen(l3);
+    tile[pidx(lr + 4 * rp)] = widen(l4);
+    tile[pidx(lr + 5 * rp)] = widen(l5);
+    tile[pidx(lr + 6 * rp)] = widen(l6);
+    tile[pidx(lr + 7 * rp)] = widen(l7);
+    if (sl + 1 < nslots) {
+      in += spec_slot;
+      l0 = in[0];
+      l1 = in[rs];
+      l2 = in[2 * rs];
+      l3 = in[3 * rs];
+      l4 = in[4 * rs];
+      l5 = in[5 * rs];
+      l6 = in[6 * rs];
+      l7 = in[7 * rs];
+    }
+    lds_barrier();  // (the next tile's loads stay in flight)
+    double2 v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = col[pidx(t + S * q)];
+    wave_fft<M>(v, col, t, tw);
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const double re = v[p].x * norm, im = v[p].y * norm;
+      s2[p] = s2[p] + (re * re + im * im);
+      sr[p] = sr[p] + re;
+      si[p] = si[p] + im;
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int kz = t + S * p;
+      a2[kz] = s2[p];
+      a2[plane + kz] = sr[p];
+      a2[2 * plane + kz] = si[p];
+    }
+  }
+  if (T.field == 0 && T.kx0 == 0) {
+    for (int sl = 0; sl < nslots; ++sl) {
+      __syncthreads();  // the tile (or the previous sum) is no longer read
+      pressure_reduce(R, ppart + sl * ppart_slot, acc, (double*)lds);
+    }
+  }
+}
+
+template <typename ST>
+__global__ __launch_bounds__(256) void k_col_fft(const RepInfo* reps, const ColTask* tasks,
+                                                 const ST* spec, int nslots,
+                                                 size_t spec_slot, double* acc,
+                                                 const double2* tw_base, const double* ppart,
+                                                 size_t ppart_slot) {
+  __shared__ double2 lds[4 * kWaveFftLds];
+  const ColTask T = tasks[blockIdx.x];
+  const RepInfo& R = reps[__builtin_amdgcn_readfirstlane(T.rep)];
+#define FNLB_COL(n) \
+  col_fft<ST, n>(R, T, spec, nslots, spec_slot, acc, tw_base, ppart, ppart_slot, lds)
+  switch (R.Lz) {
+    case 8: FNLB_COL(8); break;
+    case 16: FNLB_COL(16); break;
+    case 32: FNLB_COL(32); break;
+    case 64: FNLB_COL(64); break;
+    case 128: FNLB_COL(128); break;
+    case 256: FNLB_COL(256); break;
+    default: FNLB_COL(512); break;
+  }
+#undef FNLB_COL
 }
 
 }  // namespace
@@ -421,28 +568,74 @@ hipError_t launch_twiddles(const RepInfo* d_reps, const RepInfo* h_reps, int n_r
   return hipGetLastError();
 }
 
+hipError_t launch_row_consts(const RepInfo* d_reps, const RepInfo* h_reps, int n_rep,
+                             int precision, hipStream_t stream) {
+  int maxz = 0;
+  for (int r = 0; r < n_rep; ++r) maxz = std::max(maxz, h_reps[r].Lz);
+  const dim3 grid((maxz + 255) / 256, n_rep);
+  if (precision == FNLB_FP64)
+    hipLaunchKernelGGL(k_row_consts<double>, grid, dim3(256), 0, stream, d_reps);
+  else
+    hipLaunchKernelGGL(k_row_consts<float>, grid, dim3(256), 0, stream, d_reps);
+  return hipGetLastError();
+}
+
 hipError_t launch_row_transform(const RepInfo* reps, const RowRef* rows, int n_rows, int n_pairs,
                                 int max_row_lds, int precision, const void* fields,
-                                double2* spec, const double2* tw, double* ppart,
-                                int32_t* watchdog, hipStream_t stream) {
+                                void* spec, const double2* tw, hipStream_t stream) {
   if (n_rows <= 0) return hipSuccess;
   const size_t lds = (size_t)max_row_lds * sizeof(double2);
   if (precision == FNLB_FP64)
     hipLaunchKernelGGL(k_row_transform<double>, dim3(n_rows, n_pairs), dim3(256), lds, stream,
-                       reps, rows, fields, spec, tw, ppart, watchdog);
+                       reps, rows, fields, spec, tw);
   else
     hipLaunchKernelGGL(k_row_transform<float>, dim3(n_rows, n_pairs), dim3(256), lds, stream,
-                       reps, rows, fields, spec, tw, ppart, watchdog);
+                       reps, rows, fields, spec, tw);
   return hipGetLastError();
 }
 
 hipError_t launch_col_transform(const RepInfo* reps, const ColRef* cols, int n_cols,
-                                int max_lds_cols, const double2* spec, double* acc,
-                                const double2* tw, const double* ppart, hipStream_t stream) {
-  if (n_cols <= 0) return hipSuccess;
+                                int max_lds_cols, int precision, const void* spec, int nslots,
+                                size_t spec_slot, double* acc, const double2* tw,
+                                const double* ppart, size_t ppart_slot, hipStream_t stream) {
+  if (n_cols <= 0 || nslots <= 0) return hipSuccess;
   const size_t lds = (size_t)max_lds_cols * sizeof(double2);
-  hipLaunchKernelGGL(k_col_transform, dim3(n_cols), dim3(256), lds, stream, reps, cols, spec,
-                     acc, tw, ppart);
+  if (precision == FNLB_FP64)
+    hipLaunchKernelGGL(k_col_transform<double2>, dim3(n_cols), dim3(256), lds, stream, reps,
+                       cols, (const double2*)spec, acc, tw, ppart, nslots, spec_slot,
+                       ppart_slot);
+  else
+    hipLaunchKernelGGL(k_col_transform<float2>, dim3(n_cols), dim3(256), lds, stream, reps,
+                       cols, (const float2*)spec, acc, tw, ppart, nslots, spec_slot,
+                       ppart_slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_fft(const RepInfo* reps, const RowTask* tasks, int n_tasks, int n_pairs,
+                          int precision, const void* fields, void* spec, const double2* tw,
+                          hipStream_t stream) {
+  if (n_tasks <= 0) return hipSuccess;
+  const dim3 grid((n_tasks + 3) / 4, n_pairs);
+  if (precision == FNLB_FP64)
+    hipLaunchKernelGGL(k_row_fft<double>, grid, dim3(256), 0, stream, reps, tasks, n_tasks,
+                       fields, spec, tw);
+  else
+    hipLaunchKernelGGL(k_row_fft<float>, grid, dim3(256), 0, stream, reps, tasks, n_tasks,
+                       fields, spec, tw);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_fft(const RepInfo* reps, const ColTask* tasks, int n_tasks,
+                          int precision, const void* spec, int nslots, size_t spec_slot,
+                          double* acc, const double2* tw, const double* ppart,
+                          size_t ppart_slot, hipStream_t stream) {
+  if (n_tasks <= 0 || nslots <= 0) return hipSuccess;
+  if (precision == FNLB_FP64)
+    hipLaunchKernelGGL(k_col_fft<double2>, dim3(n_tasks), dim3(256), 0, stream, reps, tasks,
+                       (const double2*)spec, nslots, spec_slot, acc, tw, ppart, ppart_slot);
+  else
+    hipLaunchKernelGGL(k_col_fft<float2>, dim3(n_tasks), dim3(256), 0, stream, reps, tasks,
+                       (const float2*)spec, nslots, spec_slot, acc, tw, ppart, ppart_slot);
   return hipGetLastError();
 }
 

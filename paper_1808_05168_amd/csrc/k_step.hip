@@ -34,10 +34,9 @@
 // the row is collided, while the loads of the row after next are in flight.
 // Stores are the node's own 18 post-collision values; in the tiled
 // layout each link of a wavefront's row is one contiguous 256-byte run.  A
-// step that samples also writes, per node, the density deviations of the
-// state it pulled (and the momenta for velocity sampling), summed in FP64 and
-// stored in the storage type; the transform pass forms the observables from
-// them in FP64.
+// step that samples also forms, per node, the sample of the state it pulled
+// from the stencil its collision reads (node_sample, in the compute type) and
+// stores the pairs the row transform takes and the pressure deviation.
 #include "fnlb.h"
 #include "fnlb_device.hpp"
 #include "fnlb_internal.hpp"
@@ -111,6 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   const Rsrc in = make_rsrc((const char*)a.state_in + R.state_off * SB, block_b);
   const Rsrc out = make_rsrc((char*)a.state_out + R.state_off * SB, block_b);
   const int flags = R.flags;
+  const SampleDest<Store, Real> SD = sample_dest<Store, Real>(R, a.fields, a.ppart);
 
   // columns of this segment
   const int X0 = it.strip * kSeg;
@@ -287,6 +287,9 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
       load_pulled(in, link_b, row_b, ja + dir, Lz, xb, xmb, xpb, nxt);
       ev = pull_edges(ja + dir);
     }
+    // the sample constants of row j, read before the barrier
+    SampleRow<Real> srow{};
+    if constexpr (MODE != kStep) srow = sample_row(SD, j);
     __syncthreads();
     if (ahead) sum_edges(ja);
 
@@ -297,45 +300,40 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     const double rAj = rA0 + rAs * j;
     const double szref = rAs * (double)(jU - jD) * (1.0 / 6.0);  // species A
 
+    // sample of f(t) (sampling modes), formed from the stencil the collision
+    // reads (the arithmetic shares nothing with the collision) and stored
+    // before it, which keeps the sample out of the collision's registers
+    // the stencil: the sample reads its own before the collision's (this
+    // kernel is bound by its memory traffic, not by LDS; a stencil kept across
+    // the sample would cost registers, and in FP64 an occupancy step)
+    auto stencil = [&]() {
+      return load_stencil(ring[jU & 3][0], ring[j & 3][0], ring[jD & 3][0], ring[jU & 3][1],
+                          ring[j & 3][1], ring[jD & 3][1], c);
+    };
     if constexpr (MODE != kStep) {
-      // sample of f(t): the density deviations of this node and, for velocity
-      // sampling, its total momentum, summed in FP64 and stored in the storage
-      // type (in FP32 the rounding, 6e-8 relative, stays far inside the
-      // 1e-5 bar of that storage form); the transform pass forms the
-      // observables from them
-      if (act) {
-        double da, db;
-        density<double>(cur, da, db);
-        Store* fld = (Store*)a.fields + R.field_off;
-        const int64_t plane = (int64_t)Lz * Lx, n = (int64_t)j * Lx + x;
-        fld[n] = (Store)da;
-        fld[plane + n] = (Store)db;
-        if (flags & FNLB_SAMPLE_VELOCITY) {
-          double d[9];
-#pragma unroll
-          for (int l = 0; l < 9; ++l) d[l] = (double)cur[l] + (double)cur[9 + l];
-          fld[2 * plane + n] = (Store)((d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]));
-          fld[3 * plane + n] = (Store)((d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]));
+      if (wave_act) {
+        Real dp = (Real)0;
+        if (act) {
+          const bool vel = (flags & FNLB_SAMPLE_VELOCITY) != 0;
+          const NodeSample<Real> smp = sample_of<Real, DT, Store>(
+              stencil(), cur, srow, P.G, vel);
+          store_sample(SD, a.watchdog, j, x, smp, vel);
+          dp = smp.dp;
         }
+        store_pressure_part(SD, j, (X0 >> 6) + wv, dp);
       }
     }
+    const Stencil<DT> st = stencil();
 
     if constexpr (MODE != kSampleOnly) {
      if (wave_act) {
-      const DT* aU = ring[jU & 3][0];
-      const DT* bU = ring[jU & 3][1];
-      const DT* aC = ring[j & 3][0];
-      const DT* bC = ring[j & 3][1];
-      const DT* aD = ring[jD & 3][0];
-      const DT* bD = ring[jD & 3][1];
       Real dA[9], dB[9];
 #pragma unroll
       for (int l = 0; l < 9; ++l) {
         dA[l] = (Real)cur[l];
         dB[l] = (Real)cur[9 + l];
       }
-      node_update<Real, DT>(P, flags, top, bot, rAj, rho0, szref, aU, aC, aD, bU, bC, bD, c, dA,
-                            dB, gA0, gA1, gB0, gB1);
+      node_update<Real, DT>(P, flags, top, bot, rAj, rho0, szref, st, dA, dB, gA0, gA1, gB0, gB1);
 
       // store the node's post-collision populations, each shifted to the
       // reference of the row it streams to (bounced-back links stay in row)

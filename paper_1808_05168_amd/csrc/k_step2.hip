@@ -103,6 +103,7 @@ __global__ __launch_bounds__(kTBLanes) void k_step2(const Step2Args a) {
   const Rsrc in = make_rsrc((const char*)a.state_in + R.state_off * SB, block_b);
   const Rsrc out = make_rsrc((char*)a.state_out + R.state_off * SB, block_b);
   const int flags = R.flags;
+  const SampleDest<Store, Real> SD = sample_dest<Store, Real>(R, a.fields, a.ppart);
 
   const int xl = tid & (W - 1);  // column within the item
   const bool act = sub_ok && xl < Lx;
@@ -184,6 +185,11 @@ __global__ __launch_bounds__(kTBLanes) void k_step2(const Step2Args a) {
     if (doA && wave_act)
       node_noise((uint32_t)(ar * Lx + x), (uint64_t)t, k0, k1, bmt, gA0, gA1, gB0, gB1);
     if (doA && needed(ar + dir)) put_raw(ar + dir, nxt);
+    // the sample constants of row ar, read before the barrier, which waits
+    // for them
+    SampleRow<Real> srow{};
+    if constexpr (MODE == kStepSample)
+      if (doA) srow = sample_row(SD, ar);
     __syncthreads();
 
     // ---- stage A: the first step of row ar, pushed to where it streams
@@ -191,28 +197,26 @@ __global__ __launch_bounds__(kTBLanes) void k_step2(const Step2Args a) {
       const int jU = topA ? ar : ar + 1, jD = botA ? ar : ar - 1;
       const double rAj = rA0 + rAs * ar;
       const double szref = rAs * (double)(jU - jD) * (1.0 / 6.0);
+      // sample of f(t) on the item's own rows, formed as the one-step kernel
+      // forms it, from the stencil the collision reads (its own read of it)
       if constexpr (MODE == kStepSample) {
-        // sample of f(t) on the item's own rows, as the one-step kernel writes it
-        if (act && ar >= j0 && ar < j1) {
-          double da = (double)cur[0], db = (double)cur[9];
-#pragma unroll
-          for (int l = 1; l < 9; ++l) {
-            da += (double)cur[l];
-            db += (double)cur[9 + l];
+        if (wave_act && ar >= j0 && ar < j1) {
+          Real dp = (Real)0;
+          if (act) {
+            const bool vel = (flags & FNLB_SAMPLE_VELOCITY) != 0;
+            const NodeSample<Real> smp = sample_of<Real, DT, Store>(
+                load_stencil(ring[mod3(jU)][0], ring[mod3(ar)][0], ring[mod3(jD)][0],
+                             ring[mod3(jU)][1], ring[mod3(ar)][1], ring[mod3(jD)][1], c),
+                cur, srow, P.G, vel);
+            store_sample(SD, a.watchdog, ar, x, smp, vel);
+            dp = smp.dp;
           }
-          Store* fld = (Store*)a.fields + R.field_off;
-          const int64_t plane = (int64_t)Lz * Lx, n = (int64_t)ar * Lx + x;
-          fld[n] = (Store)da;
-          fld[plane + n] = (Store)db;
-          if (flags & FNLB_SAMPLE_VELOCITY) {
-            double d[9];
-#pragma unroll
-            for (int l = 0; l < 9; ++l) d[l] = (double)cur[l] + (double)cur[9 + l];
-            fld[2 * plane + n] = (Store)((d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]));
-            fld[3 * plane + n] = (Store)((d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]));
-          }
+          store_pressure_part(SD, ar, ((wv * kWave) & (W - 1)) >> 6, dp);
         }
       }
+      const Stencil<DT> st =
+          load_stencil(ring[mod3(jU)][0], ring[mod3(ar)][0], ring[mod3(jD)][0],
+                       ring[mod3(jU)][1], ring[mod3(ar)][1], ring[mod3(jD)][1], c);
       if (wave_act) {
         Real dA[9], dB[9];
 #pragma unroll
@@ -220,10 +224,9 @@ __global__ __launch_bounds__(kTBLanes) void k_step2(const Step2Args a) {
           dA[l] = cur[l];
           dB[l] = cur[9 + l];
         }
-        node_update<Real, DT>(P, flags, topA, botA, rAj, rho0, szref, ring[mod3(jU)][0],
-                              ring[mod3(ar)][0], ring[mod3(jD)][0], ring[mod3(jU)][1],
-                              ring[mod3(ar)][1], ring[mod3(jD)][1], c, dA, dB, gA0, gA1, gB0,
+        node_update<Real, DT>(P, flags, topA, botA, rAj, rho0, szref, st, dA, dB, gA0, gA1, gB0,
                               gB1);
+
         if (act) {
           // values as the one-step kernel stores them: each shifted to the
           // reference of the row it streams to (bounced-back links stay)
@@ -337,10 +340,11 @@ __global__ __launch_bounds__(kTBLanes) void k_step2(const Step2Args a) {
       const int jU = top ? br : br + 1, jD = bot ? br : br - 1;
       const double rAj = rA0 + rAs * br;
       const double szref = rAs * (double)(jU - jD) * (1.0 / 6.0);
-      node_update<Real, DT>(P, flags, top, bot, rAj, rho0, szref, dring[mod3(jU)][0],
-                            dring[mod3(br)][0], dring[mod3(jD)][0], dring[mod3(jU)][1],
-                            dring[mod3(br)][1], dring[mod3(jD)][1], c, dA, dB, gA0b, gA1b,
-                            gB0b, gB1b);
+      const Stencil<DT> stb =
+          load_stencil(dring[mod3(jU)][0], dring[mod3(br)][0], dring[mod3(jD)][0],
+                       dring[mod3(jU)][1], dring[mod3(br)][1], dring[mod3(jD)][1], c);
+      node_update<Real, DT>(P, flags, top, bot, rAj, rho0, szref, stb, dA, dB, gA0b, gA1b, gB0b,
+                            gB1b);
       if (act) {
         const uint32_t off = (uint32_t)br * row_b + xb;
         const Real upf = top ? (Real)0 : (Real)1, dnf = bot ? (Real)0 : (Real)1;

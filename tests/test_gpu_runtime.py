@@ -39,14 +39,19 @@ def _same(a, b):
 @pytest.mark.parametrize("every,prec,two", [(5, 0, 0), (4, 1, 0), (0, 0, 0), (7, 1, 0),
                                             (4, 1, 1), (7, 1, 1), (0, 1, 1)])
 def test_graph_replay_matches_direct_launches(F, every, prec, two):
+    # block transforms for the first two, wavefront transforms for the third;
+    # the step counts leave samples of a call in the spectrum slots of the
+    # batched column pass in every phase, and replay both the graph of one
+    # sampling period and the graph of sixteen
     reps = [W.Replica(Lx=96, Lz=20, grad_c0=2e-3, kT=1e-4, G=0.5, seed=51),
-            W.Replica(Lx=300, Lz=9, grad_c0=1e-2, kT=1e-4, seed=52)]
+            W.Replica(Lx=300, Lz=9, grad_c0=1e-2, kT=1e-4, seed=52),
+            W.Replica(Lx=64, Lz=32, grad_c0=5e-3, kT=1e-4, G=0.3, seed=54)]
     say(f"case: graph vs direct, every={every} precision={prec} two-step={two}")
     kern = F.TWO_STEP if two else F.ONE_STEP
     g = F.Lattice(reps, precision=prec, sample_every=every, flags=F.DEFAULT_FLAGS | kern)
     d = F.Lattice(reps, precision=prec, sample_every=every,
                   flags=F.DEFAULT_FLAGS | F.NO_GRAPH | kern)
-    for n in (3, 7, 20, 1, 13, 40, 0, 17):
+    for n in (3, 7, 20, 1, 13, 40, 0, 17, 120):
         g.step(n)
         d.step(n)
         assert g.time == d.time
