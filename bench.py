@@ -235,12 +235,18 @@ def summarize_trace(trace_dir, out_md, title, command, top=16):
         fh.write("\n".join(lines) + "\n")
 
 
+# steps of the roofline leg before its timed launches (clock ramp, then a probe
+# of 20 steps that sizes the timed part)
+ROOFLINE_LEAD_STEPS = 120
+
+
 def summarize_profile(trace_dir, fetch_dir, write_dir, out_md, command):
     """Turns rocprofv3 outputs of this benchmark into the committed summary:
     kernel-trace statistics, the average duration of the step kernel in the
-    roofline leg (the plain steps after the last sampling step, at the timed
-    grid size; in the sampled run the transforms of a sample overlap the plain
-    steps that follow it, and autotuning trials use other grids), and HBM bytes
+    roofline leg (the plain launches at the timed grid size before the first
+    sampling step, less the leg's first ROOFLINE_LEAD_STEPS steps of clock
+    ramp and probe; in the sampled run the transforms of a sample overlap the
+    plain steps that follow it, and autotuning trials use other grids), and HBM bytes
     per step launch from FETCH_SIZE and WRITE_SIZE scaled by what the same
     counters read for the plain 1 GiB copies that --copy-calibration-mb 1024
     runs first."""
@@ -256,10 +262,11 @@ def summarize_profile(trace_dir, fetch_dir, write_dir, out_md, command):
     step_name, sample_name, spl = STEP_KERNELS[kernel]
     trace = [r for r in rows if step_name in r["Kernel_Name"]]
     grid = Counter(r["Grid_Size_X"] for r in trace).most_common(1)[0][0]
-    last_sample = max((int(r["Start_Timestamp"]) for r in rows
-                       if sample_name in r["Kernel_Name"]), default=-1)
-    durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace
-            if r["Grid_Size_X"] == grid and int(r["Start_Timestamp"]) > last_sample]
+    first_sample = min((int(r["Start_Timestamp"]) for r in rows
+                        if sample_name in r["Kernel_Name"]), default=1 << 62)
+    leg = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace
+           if r["Grid_Size_X"] == grid and int(r["Start_Timestamp"]) < first_sample]
+    durs = leg[ROOFLINE_LEAD_STEPS // spl:]
     avg_us = sum(durs) / len(durs) / 1e3
 
     def counters(d, name):
@@ -583,7 +590,7 @@ def main():
     lat_r = F.Lattice(reps, precision=prec, sample_every=0,
                       flags=(flags & ~(F.ONE_STEP | F.TWO_STEP)) | kflag, chunk_rows=chunk)
     assert lat_r.launch_config() == (spl, chunk)
-    lat_r.step(100)
+    lat_r.step(ROOFLINE_LEAD_STEPS - 20)
     ms_probe = _events_time(lat_r, 20)
     nr = max(50, int(300.0 / max(ms_probe / 20, 1e-3)))
     nr += nr % spl

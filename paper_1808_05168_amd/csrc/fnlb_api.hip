@@ -364,7 +364,9 @@ void make_plan(const fnlb_replica_params* reps, int n_rep, const fnlb_options* o
     const RepInfo& R = P.info[r];
     const int nkx = R.Lx / 2 + 1;
     if (wave_fft_len(R.Lx)) {
-      const int per = kFftMax / R.Lx;  // rows per wavefront
+      // rows per wavefront: two halves of 512 / Lx rows for float pairs, one
+      // for double pairs
+      const int per = (P.store_size == 4 ? 2 : 1) * kFftMax / R.Lx;
       for (int j = 0; j < R.Lz; j += per)
         P.frows.push_back(RowTask{r, j, std::min(per, R.Lz - j), 0});
     } else {

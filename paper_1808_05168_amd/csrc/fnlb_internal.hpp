@@ -87,7 +87,8 @@ struct ColRef {
 };
 
 // Wavefront transforms (sequences of 8 to 512 points): a wavefront's rows
-// j0 .. j0 + nrows - 1 of one replica (nrows <= 512 / Lx), and a block's tile
+// j0 .. j0 + nrows - 1 of one replica (nrows <= 2 x 512 / Lx for float pairs,
+// 512 / Lx for double pairs), and a block's tile
 // of ncols <= 2048 / Lz k_x columns of one field.
 struct RowTask {
   int32_t rep, j0, nrows, pad;

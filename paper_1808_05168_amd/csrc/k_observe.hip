@@ -333,53 +333,76 @@ __global__ __launch_bounds__(256) void k_col_transform(const RepInfo* reps, cons
 // Stockham passes of wave_fft.
 
 // Row pass of a sample on rows of N = 8 to 512 points (a power of two): each
-// wavefront takes one task of up to 512 / N consecutive rows of one replica,
-// one row per group of S = N / 8 lanes, and one field pair.  Lane t of a
-// group loads the pairs of the nodes 8t .. 8t + 7 of its row; the row is
-// transformed (wave_fft) and split by Hermitian symmetry into the half
-// spectra k_x = 0 .. N/2 of the two fields.
+// wavefront takes one task of up to 2 G consecutive rows of one replica (G =
+// 512 / N) in two halves of G rows (float pairs; G rows for double pairs),
+// one row per group of S = N / 8 lanes, and one field pair.  Lane t of a group loads the pairs of the nodes
+// 8t .. 8t + 7 of its row; the row is transformed (wave_fft) and split by
+// Hermitian symmetry into the half spectra k_x = 0 .. N/2 of the two fields.
+// With float pairs the second half's pairs are loaded once the first half's
+// are in LDS, so that their latency overlaps the first half's transform.
+template <typename FT>
+struct RowPairs {  // the eight float pairs of a lane, as loaded
+  float4 q[4];
+};
+
 template <typename FT, int N>
-__device__ __forceinline__ void row_fft(const RepInfo& R, const RowTask& T, int pair, int lane,
-                                        const void* fields, void* spec,
-                                        const double2* tw_base, double2* wlds) {
-  using ST = typename SpecOf<FT>::type;
-  constexpr int S = N / 8, G = 64 / S;
-  static_assert(G * seq_pitch(N) <= kWaveFftLds, "wavefront LDS");
-  const int Lz = R.Lz;
-  const int g = lane / S, t = lane % S;
-  const bool live = g < T.nrows;
-  const int j = T.j0 + (live ? g : 0);
-  double2* buf = wlds + g * seq_pitch(N);
-  // the row's pairs, eight consecutive nodes per lane, loaded together
-  const FT* z = (const FT*)fields + R.field_off + (size_t)pair * 2 * Lz * N +
+__device__ __forceinline__ RowPairs<FT> load_row_pairs(const RepInfo& R, int pair, int j, int t,
+                                                       const void* fields) {
+  const FT* z = (const FT*)fields + R.field_off + (size_t)pair * 2 * R.Lz * N +
                 2 * ((size_t)j * N + 8 * t);
+  RowPairs<FT> r;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.q[k] = *((const float4*)z + k);
+  return r;
+}
+
+// Stage the pairs a lane loaded into its group's sequence in LDS.
+template <typename FT, int N>
+__device__ __forceinline__ void row_stage(const RowPairs<FT>& in, int t, double2* buf) {
   double2 u[8];
-  if constexpr (sizeof(FT) == 4) {
-    float4 q[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) q[k] = *(const float4*)(z + 4 * k);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      u[2 * k] = make_double2(q[k].x, q[k].y);
-      u[2 * k + 1] = make_double2(q[k].z, q[k].w);
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) u[k] = *(const double2*)(z + 2 * k);
+  for (int k = 0; k < 4; ++k) {
+    u[2 * k] = make_double2(in.q[k].x, in.q[k].y);
+    u[2 * k + 1] = make_double2(in.q[k].z, in.q[k].w);
   }
+  wave_sync();  // the group's earlier reads of buf are done
 #pragma unroll
   for (int k = 0; k < 8; ++k) buf[pidx(8 * t + k)] = u[k];
+}
+
+// The same for double pairs, loaded straight into the staging values (the
+// first use of buf in the task).
+template <int N>
+__device__ __forceinline__ void row_stage_direct(const RepInfo& R, int pair, int j, int t,
+                                                 const void* fields, double2* buf) {
+  const double* z = (const double*)fields + R.field_off + (size_t)pair * 2 * R.Lz * N +
+                    2 * ((size_t)j * N + 8 * t);
+  double2 u[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) u[k] = *(const double2*)(z + 2 * k);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) buf[pidx(8 * t + k)] = u[k];
+}
+
+// The transform of the staged row of each group (live groups only store).
+template <typename FT, int N>
+__device__ __forceinline__ void row_transform_staged(const RepInfo& R, int pair, int j, bool live,
+                                                     int t, double2* buf, void* spec,
+                                                     const double2* tw) {
+  using ST = typename SpecOf<FT>::type;
+  constexpr int S = N / 8;
   wave_sync();
   double2 v[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) v[q] = buf[pidx(t + S * q)];
-  wave_fft<N>(v, buf, t, tw_base + R.tw_off);
+  wave_fft<N>(v, buf, t, tw);
   // C(k) = (Z(k) + conj Z(N-k)) / 2, Rho(k) = (Z(k) - conj Z(N-k)) / (2i), k <= N/2
   wave_sync();
 #pragma unroll
   for (int p = 0; p < 8; ++p) buf[pidx(t + S * p)] = v[p];
   wave_sync();
   if (!live) return;
+  const int Lz = R.Lz;
   ST* out_c = (ST*)spec + R.spec_off + ((size_t)(2 * pair) * Lz + j) * R.spitch;
   ST* out_r = out_c + (size_t)Lz * R.spitch;
 #pragma unroll
@@ -390,6 +413,44 @@ __device__ __forceinline__ void row_fft(const RepInfo& R, const RowTask& T, int 
       out_c[k] = narrow<ST>(0.5 * (Z.x + Zm.x), 0.5 * (Z.y - Zm.y));
       out_r[k] = narrow<ST>(0.5 * (Z.y + Zm.y), 0.5 * (Zm.x - Z.x));
     }
+  }
+}
+
+template <typename FT, int N>
+__device__ __forceinline__ void row_fft(const RepInfo& R, const RowTask& T, int pair, int lane,
+                                        const void* fields, void* spec,
+                                        const double2* tw_base, double2* wlds) {
+  constexpr int S = N / 8, G = 64 / S;
+  static_assert(G * seq_pitch(N) <= kWaveFftLds, "wavefront LDS");
+  const int g = lane / S, t = lane % S;
+  double2* buf = wlds + g * seq_pitch(N);
+  const double2* tw = tw_base + R.tw_off;
+  // rows of the two halves (a dead group loads the task's first row)
+  const bool live0 = g < T.nrows, live1 = G + g < T.nrows;
+  const bool two = T.nrows > G;  // the whole wavefront
+  const int j0 = T.j0 + (live0 ? g : 0), j1 = T.j0 + (live1 ? G + g : 0);
+  if constexpr (sizeof(FT) == 4)
+    row_stage<FT, N>(load_row_pairs<FT, N>(R, pair, j0, t, fields), t, buf);
+  else
+    row_stage_direct<N>(R, pair, j0, t, fields, buf);
+  if constexpr (sizeof(FT) == 4) {
+    // the second half's pairs are in flight during the first half's transform
+    // (loaded whether or not the task has a second half: a value loaded under
+    // a condition would be kept in scratch memory)
+    const RowPairs<FT> b = load_row_pairs<FT, N>(R, pair, j1, t, fields);
+    row_transform_staged<FT, N>(R, pair, j0, live0, t, buf, spec, tw);
+    if (two) {
+      // (the twiddles again through a pointer the compiler cannot identify
+      // with tw: kept from the first half, they would stay in registers
+      // across it)
+      const double2* tw1 = tw;
+      asm volatile("" : "+v"(tw1));
+      row_stage<FT, N>(b, t, buf);
+      row_transform_staged<FT, N>(R, pair, j1, live1, t, buf, spec, tw1);
+    }
+  } else {
+    // FP64 pairs: tasks of one half (a second half here costs scratch memory)
+    row_transform_staged<FT, N>(R, pair, j0, live0, t, buf, spec, tw);
   }
 }
 
