@@ -335,66 +335,40 @@ __global__ __launch_bounds__(256) void k_col_transform(const RepInfo* reps, cons
 // Row pass of a sample on rows of N = 8 to 512 points (a power of two): each
 // wavefront takes one task of up to 2 G consecutive rows of one replica (G =
 // 512 / N) in two halves of G rows (float pairs; G rows for double pairs),
-// one row per group of S = N / 8 lanes, and one field pair.  Lane t of a group loads the pairs of the nodes
-// 8t .. 8t + 7 of its row; the row is transformed (wave_fft) and split by
-// Hermitian symmetry into the half spectra k_x = 0 .. N/2 of the two fields.
-// With float pairs the second half's pairs are loaded once the first half's
-// are in LDS, so that their latency overlaps the first half's transform.
+// one row per group of S = N / 8 lanes, and one field pair.  Lane t of a
+// group loads the pairs of nodes t + S q (q = 0..7), the order the first
+// pass of wave_fft takes (each load of a group is one run of S consecutive
+// pairs); the row is transformed and split by Hermitian symmetry into the
+// half spectra k_x = 0 .. N/2 of the two fields.  With float pairs the second
+// half's pairs are loaded before the first half is transformed, so that
+// their latency overlaps that transform.
 template <typename FT>
-struct RowPairs {  // the eight float pairs of a lane, as loaded
-  float4 q[4];
+struct RowPoints {  // the eight pairs of a lane, as loaded
+  float2 p[8];
 };
 
 template <typename FT, int N>
-__device__ __forceinline__ RowPairs<FT> load_row_pairs(const RepInfo& R, int pair, int j, int t,
-                                                       const void* fields) {
-  const FT* z = (const FT*)fields + R.field_off + (size_t)pair * 2 * R.Lz * N +
-                2 * ((size_t)j * N + 8 * t);
-  RowPairs<FT> r;
+__device__ __forceinline__ RowPoints<FT> load_row_points(const RepInfo& R, int pair, int j,
+                                                         int t, const void* fields) {
+  constexpr int S = N / 8;
+  const float2* z = (const float2*)((const FT*)fields + R.field_off) +
+                    (size_t)pair * R.Lz * N + (size_t)j * N + t;
+  RowPoints<FT> r;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) r.q[k] = *((const float4*)z + k);
+  for (int q = 0; q < 8; ++q) r.p[q] = z[S * q];
   return r;
 }
 
-// Stage the pairs a lane loaded into its group's sequence in LDS.
+// The transform of one row per group from its points (v[q] = node t + S q),
+// split into the two half spectra (live groups only store).  buf: the group's
+// sequence in LDS, which the previous row's split may still be reading.
 template <typename FT, int N>
-__device__ __forceinline__ void row_stage(const RowPairs<FT>& in, int t, double2* buf) {
-  double2 u[8];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    u[2 * k] = make_double2(in.q[k].x, in.q[k].y);
-    u[2 * k + 1] = make_double2(in.q[k].z, in.q[k].w);
-  }
-  wave_sync();  // the group's earlier reads of buf are done
-#pragma unroll
-  for (int k = 0; k < 8; ++k) buf[pidx(8 * t + k)] = u[k];
-}
-
-// The same for double pairs, loaded straight into the staging values (the
-// first use of buf in the task).
-template <int N>
-__device__ __forceinline__ void row_stage_direct(const RepInfo& R, int pair, int j, int t,
-                                                 const void* fields, double2* buf) {
-  const double* z = (const double*)fields + R.field_off + (size_t)pair * 2 * R.Lz * N +
-                    2 * ((size_t)j * N + 8 * t);
-  double2 u[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) u[k] = *(const double2*)(z + 2 * k);
-#pragma unroll
-  for (int k = 0; k < 8; ++k) buf[pidx(8 * t + k)] = u[k];
-}
-
-// The transform of the staged row of each group (live groups only store).
-template <typename FT, int N>
-__device__ __forceinline__ void row_transform_staged(const RepInfo& R, int pair, int j, bool live,
-                                                     int t, double2* buf, void* spec,
-                                                     const double2* tw) {
+__device__ __forceinline__ void row_transform(const RepInfo& R, double2 (&v)[8], int pair, int j,
+                                              bool live, int t, double2* buf, void* spec,
+                                              const double2* tw) {
   using ST = typename SpecOf<FT>::type;
   constexpr int S = N / 8;
-  wave_sync();
-  double2 v[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) v[q] = buf[pidx(t + S * q)];
+  wave_sync();  // the group's earlier reads of buf are done
   wave_fft<N>(v, buf, t, tw);
   // C(k) = (Z(k) + conj Z(N-k)) / 2, Rho(k) = (Z(k) - conj Z(N-k)) / (2i), k <= N/2
   wave_sync();
@@ -429,28 +403,32 @@ __device__ __forceinline__ void row_fft(const RepInfo& R, const RowTask& T, int 
   const bool live0 = g < T.nrows, live1 = G + g < T.nrows;
   const bool two = T.nrows > G;  // the whole wavefront
   const int j0 = T.j0 + (live0 ? g : 0), j1 = T.j0 + (live1 ? G + g : 0);
-  if constexpr (sizeof(FT) == 4)
-    row_stage<FT, N>(load_row_pairs<FT, N>(R, pair, j0, t, fields), t, buf);
-  else
-    row_stage_direct<N>(R, pair, j0, t, fields, buf);
+  double2 v[8];
   if constexpr (sizeof(FT) == 4) {
-    // the second half's pairs are in flight during the first half's transform
+    const RowPoints<FT> a = load_row_points<FT, N>(R, pair, j0, t, fields);
     // (loaded whether or not the task has a second half: a value loaded under
     // a condition would be kept in scratch memory)
-    const RowPairs<FT> b = load_row_pairs<FT, N>(R, pair, j1, t, fields);
-    row_transform_staged<FT, N>(R, pair, j0, live0, t, buf, spec, tw);
+    const RowPoints<FT> b = load_row_points<FT, N>(R, pair, j1, t, fields);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = make_double2(a.p[q].x, a.p[q].y);
+    row_transform<FT, N>(R, v, pair, j0, live0, t, buf, spec, tw);
     if (two) {
       // (the twiddles again through a pointer the compiler cannot identify
       // with tw: kept from the first half, they would stay in registers
       // across it)
       const double2* tw1 = tw;
       asm volatile("" : "+v"(tw1));
-      row_stage<FT, N>(b, t, buf);
-      row_transform_staged<FT, N>(R, pair, j1, live1, t, buf, spec, tw1);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = make_double2(b.p[q].x, b.p[q].y);
+      row_transform<FT, N>(R, v, pair, j1, live1, t, buf, spec, tw1);
     }
   } else {
-    // FP64 pairs: tasks of one half (a second half here costs scratch memory)
-    row_transform_staged<FT, N>(R, pair, j0, live0, t, buf, spec, tw);
+    // double pairs: tasks of one half
+    const double2* z = (const double2*)((const double*)fields + R.field_off) +
+                       (size_t)pair * R.Lz * N + (size_t)j0 * N + t;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = z[S * q];
+    row_transform<FT, N>(R, v, pair, j0, live0, t, buf, spec, tw);
   }
 }
 

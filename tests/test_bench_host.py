@@ -37,12 +37,14 @@ def profiler_dirs(tmp_path):
     def launch(name, start, dur, grid):
         return dict(Kernel_Name=name, Start_Timestamp=start, End_Timestamp=start + dur,
                     Grid_Size_X=grid)
-    # a plain step before the last sampling step (excluded), the sampling step,
-    # two plain steps at the timed grid after it (averaged), one at another grid
-    _write_csv(pt / "run_kernel_trace.csv", [
-        launch(STEP0, 100, 5000, 1024), launch(STEP1, 200, 9000, 1024),
+    # the roofline leg first: its clock-ramp and probe launches (excluded), two
+    # timed plain launches at the timed grid (averaged), one at another grid;
+    # then the sampled run: a sampling step and plain steps after it (excluded)
+    lead = [launch(STEP0, 10 + k, 5000, 1024) for k in range(bench.ROOFLINE_LEAD_STEPS)]
+    _write_csv(pt / "run_kernel_trace.csv", (lead + [
         launch(STEP0, 300, 1000, 1024), launch(STEP0, 400, 3000, 1024),
-        launch(STEP0, 500, 7000, 2048), launch(STEP0, 600, 1000, 2048)][::-1])
+        launch(STEP0, 500, 7000, 2048), launch(STEP1, 600, 9000, 1024),
+        launch(STEP0, 700, 5000, 1024), launch(STEP0, 800, 1000, 2048)])[::-1])
 
     def counter(name, kernel, value, grid=0):
         return dict(Kernel_Name=kernel, Counter_Name=name, Counter_Value=value, Grid_Size=grid)
@@ -98,10 +100,15 @@ def test_summarize_profile_of_the_two_step_kernel(tmp_path, monkeypatch):
     sampled = "void fnlb::(anonymous namespace)::k_step2<1>(fnlb::Step2Args)"
     _write_csv(pt / "run_kernel_stats.csv", [
         dict(Name=plain, Calls=3, AverageNs=2000.0, Percentage=90.0)])
-    _write_csv(pt / "run_kernel_trace.csv", [
-        dict(Kernel_Name=sampled, Start_Timestamp=0, End_Timestamp=5000, Grid_Size_X=512),
+    # the roofline leg's lead launches (half as many as its lead steps), two
+    # timed launches, then a sampling launch and a plain one after it
+    lead = [dict(Kernel_Name=plain, Start_Timestamp=k, End_Timestamp=k + 9000, Grid_Size_X=512)
+            for k in range(bench.ROOFLINE_LEAD_STEPS // 2)]
+    _write_csv(pt / "run_kernel_trace.csv", lead + [
         dict(Kernel_Name=plain, Start_Timestamp=6000, End_Timestamp=8000, Grid_Size_X=512),
-        dict(Kernel_Name=plain, Start_Timestamp=9000, End_Timestamp=13000, Grid_Size_X=512)])
+        dict(Kernel_Name=plain, Start_Timestamp=9000, End_Timestamp=13000, Grid_Size_X=512),
+        dict(Kernel_Name=sampled, Start_Timestamp=14000, End_Timestamp=19000, Grid_Size_X=512),
+        dict(Kernel_Name=plain, Start_Timestamp=20000, End_Timestamp=29000, Grid_Size_X=512)])
     _write_csv(pf / "run_counter_collection.csv", [
         dict(Kernel_Name=COPY, Counter_Name="FETCH_SIZE", Counter_Value=524288.0, Grid_Size=0),
         dict(Kernel_Name=plain, Counter_Name="FETCH_SIZE", Counter_Value=10.0, Grid_Size=512)])
