@@ -601,6 +601,14 @@ def main():
     achieved = alg_launch / t_launch / 1e9
     kernel = "k_step2" if spl == 2 else "k_step"
 
+    # the clock starts where the W warm-up steps end on a sampling-period
+    # boundary, so that the K timed steps replay whole captured periods, as a
+    # long run does, however short K is (the time only keys the noise and the
+    # sampling schedule: same steps, same samples per step)
+    t_start = (-args.warmup) % every
+    if t_start + args.warmup == 0:
+        t_start = every
+    lat.time = t_start
     lat.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
