@@ -148,9 +148,11 @@ int fnlb_init(const fnlb_replica_params* reps, int32_t n_rep,
  * the array keeps the last handle's contents, which this call overwrites
  * before use.  Work of such a handle that overlaps other use of the array on
  * the same GPU races.  The device is the current HIP device.
- * Errors: as fnlb_init; FNLB_ENOMEM also when the workspace
- * fnlb_bytes_required reports exceeds FNLB_STATIC_WORK_BYTES; FNLB_ESTATE as
- * above. */
+ * Such a handle keeps the row spectra of fewer samples per column pass than
+ * fnlb_init's (the workspace fnlb_bytes_required reports holds 16; here as
+ * many as fit, down to one); its results are the same.
+ * Errors: as fnlb_init; FNLB_ENOMEM also when even a workspace of one
+ * sample's spectra exceeds FNLB_STATIC_WORK_BYTES; FNLB_ESTATE as above. */
 #define FNLB_STATIC_WORK_BYTES (128u << 20)
 int fnlb_init_static_work(const fnlb_replica_params* reps, int32_t n_rep,
                           const fnlb_options* options, void* d_state,
