@@ -37,7 +37,8 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("every,prec,two", [(5, 0, 0), (4, 1, 0), (0, 0, 0), (7, 1, 0),
-                                            (4, 1, 1), (7, 1, 1), (0, 1, 1)])
+                                            (4, 1, 1), (7, 1, 1), (0, 1, 1), (1, 1, 1),
+                                            (2, 0, 0)])
 def test_graph_replay_matches_direct_launches(F, every, prec, two):
     # block transforms for the first two, wavefront transforms for the third;
     # the step counts leave samples of a call in the spectrum slots of the
