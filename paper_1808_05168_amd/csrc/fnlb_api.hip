@@ -118,7 +118,7 @@ struct Plan {
   size_t item_capacity = 0;  // items the work buffer holds (row ranges of one row)
   int max_lx = 0, max_lz = 0, max_col_lds = 0, max_row_lds = 0, chunk = 0;
   int n_pairs = 1;  // complex row transforms per row: (dc, drho) [, (Ux, Uz)]
-  // samples whose row spectra and pressure row sums are kept before one column
+  // samples whose row spectra and pressure parts are kept before one column
   // pass adds them all (slots of spec_slot complex pairs of the storage type
   // and ppart_slot doubles)
   int spec_slots = 1;

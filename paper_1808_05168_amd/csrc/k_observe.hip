@@ -205,7 +205,7 @@ __device__ void pressure_reduce(const RepInfo& R, const double* ppart, double* a
 
 // Column pass: one block per (replica, field, tile of 2^ltile k_x columns).
 // The block of the first tile of the first field also reduces the replica's
-// pressure (the row pass has written all row sums).
+// pressure of every sample (from the parts the sampling step wrote).
 // LDS: the tile's columns, then (power-of-two columns) the M/2 twiddles.
 template <typename ST>
 __global__ __launch_bounds__(256) void k_col_transform(const RepInfo* reps, const ColRef* cols,
