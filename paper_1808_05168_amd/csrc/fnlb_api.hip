@@ -1420,11 +1420,11 @@ int adj_plan(const fnlb_handle* h, int64_t horizon, int32_t K, AdjPlan& A) {
     o = align_up(o + bytes);
   };
   take(A.ckpt, (size_t)A.nck * SH);
-  take(A.seg, (size_t)K * SH);
+  take(A.seg, ((size_t)K + 1) * SH);  // a segment's states (and the one after it)
   take(A.mu, 2 * SH);
   take(A.gf, 18 * N * 8);
   take(A.gs, 4 * N * 8);
-  take(A.dens, 2 * N * 8);
+  take(A.dens, (size_t)K * 2 * N * 8);  // the pulled densities of a segment's states
   take(A.adjf, 2 * N * 8);  // sample term: one field, or the two pressure adjoints
   take(A.acc, h->plan.accum_bytes);
   take(A.target, P * 8);
@@ -1481,15 +1481,20 @@ struct AdjCtx {
   }
   char* ckpt(int64_t k) const { return W + A.ckpt + (size_t)k * SH; }
   char* seg(int64_t k) const { return W + A.seg + (size_t)k * SH; }
+  // the pulled densities [2][Lz][Lx] of state k of a segment
+  double* dens(int64_t k) const { return (double*)(W + A.dens) + (size_t)k * 2 * N; }
   bool sampled(int64_t t) const { return every > 0 && t >= 1 && t % every == 0; }
   // The step of a sample time runs the sampling variant of the step kernel
   // both in the forward sweep and when a segment is recomputed, so that every
   // recomputed state is bit-identical to the forward one whatever the
   // checkpoint interval (the two kernel variants may round differently).
-  hipError_t step_from(const char* in, char* out, int64_t t, bool observe_sample) const {
+  // (dens: where the step writes the pulled densities of `in`, or null)
+  hipError_t step_from(const char* in, char* out, int64_t t, bool observe_sample,
+                       double* dens = nullptr) const {
     StepArgs a = step_args(h, t - h->t_dev);
     a.state_in = in;
     a.state_out = out;
+    a.dens = dens;
     hipError_t e = launch_step(FNLB_FP64, sampled(t) ? kStepSample : kStep, a, s);
     if (e == hipSuccess && observe_sample && sampled(t)) e = observe(h, s, acc);
     return e;
@@ -1593,28 +1598,31 @@ int misfit_reverse(fnlb_handle* h, void* d_adj, size_t adj_bytes, double* grad) 
   int nx = 0;  // mu[nx] holds dJ/dS_{t+1}
   for (int64_t sgi = A.nck - 1; sgi >= 0 && e == hipSuccess; --sgi) {
     const int64_t ts = sgi * K, te = std::min<int64_t>(horizon, ts + K);
+    // the segment's states recomputed from its checkpoint, each step also
+    // writing the pulled densities of its input state (the last state's too,
+    // by one step past the segment, whose output is not used)
     e = hipMemcpyAsync(C.seg(0), C.ckpt(sgi), C.SH, hipMemcpyDeviceToDevice, s);
-    for (int64_t k = ts; k + 1 < te && e == hipSuccess; ++k)
-      e = C.step_from(C.seg(k - ts), C.seg(k - ts + 1), t0 + k, false);
+    for (int64_t k = ts; k < te && e == hipSuccess; ++k)
+      e = C.step_from(C.seg(k - ts), C.seg(k - ts + 1), t0 + k, false, C.dens(k - ts));
     for (int64_t k = te - 1; k >= ts && e == hipSuccess; --k) {
       const double* S = (const double*)C.seg(k - ts);
-      e = launch_adj_density(C.dR, *C.R, S, (double*)(W + A.dens), s);
+      double* dens = C.dens(k - ts);
       const double* adjf = nullptr;
       if (e == hipSuccess && C.sampled(t0 + k)) {
         if (pressure)
-          e = launch_adj_psample(C.dR, *C.R, (const double*)(W + A.dens),
+          e = launch_adj_psample(C.dR, *C.R, dens,
                                  (const double*)(W + A.Wq), (double*)(W + A.adjf),
                                  (double*)(W + A.tpart), s);
         else
           e = launch_adj_sample(C.dR, *C.R, h->d_tw(), (const double*)(W + A.Wq),
                                 (const double2*)(W + A.mean), field, ns,
-                                (const double*)(W + A.dens), (double2*)(W + A.rows),
+                                dens, (double2*)(W + A.rows),
                                 (double2*)(W + A.Gq), (double*)(W + A.adjf), s);
         adjf = (const double*)(W + A.adjf);
       }
       if (e == hipSuccess)
         e = launch_adj_step(C.dR, *C.R, S, (const double*)C.mu[nx], (double*)C.mu[nx ^ 1],
-                            (double*)(W + A.dens), (double*)(W + A.gf), (double*)(W + A.gs),
+                            dens, (double*)(W + A.gf), (double*)(W + A.gs),
                             adjf, pressure ? kAdjPressure : field, t0 + k,
                             (double*)(W + A.tpart), s);
       nx ^= 1;

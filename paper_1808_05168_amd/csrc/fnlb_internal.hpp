@@ -143,6 +143,9 @@ struct StepArgs {
   void* fields;           // sample (float for FP32-deviation storage, else double)
   double* ppart;          // its pressure sums, [Lz][pressure_parts(Lx)] per replica
   int32_t* watchdog;      // set non-zero when a sample sees a bad state
+  // FP64, one replica, or null: the full densities of the pulled input state,
+  // [species][Lz][Lx] (what the adjoint of the step reads)
+  double* dens;
 };
 
 // Launchers (asynchronous on `stream`).

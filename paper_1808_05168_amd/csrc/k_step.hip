@@ -300,6 +300,16 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     const double rAj = rA0 + rAs * j;
     const double szref = rAs * (double)(jU - jD) * (1.0 / 6.0);  // species A
 
+    // the full densities of this row's pulled state, on request (FP64: the
+    // adjoint's recompute of a segment), from the sums the ring holds
+    if constexpr (sizeof(Real) == 8) {
+      if (a.dens && act) {
+        const int64_t n = (int64_t)j * Lx + x;
+        a.dens[n] = rAj + (double)ring[j & 3][0][c];
+        a.dens[(int64_t)Lx * Lz + n] = (rho0 - rAj) + (double)ring[j & 3][1][c];
+      }
+    }
+
     // sample of f(t) (sampling modes), formed from the stencil the collision
     // reads (the arithmetic shares nothing with the collision) and stored
     // before it, which keeps the sample out of the collision's registers
