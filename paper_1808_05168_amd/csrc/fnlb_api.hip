@@ -965,7 +965,11 @@ int fnlb_autotune(fnlb_handle* h, int32_t steps_per_trial, int32_t* chunk_rows_o
   Plan& P = h->plan;
   int max_lz = 0;
   for (const RepInfo& R : P.info) max_lz = std::max(max_lz, R.Lz);
-  // candidates: (two-step kernel?, rows per work item)
+  // candidates: (two-step kernel?, rows per work item).  Lengths above twice
+  // the tallest lattice are left out: every replica then gets whole-lattice
+  // items, the plan a shorter length already gives.  One length per kernel is
+  // kept whatever the lattice (4 and 8), so that a short lattice still gives
+  // each kernel a candidate (the two-step list starts at 8).
   struct Cand {
     bool two;
     int rows;
