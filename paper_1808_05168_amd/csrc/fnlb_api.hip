@@ -480,6 +480,7 @@ struct fnlb_handle {
     int64_t horizon = 0, t0 = 0, nsamp = 0;
     int32_t K = 0, field = 0;
     bool pressure = false;
+    bool last_seg_kept = false;  // the segment buffers hold the last segment's states
   } adj;
 
   RepInfo* d_reps() { return (RepInfo*)(work + plan.o_reps); }
@@ -1492,16 +1493,15 @@ struct AdjCtx {
   // both in the forward sweep and when a segment is recomputed, so that every
   // recomputed state is bit-identical to the forward one whatever the
   // checkpoint interval (the two kernel variants may round differently).
-  // (dens: where the step writes the pulled densities of `in`, or null)
-  hipError_t step_from(const char* in, char* out, int64_t t, bool observe_sample,
-                       double* dens = nullptr) const {
-    StepArgs a = step_args(h, t - h->t_dev);
+  // (dens: where the step writes the pulled densities of `in`, or null;
+  // slot: the spectrum slot of a sample's pressure parts)
+  hipError_t step_from(const char* in, char* out, int64_t t, double* dens = nullptr,
+                       int slot = 0) const {
+    StepArgs a = step_args(h, t - h->t_dev, slot);
     a.state_in = in;
     a.state_out = out;
     a.dens = dens;
-    hipError_t e = launch_step(FNLB_FP64, sampled(t) ? kStepSample : kStep, a, s);
-    if (e == hipSuccess && observe_sample && sampled(t)) e = observe(h, s, acc);
-    return e;
+    return launch_step(FNLB_FP64, sampled(t) ? kStepSample : kStep, a, s);
   }
 };
 
@@ -1535,14 +1535,41 @@ int misfit_forward(fnlb_handle* h, bool pressure, int32_t field, const double* t
   if (e == hipSuccess) e = launch_fill_zero(W + A.small, 64, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(C.mu[0], h->state_copy(h->cur), C.SH, hipMemcpyDeviceToDevice, s);
+  // The states alternate between two buffers; the last segment's states, and
+  // the pulled densities of each, go straight to the segment buffers, where
+  // the reverse sweep, which differentiates that segment first, finds them
+  // without recomputing it.  The samples keep their row spectra in the
+  // spectrum slots and one column pass adds up to kSpecSlots of them into the
+  // private sums, in time order.
+  const int64_t last_ts = (A.nck - 1) * (int64_t)K;
+  const int slots = h->plan.spec_slots;
   int64_t nsamp = 0;
-  int cur = 0;
+  int cur = 0, pend = 0;
   for (int64_t k = 0; k < horizon && e == hipSuccess; ++k) {
+    const char* in = C.mu[cur];
+    char* out = C.mu[cur ^ 1];
+    double* dens = nullptr;
     if (k % K == 0) e = hipMemcpyAsync(C.ckpt(k / K), C.mu[cur], C.SH, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = C.step_from(C.mu[cur], C.mu[cur ^ 1], t0 + k, true);
-    if (C.sampled(t0 + k)) ++nsamp;
+    if (k >= last_ts) {
+      if (k == last_ts && e == hipSuccess)
+        e = hipMemcpyAsync(C.seg(0), C.mu[cur], C.SH, hipMemcpyDeviceToDevice, s);
+      in = C.seg(k - last_ts);
+      out = C.seg(k - last_ts + 1);
+      dens = C.dens(k - last_ts);
+    }
+    const bool smp = C.sampled(t0 + k);
+    if (e == hipSuccess) e = C.step_from(in, out, t0 + k, dens, smp ? pend : 0);
+    if (smp) {
+      if (e == hipSuccess) e = observe_rows(h, s, pend);
+      if (++pend == slots && e == hipSuccess) {
+        e = observe_cols(h, s, pend, C.acc);
+        pend = 0;
+      }
+      ++nsamp;
+    }
     cur ^= 1;
   }
+  if (pend > 0 && e == hipSuccess) e = observe_cols(h, s, pend, C.acc);
   if (nsamp == 0) return e == hipSuccess ? FNLB_EINVAL : dev_err(h, e);
   const double ns = (double)nsamp;
   if (pressure) {
@@ -1572,6 +1599,7 @@ int misfit_forward(fnlb_handle* h, bool pressure, int32_t field, const double* t
   h->adj.K = K;
   h->adj.field = field;
   h->adj.pressure = pressure;
+  h->adj.last_seg_kept = true;
   return FNLB_OK;
 }
 
@@ -1604,10 +1632,15 @@ int misfit_reverse(fnlb_handle* h, void* d_adj, size_t adj_bytes, double* grad) 
     const int64_t ts = sgi * K, te = std::min<int64_t>(horizon, ts + K);
     // the segment's states recomputed from its checkpoint, each step also
     // writing the pulled densities of its input state (the last state's too,
-    // by one step past the segment, whose output is not used)
-    e = hipMemcpyAsync(C.seg(0), C.ckpt(sgi), C.SH, hipMemcpyDeviceToDevice, s);
-    for (int64_t k = ts; k < te && e == hipSuccess; ++k)
-      e = C.step_from(C.seg(k - ts), C.seg(k - ts + 1), t0 + k, false, C.dens(k - ts));
+    // by one step past the segment, whose output is not used); the forward
+    // sweep left the last segment's in place, until a reverse sweep recomputes
+    // another segment there
+    if (sgi != A.nck - 1 || !h->adj.last_seg_kept) {
+      if (sgi != A.nck - 1) h->adj.last_seg_kept = false;
+      e = hipMemcpyAsync(C.seg(0), C.ckpt(sgi), C.SH, hipMemcpyDeviceToDevice, s);
+      for (int64_t k = ts; k < te && e == hipSuccess; ++k)
+        e = C.step_from(C.seg(k - ts), C.seg(k - ts + 1), t0 + k, C.dens(k - ts));
+    }
     for (int64_t k = te - 1; k >= ts && e == hipSuccess; --k) {
       const double* S = (const double*)C.seg(k - ts);
       double* dens = C.dens(k - ts);
@@ -1718,6 +1751,8 @@ int fnlb_step_vjp(fnlb_handle* h, const double* mu_next, double* mu, double* dth
   if (adj_bytes < A.total) return FNLB_ENOMEM;
   if ((uintptr_t)d_adj % kAlign) return FNLB_EINVAL;
   const AdjCtx C(h, A, d_adj);
+  // this call's layout of the workspace differs from a misfit sweep's
+  h->adj.valid = false;
   const RepInfo& R = *C.R;
   const size_t nel = 18 * (size_t)R.plane;  // stored elements of the replica
   std::vector<double> st(nel, 0.0);
