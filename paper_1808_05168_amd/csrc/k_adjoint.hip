@@ -369,7 +369,22 @@ __global__ void k_adj_gather(const AdjArgs a) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= N) return;
   const int j = r / Lx, x = r - j * Lx;
+  // the stencil adjoints of the eight nodes that read this one, all requested
+  // before any is used (a row beyond a wall reads this node's row instead,
+  // and its term is skipped below)
+  double g[8][4];
+#pragma unroll
+  for (int m = 1; m < 9; ++m) {
+    const int cx = kCXa[m], cz = kCZa[m];
+    int xn = x - cx;
+    xn = xn < 0 ? xn + Lx : (xn >= Lx ? xn - Lx : xn);
+    const int jn = j - cz;
+    const int k = (jn >= 0 && jn < Lz ? jn : j) * Lx + xn;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) g[m - 1][c] = a.gs[c * (size_t)N + k];
+  }
   double D[2] = {0, 0};
+#pragma unroll
   for (int m = 1; m < 9; ++m) {
     const int cx = kCXa[m], cz = kCZa[m];
     int xn = x - cx;
@@ -377,10 +392,8 @@ __global__ void k_adj_gather(const AdjArgs a) {
     // regular: node (x - c_x, j - c_z) reads this node through link m
     const int jn = j - cz;
     if (jn >= 0 && jn < Lz) {
-      const int k = jn * Lx + xn;
       for (int sp = 0; sp < 2; ++sp)
-        D[sp] += kWa[m] * (cx * a.gs[(2 * sp) * (size_t)N + k] +
-                           cz * a.gs[(2 * sp + 1) * (size_t)N + k]);
+        D[sp] += kWa[m] * (cx * g[m - 1][2 * sp] + cz * g[m - 1][2 * sp + 1]);
     }
     // ghost: a wall-row node whose link m leaves the fluid reads the wall row
     if ((j == 0 && cz == -1) || (j == Lz - 1 && cz == 1)) {
@@ -841,8 +854,12 @@ hipError_t launch_adj_sample(const RepInfo* d_rep, const RepInfo& h_rep, const d
   const int P = h_rep.Lz * (h_rep.Lx / 2 + 1), N = h_rep.Lx * h_rep.Lz;
   if (h_rep.pow2) {
     const int Lx = h_rep.Lx, Lz = h_rep.Lz, nkx = Lx / 2 + 1;
-    int lt = 0;  // column tiles of 2^lt: at most 16 columns and 2048 values
-    while (lt < 4 && (2 << lt) * Lz <= 2048) ++lt;
+    // column tiles of 2^lt: at most 16 columns and 2048 values, and wider
+    // only while at least 128 tiles remain (one sample of a small lattice
+    // is latency-bound: blocks matter more than full ones)
+    int lt = 0;
+    while (lt < 4 && (2 << lt) * Lz <= 2048 && ((nkx + (2 << lt) - 1) >> (lt + 1)) >= 128)
+      ++lt;
     const unsigned ntile = (unsigned)((nkx + (1 << lt) - 1) >> lt);
     const size_t row_lds = (size_t)(Lx + Lx / 2) * sizeof(double2);
     const size_t col_lds = (size_t)(((size_t)Lz << lt) + Lz / 2) * sizeof(double2);
