@@ -171,7 +171,8 @@ int fnlb_init_static_work(const fnlb_replica_params* reps, int32_t n_rep,
  * steps without sampling) that start on a period boundary are replayed from
  * HIP graphs captured by fnlb_init or fnlb_autotune (periods longer than 1024
  * steps: on first use; none with FNLB_NO_GRAPH): one of up to 16 periods while
- * that many remain (within 1024 steps), else one of a single period.  In a
+ * that many remain (within 1024 steps), else one of two periods, else one of a
+ * single period.  In a
  * graph the transforms of each sample run on a branch of their own beside the
  * steps that follow it, joined before the next sample.  The row transforms of
  * up to 16 samples are kept and their column transforms done in one pass,

@@ -459,14 +459,16 @@ struct fnlb_handle {
   int64_t nsamples = 0;
   int error = FNLB_OK;   // sticky error
   // sampling periods captured as graphs, per parity of the starting copy:
-  // graph[0] holds one period; graph[1], when sampling, kgraph periods whose
-  // samples fill the spectrum slots in turn and share one column pass at the
-  // end.  In them the transforms of each sample run on a branch of their own
-  // (captured from obs_stream) beside the plain steps that follow.
+  // graph[0] holds one period; when sampling, graph[1] holds kgraph periods
+  // and graph[2] two, whose samples fill the spectrum slots in turn and share
+  // one column pass at the end (a column pass reads and writes every FP64 sum
+  // once, whatever number of samples it adds).  In them the transforms of
+  // each sample run on a branch of their own (captured from obs_stream)
+  // beside the plain steps that follow.
   hipStream_t cap_stream = nullptr, obs_stream = nullptr;
   hipEvent_t ev_fork[kSpecSlots] = {}, ev_join[kSpecSlots] = {};
-  hipGraphExec_t graph[2][2] = {};  // [kind][parity]
-  int graph_launches[2] = {};       // kernel launches of the state in each kind
+  hipGraphExec_t graph[3][2] = {};  // [kind][parity]
+  int graph_launches[3] = {};       // kernel launches of the state in each kind
   int kgraph = 0;                   // periods of graph[1] (0: no such graph)
   int pending = 0;  // samples in the spectrum slots that no column pass has added yet
   int64_t period = 0;
@@ -620,8 +622,23 @@ void drop_graphs(fnlb_handle* h) {
       }
 }
 
-// periods in a graph of kind `which` (0: one, 1: kgraph)
-int graph_periods(const fnlb_handle* h, int which) { return which ? h->kgraph : 1; }
+// periods in a graph of kind `which` (0: one, 1: kgraph, 2: two)
+int graph_periods(const fnlb_handle* h, int which) {
+  return which == 0 ? 1 : which == 1 ? h->kgraph : 2;
+}
+
+// the kinds of graph a handle captures: one period; kgraph periods when kgraph
+// > 1; two periods when kgraph > 2
+bool graph_kind_used(const fnlb_handle* h, int which) {
+  return which == 0 || (which == 1 && h->kgraph > 1) || (which == 2 && h->kgraph > 2);
+}
+
+// The graph for n steps from a period start: the most periods that n holds.
+int graph_kind_for(const fnlb_handle* h, int64_t n) {
+  if (graph_kind_used(h, 1) && n >= h->kgraph * h->period) return 1;
+  if (graph_kind_used(h, 2) && n >= 2 * h->period) return 2;
+  return 0;
+}
 
 // Captures `graph_periods(which)` periods of `period` steps starting at a
 // period start, from state copy `parity`: the first step of each period
@@ -710,8 +727,8 @@ constexpr int64_t kPrecapturePeriod = 1024;
 hipError_t prepare_graphs(fnlb_handle* h) {
   if ((h->opt.flags & FNLB_NO_GRAPH) || h->period > kPrecapturePeriod) return hipSuccess;
   hipError_t e = hipSuccess;
-  for (int which = 0; which < (h->kgraph > 1 ? 2 : 1); ++which)
-    for (int parity = 0; parity < 2 && e == hipSuccess; ++parity)
+  for (int which = 0; which < 3; ++which)
+    for (int parity = 0; parity < 2 && e == hipSuccess && graph_kind_used(h, which); ++parity)
       if (!h->graph[which][parity]) e = capture_periods(h, which, parity);
   return e;
 }
@@ -929,9 +946,9 @@ int fnlb_step(fnlb_handle* h, int64_t n) {
   while (n > 0) {
     const int64_t t = h->t;
     // whole sampling periods from a period start replay a captured graph:
-    // kgraph periods at once while that many remain, else one
+    // kgraph periods at once while that many remain, else two, else one
     if (use_graph && n >= h->period && t % h->period == 0 && (every == 0 || t >= 1)) {
-      const int which = h->kgraph > 1 && n >= h->kgraph * h->period ? 1 : 0;
+      const int which = graph_kind_for(h, n);
       // the graphs fill the slots from the first
       const hipError_t fe = flush_samples(h);
       if (fe != hipSuccess) return dev_err(h, fe);
