@@ -671,8 +671,21 @@ hipError_t capture_periods(fnlb_handle* h, int which, int parity) {
   const int saved = h->cur;
   h->cur = parity;
   hipError_t le = hipSuccess;
-  int joins = -1;  // the branch that has yet to join (-1: none)
+  int joins = -1;   // the branch that has yet to join (-1: none)
+  int forked = -1;  // the sample whose branch has yet to be issued (-1: none)
   int launches = 0;
+  // the transforms of the sample of period p, on the side stream from the
+  // fork event recorded after its sampling step
+  auto branch = [&](int p) {
+    le = hipStreamWaitEvent(h->obs_stream, h->ev_fork[p], 0);
+    if (le != hipSuccess) return;
+    joins = p;
+    le = observe_rows(h, h->obs_stream, p);
+    if (le == hipSuccess && p == nper - 1) le = observe_cols(h, h->obs_stream, nper);
+    // recorded even after a failed launch, so that the branch can join
+    const hipError_t re = hipEventRecord(h->ev_join[p], h->obs_stream);
+    if (le == hipSuccess) le = re;
+  };
   for (int64_t k = 0; k < len && le == hipSuccess;) {
     const int per = (int)(k / h->period);
     // each period starts at a sample time and holds no other
@@ -685,16 +698,21 @@ hipError_t capture_periods(fnlb_handle* h, int which, int parity) {
     const int took = launch_state(h, k, pair_at(h, k, len - k), smp, per, s, le);
     k += took > 0 ? took : 1;
     ++launches;
+    if (le == hipSuccess && forked >= 0) {
+      branch(forked);
+      forked = -1;
+    }
     if (le == hipSuccess && smp) {
       le = hipEventRecord(h->ev_fork[per], s);
-      if (le == hipSuccess) le = hipStreamWaitEvent(h->obs_stream, h->ev_fork[per], 0);
+      // The branch is issued after the step that follows, when that step does
+      // not sample: the runtime then keeps the chain of steps, the sampling
+      // step's first successor, on one hardware queue, and the transforms
+      // start beside a step that already holds the compute units.
       if (le == hipSuccess) {
-        joins = per;
-        le = observe_rows(h, h->obs_stream, per);
-        if (le == hipSuccess && per == nper - 1) le = observe_cols(h, h->obs_stream, nper);
-        // recorded even after a failed launch, so that the branch can join
-        const hipError_t re = hipEventRecord(h->ev_join[per], h->obs_stream);
-        if (le == hipSuccess) le = re;
+        if (k < len && k % h->period != 0)
+          forked = per;
+        else
+          branch(per);
       }
     }
     h->cur ^= 1;
