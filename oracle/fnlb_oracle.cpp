@@ -133,16 +133,26 @@ void philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
 }
 
 // The 14 standard normal variates used at one node and one time step.
-// Counter = (node, t_lo, t_hi, call), call = 0..3; key = (seed_lo, seed_hi).
-// Word k of the 16 gives u_k = (w_k + 1/2) 2^-32 in (0,1); Box-Muller (Box and
-// Muller 1958) maps the pair (u_2i, u_2i+1) to g_2i, g_2i+1 for i = 0..6.
+// 14 words per step: calls 0..2 with counter (node, t_lo, t_hi, call) give
+// words 0..11; call 3 is shared by the two steps 2s and 2s + 1 (counter
+// (node, 2s, 3)): step 2s takes its words 0 and 1, step 2s + 1 its words 2
+// and 3, as words 12 and 13.  Key = (seed_lo, seed_hi).  Word k gives
+// u_k = (w_k + 1/2) 2^-32 in (0,1); Box-Muller (Box and Muller 1958) maps the
+// pair (u_2i, u_2i+1) to g_2i, g_2i+1 for i = 0..6.
 void node_gaussians(uint64_t seed, uint32_t node, uint64_t t, double g[14]) {
-  uint32_t words[16];
+  uint32_t words[14];
   const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-  for (uint32_t call = 0; call < 4; ++call) {
+  for (uint32_t call = 0; call < 3; ++call) {
     const uint32_t ctr[4] = {node, (uint32_t)t, (uint32_t)(t >> 32), call};
     philox4x32_10(ctr, key, words + 4 * call);
   }
+  const uint64_t ts = t & ~(uint64_t)1;
+  const uint32_t ctr3[4] = {node, (uint32_t)ts, (uint32_t)(ts >> 32), 3u};
+  uint32_t shared[4];
+  philox4x32_10(ctr3, key, shared);
+  const int h = (int)(t & 1) * 2;
+  words[12] = shared[h];
+  words[13] = shared[h + 1];
   const double two_pi = 6.283185307179586476925286766559;
   for (int i = 0; i < 7; ++i) {
     const double u1 = ((double)words[2 * i] + 0.5) * 2.3283064365386962890625e-10;

@@ -132,15 +132,15 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& g0, 
 }
 
 // Words 4 call .. 4 call + 3 of one node and one step: counter
-// (node, t_lo, t_hi, call), key (seed_lo, seed_hi).  A node uses calls 0..3.
+// (node, t_lo, t_hi, call), key (seed_lo, seed_hi).  A step takes calls 0..2
+// of its own and half of call 3 of the even step of its pair (shared_words).
 __device__ __forceinline__ Philox4 node_call(uint32_t node, uint64_t t, uint32_t call,
                                              uint32_t k0, uint32_t k1) {
   return philox4x32_10(node, (uint32_t)t, (uint32_t)(t >> 32), call, k0, k1);
 }
 
 // The standard normals g_{4c}, ..., g_{4c+3} (Box-Muller on the word pairs of
-// call c); g_14 and g_15 of call 3 are not used by the step.  tab: the FP64
-// Box-Muller tables (unused by the FP32 form).
+// call c, c = 0..2).  tab: the FP64 Box-Muller tables (unused by the FP32 form).
 template <typename Real>
 __device__ __forceinline__ void node_normals(uint32_t node, uint64_t t, uint32_t call,
                                              uint32_t k0, uint32_t k1, Real (&g)[4],
@@ -148,6 +148,21 @@ __device__ __forceinline__ void node_normals(uint32_t node, uint64_t t, uint32_t
   const Philox4 r = node_call(node, t, call, k0, k1);
   box_muller(r.v[0], r.v[1], g[0], g[1], tab);
   box_muller(r.v[2], r.v[3], g[2], g[3], tab);
+}
+
+// Call 3 is shared by the steps 2s and 2s + 1 (counter (node, 2s, 3)): its
+// words 0 and 1 are words 12 and 13 of step 2s, its words 2 and 3 those of
+// step 2s + 1, so that two steps draw seven calls.  This step's two words in
+// (w12, w13), the other step's in (o12, o13).
+__device__ __forceinline__ void shared_words(uint32_t node, uint64_t t, uint32_t k0, uint32_t k1,
+                                             uint32_t& w12, uint32_t& w13, uint32_t& o12,
+                                             uint32_t& o13) {
+  const Philox4 r = node_call(node, t & ~(uint64_t)1, 3u, k0, k1);
+  const bool odd = (t & 1) != 0;
+  w12 = odd ? r.v[2] : r.v[0];
+  w13 = odd ? r.v[3] : r.v[1];
+  o12 = odd ? r.v[0] : r.v[2];
+  o13 = odd ? r.v[1] : r.v[3];
 }
 
 // Deterministic sum over the 64 lanes of a wavefront (fixed butterfly order);

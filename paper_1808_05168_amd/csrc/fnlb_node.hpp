@@ -59,15 +59,30 @@ struct NodePhys {
 };
 
 // The 14 standard normals of a node at time t: species A uses g_0..g_7 from
-// Philox calls 0 and 1, species B g_8..g_13 from calls 2 and 3.
+// Philox calls 0 and 1, species B g_8..g_11 from call 2 and g_12, g_13 from
+// the words (w12, w13) of the call that steps 2s and 2s + 1 share (gB1[2] and
+// gB1[3] are not used).
+template <typename Real>
+__device__ __forceinline__ void node_noise_words(uint32_t node, uint64_t t, uint32_t k0,
+                                                 uint32_t k1, const BmTables* bmt,
+                                                 uint32_t w12, uint32_t w13, Real (&gA0)[4],
+                                                 Real (&gA1)[4], Real (&gB0)[4],
+                                                 Real (&gB1)[4]) {
+  node_normals(node, t, 2u, k0, k1, gB0, bmt);
+  box_muller(w12, w13, gB1[0], gB1[1], bmt);
+  gB1[2] = gB1[3] = (Real)0;
+  node_normals(node, t, 0u, k0, k1, gA0, bmt);
+  node_normals(node, t, 1u, k0, k1, gA1, bmt);
+}
+
+// The same, drawing the shared call itself.
 template <typename Real>
 __device__ __forceinline__ void node_noise(uint32_t node, uint64_t t, uint32_t k0, uint32_t k1,
                                            const BmTables* bmt, Real (&gA0)[4], Real (&gA1)[4],
                                            Real (&gB0)[4], Real (&gB1)[4]) {
-  node_normals(node, t, 2u, k0, k1, gB0, bmt);
-  node_normals(node, t, 3u, k0, k1, gB1, bmt);
-  node_normals(node, t, 0u, k0, k1, gA0, bmt);
-  node_normals(node, t, 1u, k0, k1, gA1, bmt);
+  uint32_t w12, w13, o12, o13;
+  shared_words(node, t, k0, k1, w12, w13, o12, o13);
+  node_noise_words(node, t, k0, k1, bmt, w12, w13, gA0, gA1, gB0, gB1);
 }
 
 // ---- The sample of one node, formed by the sampling step from the values

@@ -194,14 +194,22 @@ __global__ __launch_bounds__(256) void k_adj_local(const AdjArgs a) {
     // one call at a time (not unrolled): the table-driven FP64 Box-Muller of
     // four calls interleaved would raise the register pressure of this kernel
 #pragma unroll 1
-    for (uint32_t call = 0; call < 4; ++call) {
+    for (uint32_t call = 0; call < 3; ++call) {
       double q4[4];
       node_normals(node, (uint64_t)a.t, call, R.seed_lo, R.seed_hi, q4, R.bm);
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
           if (c == (int)call) g[4 * c + i] = q4[i];
+    }
+    {
+      // g_12, g_13: this step's half of the call shared with the other step
+      // of its pair
+      uint32_t w12, w13, o12, o13;
+      shared_words(node, (uint64_t)a.t, R.seed_lo, R.seed_hi, w12, w13, o12, o13);
+      box_muller(w12, w13, g[12], g[13], R.bm);
+      g[14] = g[15] = 0.0;
     }
     // gaussian index of moment a for species A / B (a = 3..8); a = 1,2 use g0, g1
     const int gA[9] = {0, 0, 1, 2, 3, 4, 5, 6, 7};

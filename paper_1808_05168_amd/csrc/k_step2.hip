@@ -170,20 +170,33 @@ __global__ __launch_bounds__(kTBLanes) void k_step2(const Step2Args a) {
     if (needed(afirst + dir)) load_pulled(in, link_b, row_b, afirst + dir, Lz, xb, xmb, xpb, nxt);
   }
 
+  // With t even the two steps share one noise call per node (words 12 and 13
+  // of both steps): stage A draws it and keeps the second step's two words,
+  // which its second step uses two rows (two iterations) later.
+  const bool odd_t = (t & 1) != 0;
+  uint32_t cw_even[2] = {0u, 0u}, cw_odd[2] = {0u, 0u};
+
   // One row of each stage.  cur: the pulled row ar of t, nxt: the row ahead;
   // hp: the populations of t + 1 of the row whose second step runs now, hn:
-  // receives those of the row behind.  The loop runs two iterations per trip
-  // with the register sets swapped in the second, so that no set is copied.
+  // receives those of the row behind; cw: the kept words of the row whose
+  // second step runs now, replaced by those of row ar.  The loop runs two
+  // iterations per trip with the register sets swapped in the second, so that
+  // no set is copied.
   auto iteration = [&](int i, Store(&cur)[18], Store(&nxt)[18], Store(&hp)[18],
-                       Store(&hn)[18]) {
+                       Store(&hn)[18], uint32_t(&cw)[2]) {
     const int ar = afirst + dir * i;  // row of the first step
     const bool doA = sub_ok && a_row(ar);
     const bool topA = ar == Lz - 1, botA = ar == 0;
 
     // ---- stage A, before the barrier: noise, densities of the row ahead
     Real gA0[4], gA1[4], gB0[4], gB1[4];
-    if (doA && wave_act)
-      node_noise((uint32_t)(ar * Lx + x), (uint64_t)t, k0, k1, bmt, gA0, gA1, gB0, gB1);
+    uint32_t nw12 = 0u, nw13 = 0u;  // words 12, 13 of step t + 1 at (ar, x), t even
+    if (doA && wave_act) {
+      const uint32_t node = (uint32_t)(ar * Lx + x);
+      uint32_t w12, w13;
+      shared_words(node, (uint64_t)t, k0, k1, w12, w13, nw12, nw13);
+      node_noise_words(node, (uint64_t)t, k0, k1, bmt, w12, w13, gA0, gA1, gB0, gB1);
+    }
     if (doA && needed(ar + dir)) put_raw(ar + dir, nxt);
     // the sample constants of row ar, read before the barrier, which waits
     // for them
@@ -307,9 +320,17 @@ __global__ __launch_bounds__(kTBLanes) void k_step2(const Step2Args a) {
     const int br = ar - 2 * dir;
     const bool doB = sub_ok && wave_act && br >= j0 && br < j1;
     Real gA0b[4], gA1b[4], gB0b[4], gB1b[4];
-    if (doB)
-      node_noise((uint32_t)(br * Lx + x), (uint64_t)(t + 1), k0, k1, bmt, gA0b, gA1b, gB0b,
-                 gB1b);
+    if (doB) {
+      const uint32_t node = (uint32_t)(br * Lx + x);
+      uint32_t w12 = cw[0], w13 = cw[1];
+      if (odd_t) {  // t + 1 even: its shared call is its own
+        uint32_t o12, o13;
+        shared_words(node, (uint64_t)(t + 1), k0, k1, w12, w13, o12, o13);
+      }
+      node_noise_words(node, (uint64_t)(t + 1), k0, k1, bmt, w12, w13, gA0b, gA1b, gB0b, gB1b);
+    }
+    cw[0] = nw12;
+    cw[1] = nw13;
     if (doD) {
       DT da, db;
       density18(hn, da, db);
@@ -367,8 +388,8 @@ __global__ __launch_bounds__(kTBLanes) void k_step2(const Step2Args a) {
   };
   // the host rounds niter up to an even count (trailing iterations do nothing)
   for (int i = 0; i < niter; i += 2) {
-    iteration(i, cur, nxt, hp, hn);
-    iteration(i + 1, nxt, cur, hn, hp);
+    iteration(i, cur, nxt, hp, hn, cw_even);
+    iteration(i + 1, nxt, cur, hn, hp, cw_odd);
   }
 }
 

@@ -187,7 +187,11 @@ def test_sample_now_and_population_roundtrip(F):
     f0, _ = run_oracle(rep, 30)
     lat = F.Lattice([rep], precision=F.FP64)
     lat.write_populations(0, f0)
-    np.testing.assert_array_equal(lat.read_populations(0), f0)
+    # FP64 storage keeps f - f_ref rounded once (exact while f is within a factor
+    # two of f_ref) and the read adds f_ref back: one rounding each way
+    ref = O.init_state(rep)
+    err = np.abs(lat.read_populations(0) - f0)
+    assert (err <= np.finfo(float).eps * (np.abs(f0) + np.abs(ref))).all()
     lat.time = 30
     lat.accumulate_structure_factor()
     lat.step(20)

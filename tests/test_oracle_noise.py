@@ -57,6 +57,40 @@ def test_gaussians_are_standard_normal(ora):
     assert np.abs(C).max() < 5 / np.sqrt(G.shape[0])
 
 
+def _box_muller(w0, w1):
+    u1 = (w0 + 0.5) * 2.0**-32
+    u2 = (w1 + 0.5) * 2.0**-32
+    r = np.sqrt(-2.0 * np.log(u1))
+    return r * np.cos(2 * np.pi * u2), r * np.sin(2 * np.pi * u2)
+
+
+@pytest.mark.parametrize("seed,node,t", [(1, 0, 0), (7, 513, 10), (3, 2047, 4998),
+                                         (5, 9, 2**32 + 6)])
+def test_shared_call_splits_between_two_steps(ora, seed, node, t):
+    """Steps t (even) and t + 1 draw 28 words from seven Philox calls: calls
+    0..2 of each step, and call 3 of step t, whose words 0, 1 go to step t and
+    words 2, 3 to step t + 1 (as g_12, g_13)."""
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for step in (t, t + 1):
+        g = ora.node_gaussians(seed, node, step)
+        words = []
+        for call in range(3):
+            words += ora.philox([node, step & 0xFFFFFFFF, step >> 32, call], key)
+        shared = ora.philox([node, t & 0xFFFFFFFF, t >> 32, 3], key)
+        words += shared[0:2] if step == t else shared[2:4]
+        expect = np.array([v for i in range(7) for v in _box_muller(words[2 * i], words[2 * i + 1])])
+        np.testing.assert_allclose(g, expect, rtol=1e-13, atol=1e-15)
+
+
+def test_two_steps_draw_independent_normals(ora):
+    """The 28 variates of a node over an even step and the odd step after it
+    are uncorrelated (the shared call gives each step words of its own)."""
+    G = np.array([np.concatenate([ora.node_gaussians(4, node, 6), ora.node_gaussians(4, node, 7)])
+                  for node in range(6000)])
+    C = np.corrcoef(G.T) - np.eye(28)
+    assert np.abs(C).max() < 5 / np.sqrt(G.shape[0])
+
+
 def test_gaussians_depend_on_seed_node_and_time(ora):
     a = ora.node_gaussians(1, 10, 20)
     assert not np.array_equal(a, ora.node_gaussians(2, 10, 20))
