@@ -235,6 +235,99 @@ def summarize_trace(trace_dir, out_md, title, command, top=16):
         fh.write("\n".join(lines) + "\n")
 
 
+def summarize_timeline(trace_dir, out_md, title, command):
+    """Where a sample's time goes in graph replays, from the start and end
+    timestamps and queue ids of a rocprofv3 kernel trace (no --stats needed):
+    per sample, the sampling launch over a plain one, the idle time between
+    the step launches before and after it, what the row pass and the column
+    pass add to the plain launches they run beside, and the sum, against the
+    measured time between sampling launches."""
+    import csv
+    rows = list(csv.DictReader(open(os.path.join(trace_dir, "run_kernel_trace.csv"))))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+
+    def kind(name):
+        for k, tag in (("k_step2<1>", "S"), ("k_step2<0>", "P"), ("k_row_fft", "R"),
+                       ("k_col_fft", "C"), ("k_advance_time", "A")):
+            if k in name:
+                return tag
+        return None
+
+    ev = [(kind(r["Kernel_Name"]), int(r["Queue_Id"]), int(r["Start_Timestamp"]) / 1e3,
+           int(r["End_Timestamp"]) / 1e3) for r in rows]
+    ev = [e for e in ev if e[0]]
+    first_s = next(i for i, e in enumerate(ev) if e[0] == "S")
+    ev = ev[first_s:]
+    # the step launches (and the time-counter node at a graph's end) form one
+    # chain, whatever queues they run on
+    chain = [e for e in ev if e[0] in "SPA"]
+    passes = [e for e in ev if e[0] in "RC"]
+
+    def overlaps(a, b):
+        return a[2] < b[3] and b[2] < a[3]
+
+    def mean(v):
+        return sum(v) / len(v) if v else float("nan")
+
+    alone = [e[3] - e[2] for e in chain if e[0] == "P" and
+             not any(overlaps(p, e) for p in passes)]
+    plain = mean(alone)
+    gap_before, gap_after, s_extra, periods = [], [], [], []
+    s_idx = [i for i, e in enumerate(chain) if e[0] == "S"]
+    for i in s_idx:
+        e = chain[i]
+        if i == 0 or i + 1 >= len(chain) or chain[i - 1][0] == "A":
+            continue  # samples inside a replay only (not at a graph's first node)
+        gap_before.append(e[2] - chain[i - 1][3])
+        gap_after.append(chain[i + 1][2] - e[3])
+        s_extra.append(e[3] - e[2] - plain)
+    cols = [p for p in passes if p[0] == "C"]
+    for a, b in zip(s_idx, s_idx[1:]):
+        span = (None, None, chain[a][2], chain[b][2])
+        if not any(chain[k][0] == "A" for k in range(a, b)) and \
+                not any(overlaps(c, span) for c in cols):
+            periods.append((chain[b][2] - chain[a][2], b - a))
+    n_r = sum(e[0] == "R" for e in ev)
+    beside_r = [e[3] - e[2] - plain for e in chain if e[0] == "P" and
+                any(p[0] == "R" and overlaps(p, e) for p in passes) and
+                not any(p[0] == "C" and overlaps(p, e) for p in passes)]
+    beside_c = [e[3] - e[2] - plain for e in chain if e[0] == "P" and
+                any(p[0] == "C" and overlaps(p, e) for p in passes)]
+    col_per_sample = sum(beside_c) / n_r if n_r else float("nan")
+    per_sample = (mean(s_extra) + mean(gap_before) + mean(gap_after) + mean(beside_r) +
+                  col_per_sample)
+    launches = mean([n for _, n in periods])
+    period_extra = mean([t for t, _ in periods]) - launches * plain
+    queues = {k: sorted(set(e[1] for e in ev if e[0] == k)) for k in "SPRC"}
+    lines = [f"# {title}", "", "Command (run from the repository root; <out> is any output "
+             "directory):", "", "```", command.strip(), "```", "",
+             "Launches from the first sampling launch on. Hardware queues: " +
+             ", ".join(f"{n} {queues[k]}" for k, n in
+                       (("S", "sampling launches"), ("P", "plain launches"),
+                        ("R", "row passes"), ("C", "column passes"))) + ".", "",
+             f"A plain launch with nothing beside it: {plain:.1f} us ({len(alone)} launches).",
+             "", "| per sample | us | from |", "|---|---|---|",
+             f"| sampling launch over a plain one | {mean(s_extra):.1f} | {len(s_extra)} "
+             "sampling launches inside replays |",
+             f"| idle before the sampling launch | {mean(gap_before):.1f} | the same |",
+             f"| idle after the sampling launch | {mean(gap_after):.1f} | the same |",
+             f"| row pass: what the plain launch beside it takes over a plain one | "
+             f"{mean(beside_r):.1f} | {len(beside_r)} launches (row passes average "
+             f"{mean([e[3] - e[2] for e in ev if e[0] == 'R']):.1f} us) |",
+             f"| column pass: what the plain launches beside it take over plain ones, per "
+             f"sample | {col_per_sample:.1f} | {len(beside_c)} launches, {n_r} samples |",
+             f"| sum | {per_sample:.1f} | |",
+             f"| measured: time between sampling launches in a replay over the same number of "
+             f"plain launches | {period_extra:.1f} | {len(periods)} periods of {launches:.0f} "
+             "launches (no column pass) |"]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return dict(plain=plain, sampling_extra=mean(s_extra), gap_before=mean(gap_before),
+                gap_after=mean(gap_after), beside_row=mean(beside_r),
+                col_per_sample=col_per_sample, per_sample=per_sample,
+                period_extra=period_extra)
+
+
 # steps of the roofline leg before its timed launches (clock ramp, then a probe
 # of 20 steps that sizes the timed part)
 ROOFLINE_LEAD_STEPS = 120
@@ -484,7 +577,22 @@ def main():
                          "with the counters of PMC_SET")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE", "NAME", "TITLE"),
                     help="summarise a rocprofv3 kernel trace into profiles/NAME.md (CPU only)")
+    ap.add_argument("--summarize-timeline", metavar="TRACE",
+                    help="write profiles/sample_timeline_batched96_fp32dev.md from a "
+                         "rocprofv3 kernel trace of graph replays (CPU only)")
     args = ap.parse_args()
+
+    if args.summarize_timeline:
+        d = args.summarize_timeline
+        summarize_timeline(
+            d, os.path.join(ROOT, "profiles", "sample_timeline_batched96_fp32dev.md"),
+            "A sample in graph replays, batched 96-replica FP32-deviation workload, "
+            "two-step kernel",
+            "rocprofv3 --kernel-trace --output-format csv -d <out>/tl -o run -- python3 "
+            "bench.py --steps 2000 --warmup 20 --no-cpu-baseline --no-compare --no-adjoint "
+            "--kernel two --chunk-rows 32\n"
+            "python3 bench.py --summarize-timeline <out>/tl")
+        return
 
     if args.summarize_counters:
         d = args.summarize_counters

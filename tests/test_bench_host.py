@@ -138,6 +138,54 @@ def test_summarize_trace_writes_the_command_and_table(profiler_dirs, tmp_path):
     assert any(line.startswith(f"| {STEP0[:90]} | 5 | 1.0 | 80.00 |") for line in text)
 
 
+def test_summarize_timeline_accounts_for_a_sample(tmp_path):
+    """Synthetic graph replay: plain launches of 100 us, a sampling launch of
+    120 us with 6 us idle before and 5 after it, a row pass that stretches
+    the plain launch beside it to 107 us, and one column pass that stretches
+    two plain launches to 150 us each for two samples."""
+    S2 = "void fnlb::(anonymous namespace)::k_step2<1>(fnlb::Step2Args)"
+    P2 = "void fnlb::(anonymous namespace)::k_step2<0>(fnlb::Step2Args)"
+    R2 = "void fnlb::(anonymous namespace)::k_row_fft<float>(fnlb::RepInfo const*)"
+    C2 = "void fnlb::(anonymous namespace)::k_col_fft<float2>(fnlb::RepInfo const*)"
+    A2 = "fnlb::(anonymous namespace)::k_advance_time(long*, long)"
+    rows, t = [], 0.0
+
+    def k(name, q, start, dur):
+        rows.append(dict(Kernel_Name=name, Queue_Id=q, Start_Timestamp=int(start * 1e3),
+                         End_Timestamp=int((start + dur) * 1e3)))
+        return start + dur
+
+    for rep in range(2):          # two replays of a two-period graph
+        for per in range(2):
+            t = k(S2, 1, t + (6.0 if per else 3.0), 120.0)
+            t += 5.0
+            k(R2, 3, t + 1.0, 40.0)   # beside the next plain launch
+            t = k(P2, 1, t, 107.0)
+            if per == 1:
+                k(C2, 3, t + 1.0, 200.0)
+                t = k(P2, 1, t, 150.0)
+                t = k(P2, 1, t, 150.0)
+            else:
+                t = k(P2, 1, t, 100.0)
+                t = k(P2, 1, t, 100.0)
+            t = k(P2, 1, t, 100.0)
+        t = k(A2, 1, t, 2.0)
+    d = tmp_path / "tl"
+    d.mkdir()
+    _write_csv(d / "run_kernel_trace.csv", rows)
+    r = bench.summarize_timeline(str(d), str(tmp_path / "tl.md"), "T", "cmd")
+    assert r["plain"] == pytest.approx(100.0)
+    assert r["sampling_extra"] == pytest.approx(20.0)
+    assert r["gap_before"] == pytest.approx(6.0)   # the first node of a replay is left out
+    assert r["gap_after"] == pytest.approx(5.0)
+    assert r["beside_row"] == pytest.approx(7.0)
+    assert r["col_per_sample"] == pytest.approx(4 * 50.0 / 4)
+    assert r["per_sample"] == pytest.approx(20 + 6 + 5 + 7 + 50)
+    # the periods without a column pass: 6 + 120 + 5 + 107 + 100 + 100 + 100 over 5 plain
+    assert r["period_extra"] == pytest.approx(6 + 20 + 5 + 7)
+    assert "cmd" in (tmp_path / "tl.md").read_text()
+
+
 def test_more_than_one_gpu_is_refused():
     import subprocess
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
