@@ -707,7 +707,9 @@ hipError_t capture_periods(fnlb_handle* h, int which, int parity) {
       // The branch is issued after the step that follows, when that step does
       // not sample: the runtime then keeps the chain of steps, the sampling
       // step's first successor, on one hardware queue, and the transforms
-      // start beside a step that already holds the compute units.
+      // start beside a step that already holds the compute units (as kernel
+      // traces show; captured first, the branch took the sampling step's
+      // queue and each sample added two waits between queues).
       if (le == hipSuccess) {
         if (k < len && k % h->period != 0)
           forked = per;
