@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_adj_local(const AdjArgs a) {
     const uint32_t node = (uint32_t)(j * Lx + x);
     double g[16];
     // one call at a time (not unrolled): the table-driven FP64 Box-Muller of
-    // four calls interleaved would raise the register pressure of this kernel
+    // three calls interleaved would raise the register pressure of this kernel
 #pragma unroll 1
     for (uint32_t call = 0; call < 3; ++call) {
       double q4[4];

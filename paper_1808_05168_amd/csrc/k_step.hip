@@ -270,7 +270,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
 
     // thermal noise of this node: 14 standard normals, drawn while the next
     // row's loads are in flight (species A uses g_0..g_7 from calls 0 and 1,
-    // species B g_8..g_13 from calls 2 and 3)
+    // species B g_8..g_11 from call 2 and g_12, g_13 from its half of the
+    // call shared with the other step of its pair)
     const uint32_t node = (uint32_t)(j * Lx + x);
     Real gA0[4], gA1[4], gB0[4], gB1[4];
     if constexpr (MODE != kSampleOnly) {
