@@ -90,6 +90,35 @@ __global__ void k_adj_density(const AdjArgs a) {
   a.dens[Lx * Lz + n] = (R.rho0 - rA) + db;
 }
 
+// Three block sums at once, each added in the order block_sum adds it (the
+// same butterfly, then the wavefront totals in wavefront order), behind one
+// pair of barriers.  sh holds 3 doubles per wavefront.
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* sh) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    a += __shfl_xor(a, m, 64);
+    b += __shfl_xor(b, m, 64);
+    c += __shfl_xor(c, m, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    sh[3 * w] = a;
+    sh[3 * w + 1] = b;
+    sh[3 * w + 2] = c;
+  }
+  __syncthreads();
+  double sa = 0, sb = 0, sc = 0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+    sa += sh[3 * k];
+    sb += sh[3 * k + 1];
+    sc += sh[3 * k + 2];
+  }
+  a = sa;
+  b = sb;
+  c = sc;
+}
+
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6;
@@ -102,7 +131,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 __global__ __launch_bounds__(256) void k_adj_local(const AdjArgs a) {
-  __shared__ double sh[4];
+  __shared__ double sh[12];  // 3 per wavefront
   const RepInfo& R = *a.rep;
   const int Lx = R.Lx, Lz = R.Lz, N = Lx * Lz;
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -358,13 +387,11 @@ __global__ __launch_bounds__(256) void k_adj_local(const AdjArgs a) {
     a.gs[2 * (size_t)N + n] = gs_out[1][0];
     a.gs[3 * (size_t)N + n] = gs_out[1][1];
   }
-  const double bs = block_sum(th_s, sh);
-  const double bd = block_sum(th_d, sh);
-  const double bg = block_sum(th_g, sh);
+  block_sum3(th_s, th_d, th_g, sh);
   if (threadIdx.x == 0) {  // running partials of this block over the reverse sweep
-    a.tpart[3 * blockIdx.x + 0] += bs;
-    a.tpart[3 * blockIdx.x + 1] += bd;
-    a.tpart[3 * blockIdx.x + 2] += bg;
+    a.tpart[3 * blockIdx.x + 0] += th_s;
+    a.tpart[3 * blockIdx.x + 1] += th_d;
+    a.tpart[3 * blockIdx.x + 2] += th_g;
   }
 }
 
