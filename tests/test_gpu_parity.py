@@ -138,6 +138,25 @@ def test_parity_time_offset(F):
     compare_observables(lat, acc, 0, rep, TOL64)
 
 
+@pytest.mark.parametrize("kernel", ["one-step", "two-step"])
+def test_parity_time_offset_fp32(F, kernel):
+    """The FP32 kernels across t = 2^32 from an odd start, sampled every 3
+    steps: the two-step kernel's pairs then start at odd steps (two steps
+    that draw two shared calls) and at even ones (one call shared), and the
+    shared calls of the last pairs are keyed by t_hi = 1."""
+    rep = W.Replica(Lx=40, Lz=12, grad_c0=5e-3, kT=1e-4, G=0.5, seed=21)
+    flags = W.DEFAULT_FLAGS | (W.TWO_STEP if kernel == "two-step" else W.ONE_STEP)
+    say(f"case: fp32 time offset across 2^32, {kernel}")
+    f0 = O.init_state(rep)
+    t0 = (1 << 32) - 7
+    lat = F.Lattice([rep], precision=F.FP32_DEV, sample_every=3, flags=flags)
+    lat.time = t0
+    lat.step(12)
+    f_o, acc = run_oracle(rep, 12, every=3, f0=f0, t0=t0, flags=flags)
+    assert dev_norm(lat.read_populations(0), f_o, rep) <= TOL32
+    compare_observables(lat, acc, 0, rep, TOL32)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("chunk", [1, 2, 3, 5, 64])
 def test_row_range_split_is_invisible(F, chunk, prec):
