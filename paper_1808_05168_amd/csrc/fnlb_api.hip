@@ -152,7 +152,8 @@ void make_items(Plan& P, int chunk) {
 // row ranges (alternating march direction, as for the one-step kernel), packed
 // kTBLanes >> lwidth to a block among replicas of the same lane width.  A
 // block's iteration count is its longest item's: the first-step rows (the
-// range plus two rows on each side, clipped at the walls) and two more.
+// range plus two rows on each side, clipped at the walls) and three more
+// (the second step of a row runs three iterations after its first).
 void make_pitems(Plan& P, int chunk) {
   P.pitems.clear();
   if (!P.tb_ok) return;
@@ -167,7 +168,7 @@ void make_pitems(Plan& P, int chunk) {
         const int j1 = std::min(R.Lz, j0 + chunk);
         const int dir = ((j0 / chunk) & 1) ? -1 : 1;
         const int alo = std::max(j0 - 2, 0), ahi = std::min(j1 + 2, R.Lz);
-        const int niter = dir > 0 ? j1 + 2 - alo : ahi - j0 + 2;
+        const int niter = dir > 0 ? j1 + 3 - alo : ahi - j0 + 3;
         const int k = cur.nsub++;
         cur.rep[k] = (int32_t)r;
         cur.j0[k] = j0;

@@ -22,11 +22,13 @@
 // LDS to where they stream: the node itself for links with c_z = 0, the row
 // ahead or behind otherwise (or, at a wall, back into the node's own opposite
 // link).  Once a row of time t + 1 is complete, each lane reads its node's 18
-// populations of it and their densities go into a second ring; one row later
-// stage B runs the second step on that row (b = a - 2 dir) from those
+// populations of it and their densities go into a second ring; two rows
+// later stage B runs the second step on that row (b = a - 3 dir) from those
 // populations and that ring, and stores the result (time t + 2) to HBM in the
-// layout of the state.  Three barriers per row separate the pushes, the
-// densities of t + 1 and the second step.
+// layout of the state.  Two barriers per row: the first separates the
+// densities of the row ahead from stage A and the densities of t + 1 from
+// stage B, the second the pushes from their reads; stage B runs between them,
+// after stage A, so that it needs none of its own.
 //
 // LDS per block: the density rings of t and t + 1 (3 rows each, 12 KiB each)
 // and the pushed populations, kept per class of link for as long as each
@@ -64,8 +66,8 @@ __global__ __launch_bounds__(kTBLanes) void k_step2(const Step2Args a) {
   using Real = float;
   using Store = float;
   using DT = float;
-  // Densities of t and of t + 1, rows mod 3.  Three barriers per row keep a
-  // slot's readers apart from its next writer.
+  // Densities of t and of t + 1, rows mod 3.  The two barriers per row keep
+  // a slot's readers apart from its next writer.
   __shared__ DT ring[3][2][kRingCols];
   __shared__ DT dring[3][2][kRingCols];
   // Pushed populations of t + 1, [slot][3 s + k][column]: links 0, 1, 3 of
@@ -174,16 +176,18 @@ __global__ __launch_bounds__(kTBLanes) void k_step2(const Step2Args a) {
   // of both steps): stage A draws it and keeps the second step's two words,
   // which its second step uses two rows (two iterations) later.
   const bool odd_t = (t & 1) != 0;
-  uint32_t cw_even[2] = {0u, 0u}, cw_odd[2] = {0u, 0u};
+  // kept words of the rows ar - 3 dir, ar - 2 dir and ar - dir (t even)
+  uint32_t kw[3][2] = {{0u, 0u}, {0u, 0u}, {0u, 0u}};
 
   // One row of each stage.  cur: the pulled row ar of t, nxt: the row ahead;
-  // hp: the populations of t + 1 of the row whose second step runs now, hn:
-  // receives those of the row behind; cw: the kept words of the row whose
-  // second step runs now, replaced by those of row ar.  The loop runs two
-  // iterations per trip with the register sets swapped in the second, so that
-  // no set is copied.
+  // hn: the populations of t + 1 of the row whose second step runs now (row
+  // ar - 3 dir), then those of the row behind (ar - dir); hp: those of row
+  // ar - 2 dir, whose second step runs in the next iteration.  The loop runs
+  // two iterations per trip with the register sets swapped in the second, so
+  // that no set is copied.
   auto iteration = [&](int i, Store(&cur)[18], Store(&nxt)[18], Store(&hp)[18],
-                       Store(&hn)[18], uint32_t(&cw)[2]) {
+                       Store(&hn)[18]) {
+    (void)hp;
     const int ar = afirst + dir * i;  // row of the first step
     const bool doA = sub_ok && a_row(ar);
     const bool topA = ar == Lz - 1, botA = ar == 0;
@@ -288,6 +292,62 @@ __global__ __launch_bounds__(kTBLanes) void k_step2(const Step2Args a) {
       // and the next noise
       if (needed(ar + 2 * dir)) load_pulled(in, link_b, row_b, ar + 2 * dir, Lz, xb, xmb, xpb, cur);
     }
+
+    // ---- stage B: the second step of row bq = ar - 3 dir, whose populations
+    // of t + 1 were read two iterations ago (into hn) and whose densities of
+    // t + 1 (rows bq and bq +- 1) are complete since the last iteration; the
+    // result is stored to HBM.  Run between the two barriers (after stage A,
+    // whose noise is then no longer live), it needs no barrier of its own:
+    // the next writes of the density slots it reads follow the second one.
+    const int bq = ar - 3 * dir;
+    const bool doB = sub_ok && wave_act && bq >= j0 && bq < j1;
+    if (doB) {
+      Real gA0b[4], gA1b[4], gB0b[4], gB1b[4];
+      {
+        const uint32_t node = (uint32_t)(bq * Lx + x);
+        uint32_t w12 = kw[0][0], w13 = kw[0][1];
+        if (odd_t) {  // t + 1 even: its shared call is its own
+          uint32_t o12, o13;
+          shared_words(node, (uint64_t)(t + 1), k0, k1, w12, w13, o12, o13);
+        }
+        node_noise_words(node, (uint64_t)(t + 1), k0, k1, bmt, w12, w13, gA0b, gA1b, gB0b,
+                         gB1b);
+      }
+      const bool top = bq == Lz - 1, bot = bq == 0;
+      Real dA[9], dB[9];
+#pragma unroll
+      for (int l = 0; l < 9; ++l) {
+        dA[l] = hn[l];
+        dB[l] = hn[9 + l];
+      }
+      const int jU = top ? bq : bq + 1, jD = bot ? bq : bq - 1;
+      const double rAj = rA0 + rAs * bq;
+      const double szref = rAs * (double)(jU - jD) * (1.0 / 6.0);
+      const Stencil<DT> stb =
+          load_stencil(dring[mod3(jU)][0], dring[mod3(bq)][0], dring[mod3(jD)][0],
+                       dring[mod3(jU)][1], dring[mod3(bq)][1], dring[mod3(jD)][1], c);
+      node_update<Real, DT>(P, flags, top, bot, rAj, rho0, szref, stb, dA, dB, gA0b, gA1b, gB0b,
+                            gB1b);
+      if (act) {
+        const uint32_t off = (uint32_t)bq * row_b + xb;
+        const Real upf = top ? (Real)0 : (Real)1, dnf = bot ? (Real)0 : (Real)1;
+        auto emit = [&](int s, const Real(&d)[9], Real sh1, Real sh5) {
+          const uint32_t p = (uint32_t)(9 * s) * link_b;
+          bstore<Store>(out, off, p, (Store)d[0]);
+          bstore<Store>(out, off, p + link_b, (Store)d[1]);
+          bstore<Store>(out, off, p + 2 * link_b, (Store)(d[2] + upf * sh1));
+          bstore<Store>(out, off, p + 3 * link_b, (Store)d[3]);
+          bstore<Store>(out, off, p + 4 * link_b, (Store)(d[4] - dnf * sh1));
+          bstore<Store>(out, off, p + 5 * link_b, (Store)(d[5] + upf * sh5));
+          bstore<Store>(out, off, p + 6 * link_b, (Store)(d[6] + upf * sh5));
+          bstore<Store>(out, off, p + 7 * link_b, (Store)(d[7] - dnf * sh5));
+          bstore<Store>(out, off, p + 8 * link_b, (Store)(d[8] - dnf * sh5));
+        };
+        emit(0, dA, P.shA1, P.shA5);
+        emit(1, dB, -P.shA1, -P.shA5);
+      }
+    }
+
     __syncthreads();
 
     // the populations of row r of t + 1 at this lane's column, in link order
@@ -311,26 +371,17 @@ __global__ __launch_bounds__(kTBLanes) void k_step2(const Step2Args a) {
     };
 
     // ---- the row behind is complete: read its populations of t + 1 (kept in
-    // registers for its second step in the next iteration) and sum its
-    // densities; the noise of this iteration's second step is drawn while
-    // those reads are in flight
+    // registers for its second step two iterations later) and sum its
+    // densities
     const int dr = ar - dir;
     const bool doD = sub_ok && act && dr >= max(j0 - 1, 0) && dr <= min(j1, Lz - 1);
     if (doD) pulled1(dr, hn);
-    const int br = ar - 2 * dir;
-    const bool doB = sub_ok && wave_act && br >= j0 && br < j1;
-    Real gA0b[4], gA1b[4], gB0b[4], gB1b[4];
-    if (doB) {
-      const uint32_t node = (uint32_t)(br * Lx + x);
-      uint32_t w12 = cw[0], w13 = cw[1];
-      if (odd_t) {  // t + 1 even: its shared call is its own
-        uint32_t o12, o13;
-        shared_words(node, (uint64_t)(t + 1), k0, k1, w12, w13, o12, o13);
-      }
-      node_noise_words(node, (uint64_t)(t + 1), k0, k1, bmt, w12, w13, gA0b, gA1b, gB0b, gB1b);
-    }
-    cw[0] = nw12;
-    cw[1] = nw13;
+    kw[0][0] = kw[1][0];
+    kw[0][1] = kw[1][1];
+    kw[1][0] = kw[2][0];
+    kw[1][1] = kw[2][1];
+    kw[2][0] = nw12;
+    kw[2][1] = nw13;
     if (doD) {
       DT da, db;
       density18(hn, da, db);
@@ -346,50 +397,11 @@ __global__ __launch_bounds__(kTBLanes) void k_step2(const Step2Args a) {
         dring[sl][1][cb + Lx + 1] = db;
       }
     }
-    __syncthreads();
-
-    // ---- stage B: the second step of row br (read in the previous
-    // iteration), stored to HBM
-    if (doB) {
-      const bool top = br == Lz - 1, bot = br == 0;
-      Real dA[9], dB[9];
-#pragma unroll
-      for (int l = 0; l < 9; ++l) {
-        dA[l] = hp[l];
-        dB[l] = hp[9 + l];
-      }
-      const int jU = top ? br : br + 1, jD = bot ? br : br - 1;
-      const double rAj = rA0 + rAs * br;
-      const double szref = rAs * (double)(jU - jD) * (1.0 / 6.0);
-      const Stencil<DT> stb =
-          load_stencil(dring[mod3(jU)][0], dring[mod3(br)][0], dring[mod3(jD)][0],
-                       dring[mod3(jU)][1], dring[mod3(br)][1], dring[mod3(jD)][1], c);
-      node_update<Real, DT>(P, flags, top, bot, rAj, rho0, szref, stb, dA, dB, gA0b, gA1b, gB0b,
-                            gB1b);
-      if (act) {
-        const uint32_t off = (uint32_t)br * row_b + xb;
-        const Real upf = top ? (Real)0 : (Real)1, dnf = bot ? (Real)0 : (Real)1;
-        auto emit = [&](int s, const Real(&d)[9], Real sh1, Real sh5) {
-          const uint32_t p = (uint32_t)(9 * s) * link_b;
-          bstore<Store>(out, off, p, (Store)d[0]);
-          bstore<Store>(out, off, p + link_b, (Store)d[1]);
-          bstore<Store>(out, off, p + 2 * link_b, (Store)(d[2] + upf * sh1));
-          bstore<Store>(out, off, p + 3 * link_b, (Store)d[3]);
-          bstore<Store>(out, off, p + 4 * link_b, (Store)(d[4] - dnf * sh1));
-          bstore<Store>(out, off, p + 5 * link_b, (Store)(d[5] + upf * sh5));
-          bstore<Store>(out, off, p + 6 * link_b, (Store)(d[6] + upf * sh5));
-          bstore<Store>(out, off, p + 7 * link_b, (Store)(d[7] - dnf * sh5));
-          bstore<Store>(out, off, p + 8 * link_b, (Store)(d[8] - dnf * sh5));
-        };
-        emit(0, dA, P.shA1, P.shA5);
-        emit(1, dB, -P.shA1, -P.shA5);
-      }
-    }
   };
   // the host rounds niter up to an even count (trailing iterations do nothing)
   for (int i = 0; i < niter; i += 2) {
-    iteration(i, cur, nxt, hp, hn, cw_even);
-    iteration(i + 1, nxt, cur, hn, hp, cw_odd);
+    iteration(i, cur, nxt, hp, hn);
+    iteration(i + 1, nxt, cur, hn, hp);
   }
 }
 
