@@ -561,12 +561,19 @@ __device__ __forceinline__ void col_fft(const RepInfo& R, const ColTask& T, cons
 
 template <typename ST>
 __global__ __launch_bounds__(256) void k_col_fft(const RepInfo* reps, const ColTask* tasks,
-                                                 const ST* spec, int nslots,
+                                                 int n_tasks, const ST* spec, int nslots,
                                                  size_t spec_slot, double* acc,
                                                  const double2* tw_base, const double* ppart,
                                                  size_t ppart_slot) {
   __shared__ double2 lds[4 * kWaveFftLds];
-  const ColTask T = tasks[blockIdx.x];
+  // XCD-aware order: the grid is a multiple of 8 blocks, and block b runs on
+  // XCD b % 8, which gets the consecutive tasks (b % 8) per_xcd ...; the
+  // tiles of neighbouring columns, which share the 128-byte lines of the
+  // spectrum rows, then meet in one L2
+  const int per_xcd = (int)(gridDim.x >> 3);
+  const int task = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (task >= n_tasks) return;  // whole block
+  const ColTask T = tasks[task];
   const RepInfo& R = reps[__builtin_amdgcn_readfirstlane(T.rep)];
 #define FNLB_COL(n) \
   col_fft<ST, n>(R, T, spec, nslots, spec_slot, acc, tw_base, ppart, ppart_slot, lds)
@@ -669,11 +676,12 @@ hipError_t launch_col_fft(const RepInfo* reps, const ColTask* tasks, int n_tasks
                           double* acc, const double2* tw, const double* ppart,
                           size_t ppart_slot, hipStream_t stream) {
   if (n_tasks <= 0 || nslots <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((n_tasks + 7) / 8 * 8));  // a multiple of the 8 XCDs
   if (precision == FNLB_FP64)
-    hipLaunchKernelGGL(k_col_fft<double2>, dim3(n_tasks), dim3(256), 0, stream, reps, tasks,
+    hipLaunchKernelGGL(k_col_fft<double2>, grid, dim3(256), 0, stream, reps, tasks, n_tasks,
                        (const double2*)spec, nslots, spec_slot, acc, tw, ppart, ppart_slot);
   else
-    hipLaunchKernelGGL(k_col_fft<float2>, dim3(n_tasks), dim3(256), 0, stream, reps, tasks,
+    hipLaunchKernelGGL(k_col_fft<float2>, grid, dim3(256), 0, stream, reps, tasks, n_tasks,
                        (const float2*)spec, nslots, spec_slot, acc, tw, ppart, ppart_slot);
   return hipGetLastError();
 }
